@@ -1,0 +1,142 @@
+"""The FP64 network oracle against torch (a separate implementation):
+forward values against a float64 nn.Sequential, the derivative streams
+against torch.autograd.grad with create_graph, the PINN loss gradient against
+torch autograd and against central finite differences.  The residual formula
+is pinned on the closed-form price, whose residual vanishes."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import mlp
+from workloads import collocation, perturbed, xavier_normal
+
+
+def _torch_net(theta, n_in, depth, width):
+    layers, mods = mlp.unpack(theta, n_in, depth, width), []
+    for W, b in layers[:-1]:
+        lin = torch.nn.Linear(W.shape[1], W.shape[0]).double()
+        lin.weight.data = torch.tensor(W.copy())
+        lin.bias.data = torch.tensor(b.copy())
+        mods += [lin, torch.nn.Tanh()]
+    W, b = layers[-1]
+    lin = torch.nn.Linear(W.shape[1], 1).double()
+    lin.weight.data = torch.tensor(W.copy())
+    lin.bias.data = torch.tensor(b.copy())
+    mods.append(lin)
+    return torch.nn.Sequential(*mods)
+
+
+def _torch_streams(net, X):
+    Xt = torch.tensor(X, requires_grad=True)
+    v = net(Xt)[:, 0]
+    (g,) = torch.autograd.grad(v.sum(), Xt, create_graph=True)
+    v_t, v_x = g[:, 0], g[:, 1]
+    (gx,) = torch.autograd.grad(v_x.sum(), Xt, create_graph=True)
+    return v, v_t, v_x, gx[:, 1]
+
+
+CASES = [(2, 1, 5), (2, 3, 16), (2, 4, 64), (4, 4, 32)]
+
+
+def _theta(n_in, depth, width):
+    return perturbed(xavier_normal(n_in, depth, width, seed=width), 0.1, seed=depth).astype(np.float64)
+
+
+@pytest.mark.parametrize("n_in,depth,width", CASES)
+def test_forward_and_streams_vs_torch(n_in, depth, width):
+    th = _theta(n_in, depth, width)
+    box = ((0.1, 0.5), (0.0, 0.1)) if n_in == 4 else None
+    X, _, _ = collocation(64, 1, 2, 1.0, 3.0, seed=5, coeff_box=box)
+    net = _torch_net(th, n_in, depth, width)
+    ref = [t.detach().numpy() for t in _torch_streams(net, X)]
+    got = mlp.streams(th, X, n_in, depth, width)
+    for g, r in zip(got, ref):
+        assert np.max(np.abs(g - r)) <= 1e-13 * max(1.0, np.max(np.abs(r)))
+    assert np.max(np.abs(mlp.forward(th, X, n_in, depth, width) - ref[0])) <= 1e-13
+
+
+@pytest.mark.parametrize("n_in,depth,width", CASES)
+@pytest.mark.parametrize("is_put", [False, True])
+def test_loss_and_gradient_vs_torch_autograd(n_in, depth, width, is_put):
+    th = _theta(n_in, depth, width)
+    box = ((0.1, 0.5), (0.0, 0.1)) if n_in == 4 else None
+    X_f, X_e, X_b = collocation(48, 16, 12, 1.0, 3.0, seed=6, coeff_box=box)
+    sig, rr = (None, None) if n_in == 4 else (0.2, 0.05)
+    net = _torch_net(th, n_in, depth, width)
+    v, v_t, v_x, v_xx = _torch_streams(net, X_f)
+    x = torch.tensor(X_f[:, 1])
+    sg = torch.tensor(X_f[:, 2]) if n_in == 4 else sig
+    rt = torch.tensor(X_f[:, 3]) if n_in == 4 else rr
+    f = v_t - 0.5 * sg * sg * x * x * v_xx - rt * x * v_x + rt * v
+    ve = net(torch.tensor(X_e))[:, 0]
+    vb = net(torch.tensor(X_b))[:, 0]
+    ye = torch.tensor(mlp.terminal_target(X_e, is_put))
+    yb = torch.tensor(mlp.boundary_target(X_b, is_put, rr))
+    terms = [(f * f).mean(), ((ve - ye) ** 2).mean(), ((vb - yb) ** 2).mean()]
+    loss = terms[0] + terms[1] + terms[2]
+    loss.backward()
+    ref_grad = np.concatenate([torch.cat([m.weight.grad.reshape(-1), m.bias.grad]).numpy()
+                               for m in net if isinstance(m, torch.nn.Linear)])
+    got3 = mlp.loss3(th, X_f, X_e, X_b, n_in, depth, width, is_put, sig, rr)
+    for g, r in zip(got3, terms):
+        assert abs(g - r.item()) <= 1e-12 * max(1.0, abs(r.item()))
+    got = mlp.loss_grad(th, X_f, X_e, X_b, n_in, depth, width, is_put, sig, rr)
+    assert np.max(np.abs(got - ref_grad)) <= 1e-11 * max(1.0, np.max(np.abs(ref_grad)))
+
+
+def test_gradient_vs_finite_differences():
+    n_in, depth, width = 2, 3, 8
+    th = _theta(n_in, depth, width)
+    X_f, X_e, X_b = collocation(30, 10, 10, 1.0, 3.0, seed=7)
+    g = mlp.loss_grad(th, X_f, X_e, X_b, n_in, depth, width, False, 0.2, 0.05)
+    h = 1e-6
+    fd = np.empty_like(th)
+    for i in range(th.size):
+        e = np.zeros_like(th)
+        e[i] = h
+        fd[i] = (sum(mlp.loss3(th + e, X_f, X_e, X_b, n_in, depth, width, False, 0.2, 0.05))
+                 - sum(mlp.loss3(th - e, X_f, X_e, X_b, n_in, depth, width, False, 0.2, 0.05))) / (2 * h)
+    assert np.max(np.abs(g - fd)) <= 1e-6 * np.max(np.abs(fd))
+
+
+@pytest.mark.parametrize("is_put", [False, True])
+def test_residual_vanishes_on_closed_form(is_put):
+    """The residual formula applied to the closed-form price (v = V/K,
+    derivatives by central differences) is zero up to the differencing error."""
+    K, r, sigma = 100.0, 0.05, 0.2
+    x = np.linspace(0.5, 2.0, 7)
+    tau, h = 0.6, 1e-4
+
+    def v(t, xx):
+        return oracle.bs_price(xx * K, K, r, sigma, t, is_put) / K
+
+    v0 = v(tau, x)
+    v_t = (v(tau + h, x) - v(tau - h, x)) / (2 * h)
+    v_x = (v(tau, x + h) - v(tau, x - h)) / (2 * h)
+    v_xx = (v(tau, x + h) - 2 * v0 + v(tau, x - h)) / h ** 2
+    f = mlp.residual_from_streams(v0, v_t, v_x, v_xx, x, sigma, r)
+    assert np.max(np.abs(f)) < 1e-5
+    f_wrong = mlp.residual_from_streams(v0, -v_t, v_x, v_xx, x, sigma, r)
+    assert np.max(np.abs(f_wrong)) > 1e-3
+
+
+def test_targets():
+    X = np.array([[0.0, 0.5], [0.0, 1.5]])
+    assert np.allclose(mlp.terminal_target(X, False), [0.0, 0.5])
+    assert np.allclose(mlp.terminal_target(X, True), [0.5, 0.0])
+    Xb = np.array([[0.5, 0.0], [0.5, 3.0]])
+    assert np.allclose(mlp.boundary_target(Xb, False, 0.05), [0.0, 3.0 - np.exp(-0.025)])
+    assert np.allclose(mlp.boundary_target(Xb, True, 0.05), [np.exp(-0.025), 0.0])
+
+
+def test_grid_values_layout():
+    n_in, depth, width = 2, 2, 8
+    th = _theta(n_in, depth, width)
+    taus = np.array([0.0, 0.25, 1.0])
+    S = np.array([10.0, 100.0, 250.0, 290.0])
+    G = mlp.grid_values(th, n_in, depth, width, 100.0, taus, S)
+    for i, t in enumerate(taus):
+        for j, s in enumerate(S):
+            ref = 100.0 * mlp.forward(th, np.array([[t, s / 100.0]]), n_in, depth, width)[0]
+            assert G[i, j] == pytest.approx(ref, rel=1e-15, abs=1e-13)

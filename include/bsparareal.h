@@ -1,0 +1,190 @@
+/*
+ * bsparareal: Parareal for the Black-Scholes equation on one AMD Instinct
+ * MI355X (gfx950).  C ABI of libbsparareal.so.
+ *
+ * The method is the one of "Parareal with a physics-informed neural network
+ * as coarse propagator" (Ibrahim, Goetschel, Ruprecht):
+ *   - the model, eqs. (1)-(4): the Black-Scholes equation for a European
+ *     option with expiry payoff and Dirichlet conditions at S = 0 and S_max;
+ *   - the space discretisation, Sec. 3.2: second-order centred differences on
+ *     S_j = j dS, j = 1..M, dS = S_max/(M+1); the problem is integrated in
+ *     time to maturity tau = T - t (the paper solves backwards from T);
+ *   - the propagators, Sec. 3.2: Crank-Nicolson as fine F, implicit Euler as
+ *     numerical coarse G; Sec. 3.3: a physics-informed network as coarse G;
+ *   - the iteration, Sec. 3.1 eq. (7):
+ *       U^k_{n+1} = G(U^k_n) + F(U^{k-1}_n) - G(U^{k-1}_n),
+ *     with F run on all N time slices concurrently;
+ *   - the network loss, eqs. (11)-(14).
+ *
+ * Conventions for every call:
+ *   - All array arguments are DEVICE pointers to caller-owned, contiguous,
+ *     row-major memory unless marked "host".  The library never frees or
+ *     keeps caller memory beyond the call.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls are
+ *     asynchronous on it unless stated otherwise.
+ *   - Return value: BS_OK (0) on success, a negative BS_ERR_* code on error
+ *     (nothing has been launched when an argument check fails), or the
+ *     positive warning BS_NOT_CONVERGED.  bs_last_error() gives a message.
+ *     No C++ exception crosses the ABI.
+ *   - Limits: 1 <= M <= 16384 interior nodes; 1 <= N; steps >= 1.
+ */
+#ifndef BSPARAREAL_H
+#define BSPARAREAL_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+    BS_OK = 0,
+    BS_NOT_CONVERGED = 1,  /* max_iter reached before tol; outputs are the last iterate */
+    BS_ERR_ARG = -1,       /* invalid argument (null pointer, size out of range, ...) */
+    BS_ERR_HIP = -2,       /* a HIP runtime call failed */
+    BS_ERR_NONFINITE = -3, /* a NaN or Inf appeared in the Parareal state */
+    BS_ERR_WORKSPACE = -5  /* workspace pointer null or too small */
+};
+
+/* Option and model coefficients (eq. (1)): strike K, riskless rate r,
+ * volatility sigma, expiry T, truncation S_max of the asset axis.
+ * is_put = 0: call, V(tau,0) = 0, V(tau,S_max) = S_max - K exp(-r tau);
+ * is_put = 1: put,  V(tau,0) = K exp(-r tau), V(tau,S_max) = 0. */
+typedef struct bs_params {
+    double K, r, sigma, T, s_max;
+    int is_put;
+} bs_params;
+
+/* Space grid: M interior nodes.  payoff_mode 0 samples the expiry payoff
+ * (eq. (2)) at S_j; payoff_mode 1 averages it over [S_j - dS/2, S_j + dS/2]. */
+typedef struct bs_grid {
+    int M;
+    int payoff_mode;
+} bs_grid;
+
+/* Time slices (Sec. 3.1): N slices of length T/N; F takes fine_steps
+ * Crank-Nicolson steps per slice, the numerical G coarse_steps implicit-Euler
+ * steps per slice. */
+typedef struct bs_slices {
+    int N;
+    int fine_steps;
+    int coarse_steps;
+} bs_slices;
+
+/* Coarse propagator kinds (Sec. 3.3 for the network ones).
+ *   BS_COARSE_IE      : coarse_steps implicit-Euler steps.
+ *   BS_COARSE_PINN    : G(U_n) = Vt_{n+1}, the network's price at the end of
+ *                       slice n, independent of U_n (the literal reading).
+ *   BS_COARSE_PINN_IE : G(U_n) = Vt_{n+1} + E(U_n - Vt_n), E = coarse_steps
+ *                       implicit-Euler steps with zero boundary data: the
+ *                       network anchors the state, one cheap solve carries
+ *                       the deviation.
+ * Vt_n(S_j) = K * v(tau_n, S_j / K) with v the network of `pinn_net`. */
+enum { BS_COARSE_IE = 0, BS_COARSE_PINN = 1, BS_COARSE_PINN_IE = 2 };
+
+/* Network arithmetic. */
+enum { BS_PREC_FP32 = 0, BS_PREC_BF16 = 1 };
+
+/* A fully connected tanh network (Sec. 3.3) with n_in inputs (2: (tau, S/K);
+ * 4: (tau, S/K, sigma, r)), `depth` hidden tanh layers of `width` units and
+ * one linear output v = V/K.  `params` (device, float32) packs the layers in
+ * torch.nn.Linear order: W1[width][n_in], b1[width], W2[width][width], b2,
+ * ..., W_depth, b_depth, Wo[1][width], bo[1]; its length is
+ *   width*n_in + width + (depth-1)*(width*width + width) + width + 1.
+ * precision BS_PREC_BF16: matrix products take bfloat16 inputs on the matrix
+ * cores with float32 accumulation; BS_PREC_FP32: float32 throughout.
+ * Limits: n_in in {2, 4}; 1 <= depth <= 16; width in {16, 32, 64, 128, 256}. */
+typedef struct pinn_net {
+    int n_in, depth, width, precision;
+    const float* params;
+} pinn_net;
+
+/* Message describing the last error of the calling thread ("" if none). */
+const char* bs_last_error(void);
+
+/* Expiry payoff at the interior nodes (eq. (2), or its put analogue):
+ * u0[M] (device, out). */
+int bs_initial(const bs_params* prm, const bs_grid* grid, double* u0, void* stream);
+
+/* Fine propagator F on a batch of independent systems (Sec. 3.2):
+ * system s starts at time to maturity tau0[s] (device, [nsys]) from state
+ * u_in[s][0..M) and takes `steps` Crank-Nicolson steps of size dtau/steps
+ * with the exact Dirichlet data of `prm` at every time level; the result goes
+ * to u_out[s][0..M).  u_in and u_out may be the same array.
+ * Errors: BS_ERR_ARG for null pointers, nsys < 0, steps < 1, dtau <= 0, M
+ * out of range; BS_ERR_HIP if the launch fails. */
+int bs_fine_propagate_batch(const bs_params* prm, const bs_grid* grid, int nsys,
+                            const double* tau0, double dtau, int steps, const double* u_in,
+                            double* u_out, void* stream);
+
+/* Numerical coarse propagator G (Sec. 3.2): as bs_fine_propagate_batch with
+ * implicit-Euler steps. */
+int bs_coarse_numeric(const bs_params* prm, const bs_grid* grid, int nsys, const double* tau0,
+                      double dtau, int steps, const double* u_in, double* u_out, void* stream);
+
+/* Network forward pass (Sec. 3.3): v_out[i] = v(X[i][0..n_in)), i < n.
+ * X: device float32 [n][n_in]; v_out: device float32 [n]. */
+int pinn_forward(const pinn_net* net, int n, const float* X, float* v_out, void* stream);
+
+/* Bytes of device workspace pinn_residual_fwd_bwd needs. */
+size_t pinn_residual_workspace_size(const pinn_net* net, int n_f, int n_e, int n_b);
+
+/* PINN loss and its gradient (eqs. (11)-(14)), one fused pass.
+ * Interior points X_f [n_f][n_in]: residual
+ *     f = v_tau - sigma^2 x^2 v_xx / 2 - r x v_x + r v   (eq. (1) in tau, x = S/K, v = V/K),
+ *   with v_tau, v_x, v_xx differentiated through the network by hand-written
+ *   forward-mode streams (the paper uses automatic differentiation).
+ * Terminal points X_e [n_e][n_in] (tau = 0): target max(x-1,0) (call) or
+ *   max(1-x,0) (put), eq. (2).
+ * Boundary points X_b [n_b][n_in]: x == 0 is the lower boundary (call 0, put
+ *   exp(-r tau)); any other x is the upper one (call x - exp(-r tau), put 0).
+ * sigma and r come from `prm` when n_in == 2 and from columns 2, 3 of X when
+ * n_in == 4; prm->is_put selects the targets (prm must not be NULL; K, T,
+ * s_max are not used).
+ * Outputs (device, float32): loss3[3] = (MSE_f, MSE_exp, MSE_b); grad[n_params]
+ * = d(MSE_f + MSE_exp + MSE_b)/d params, packed like net->params.
+ * ws: device workspace of pinn_residual_workspace_size() bytes.
+ * n_f, n_e, n_b >= 0; an empty set contributes 0 to loss and gradient. */
+int pinn_residual_fwd_bwd(const pinn_net* net, const bs_params* prm, int n_f, const float* X_f,
+                          int n_e, const float* X_e, int n_b, const float* X_b, float* loss3,
+                          float* grad, void* ws, size_t ws_bytes, void* stream);
+
+/* Bytes of device workspace one Parareal solve needs. */
+size_t parareal_workspace_size(const bs_grid* grid, const bs_slices* sl, int coarse_kind);
+
+/* Start a Parareal solve: U[0] = expiry payoff; for the network kinds the
+ * network is evaluated at every (tau_n, S_j), n = 0..N; then the coarse
+ * prediction U[n+1] = G(U[n]), n = 0..N-1 (iteration k = 0).
+ * U: device [N+1][M] (out).  ws: device workspace (state kept between calls). */
+int parareal_start(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,
+                   int coarse_kind, const pinn_net* net, void* ws, size_t ws_bytes, double* U,
+                   void* stream);
+
+/* One Parareal iteration k >= 1 (eq. (7)) on the state left by
+ * parareal_start / the previous iteration: F on every slice n >= k-1
+ * concurrently (slices n < k-1 already hold the serial fine solution and
+ * their F values from the previous iteration are reused unchanged), then the
+ * serial sweep U[n+1] = F_n + (G(U[n]) - G_old_n) with the max-norm change
+ * of U.  SYNCHRONOUS: returns after the stream has drained.
+ * defect (host, out): max_{n,j} |U^k - U^{k-1}|; nonfinite (host, out): 1 if
+ * any NaN/Inf was produced (then BS_ERR_NONFINITE is returned). */
+int parareal_iterate(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,
+                     int coarse_kind, const pinn_net* net, void* ws, size_t ws_bytes, double* U,
+                     int k, double* defect, int* nonfinite, void* stream);
+
+/* Whole solve: parareal_start, then iterations until defect <= tol, k == N
+ * (the iterate then equals serial fine integration) or k == max_iter.
+ * SYNCHRONOUS.  iters (host, out): iterations done; defect_hist (host,
+ * [max_iter] or NULL): defect of each iteration.  net may be NULL for
+ * BS_COARSE_IE.  Returns BS_OK, BS_NOT_CONVERGED (max_iter hit first) or an
+ * error. */
+int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,
+                   int coarse_kind, double tol, const pinn_net* net, int max_iter, void* ws,
+                   size_t ws_bytes, double* U, int* iters, double* defect_hist, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSPARAREAL_H */

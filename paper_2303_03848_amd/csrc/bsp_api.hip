@@ -1,0 +1,233 @@
+// C ABI entry points: argument checks, workspace layout, and the host side of
+// the Parareal iteration (one F launch over all unconverged slices, one sweep
+// launch, one 16-byte read-back of the defect per iteration).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "bsp_common.hpp"
+
+namespace bsp {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = '\0'; }
+
+static int check_params(const bs_params* prm) {
+    BSP_CHECK_ARG(prm != nullptr, "bs_params is NULL");
+    BSP_CHECK_ARG(prm->K > 0 && prm->sigma > 0 && prm->r >= 0 && prm->T > 0 && prm->s_max > 0,
+                  "bs_params out of range (need K > 0, sigma > 0, r >= 0, T > 0, s_max > 0)");
+    BSP_CHECK_ARG(std::isfinite(prm->K) && std::isfinite(prm->sigma) && std::isfinite(prm->r) &&
+                      std::isfinite(prm->T) && std::isfinite(prm->s_max),
+                  "bs_params must be finite");
+    return BS_OK;
+}
+
+static int check_grid(const bs_grid* g) {
+    BSP_CHECK_ARG(g != nullptr, "bs_grid is NULL");
+    BSP_CHECK_ARG(g->M >= 1 && g->M <= kMaxM, "M must be in [1, %d] (got %d)", kMaxM, g->M);
+    BSP_CHECK_ARG(g->payoff_mode == 0 || g->payoff_mode == 1, "payoff_mode must be 0 or 1");
+    BSP_CHECK_ARG(tri_shape(g->M).T > 0, "M = %d is not supported by the tridiagonal kernels",
+                  g->M);
+    return BS_OK;
+}
+
+static int check_slices(const bs_slices* s) {
+    BSP_CHECK_ARG(s != nullptr, "bs_slices is NULL");
+    BSP_CHECK_ARG(s->N >= 1 && s->N <= (1 << 20), "N must be >= 1 (got %d)", s->N);
+    BSP_CHECK_ARG(s->fine_steps >= 1 && s->coarse_steps >= 1, "step counts must be >= 1");
+    return BS_OK;
+}
+
+// Parareal workspace: [result 2 doubles | Fv N*M | Gold N*M | Vt (N+1)*M (network kinds)]
+struct Workspace {
+    double* result;
+    double* Fv;
+    double* Gold;
+    double* Vt;
+};
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static size_t ws_bytes(int M, int N, int kind) {
+    size_t b = 256;
+    b += align256(sizeof(double) * (size_t)N * M);
+    b += align256(sizeof(double) * (size_t)N * M);
+    if (kind != BS_COARSE_IE) b += align256(sizeof(double) * (size_t)(N + 1) * M);
+    return b;
+}
+
+static Workspace ws_layout(void* ws, int M, int N, int kind) {
+    char* p = (char*)ws;
+    Workspace w;
+    w.result = (double*)p;
+    p += 256;
+    w.Fv = (double*)p;
+    p += align256(sizeof(double) * (size_t)N * M);
+    w.Gold = (double*)p;
+    p += align256(sizeof(double) * (size_t)N * M);
+    w.Vt = (kind != BS_COARSE_IE) ? (double*)p : nullptr;
+    return w;
+}
+
+static int check_parareal(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,
+                          int kind, const pinn_net* net, void* ws, size_t ws_size, double* U) {
+    int rc;
+    if ((rc = check_params(prm))) return rc;
+    if ((rc = check_grid(grid))) return rc;
+    if ((rc = check_slices(sl))) return rc;
+    BSP_CHECK_ARG(kind == BS_COARSE_IE || kind == BS_COARSE_PINN || kind == BS_COARSE_PINN_IE,
+                  "unknown coarse kind %d", kind);
+    if (kind != BS_COARSE_IE) {
+        if ((rc = check_net(net))) return rc;
+        BSP_CHECK_ARG(net->n_in == 2 || net->n_in == 4, "network inputs must be 2 or 4");
+    }
+    BSP_CHECK_ARG(U != nullptr, "U is NULL");
+    if (ws == nullptr || ws_size < ws_bytes(grid->M, sl->N, kind)) {
+        set_error("workspace is NULL or smaller than parareal_workspace_size() = %zu bytes",
+                  ws_bytes(grid->M, sl->N, kind));
+        return BS_ERR_WORKSPACE;
+    }
+    return BS_OK;
+}
+
+static int propagate_checked(const bs_params* prm, const bs_grid* grid, int nsys,
+                             const double* tau0, double dtau, int steps, const double* u_in,
+                             double* u_out, double theta, void* stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_params(prm))) return rc;
+    if ((rc = check_grid(grid))) return rc;
+    BSP_CHECK_ARG(nsys >= 0, "nsys must be >= 0");
+    BSP_CHECK_ARG(steps >= 1, "steps must be >= 1");
+    BSP_CHECK_ARG(dtau > 0 && std::isfinite(dtau), "dtau must be positive");
+    if (nsys == 0) return BS_OK;
+    BSP_CHECK_ARG(tau0 && u_in && u_out, "tau0, u_in and u_out must be non-NULL");
+    const OptionDev o = make_option(*prm, grid->M);
+    return launch_theta_batch(o, grid->M, nsys, tau0, 0.0, 0.0, 0, dtau / steps, steps, theta, 0,
+                              u_in, grid->M, u_out, grid->M, (hipStream_t)stream);
+}
+
+}  // namespace bsp
+
+using namespace bsp;
+
+extern "C" {
+
+const char* bs_last_error(void) { return g_err; }
+
+int bs_initial(const bs_params* prm, const bs_grid* grid, double* u0, void* stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_params(prm))) return rc;
+    if ((rc = check_grid(grid))) return rc;
+    BSP_CHECK_ARG(u0 != nullptr, "u0 is NULL");
+    return launch_initial(make_option(*prm, grid->M), grid->M, grid->payoff_mode, u0,
+                          (hipStream_t)stream);
+}
+
+int bs_fine_propagate_batch(const bs_params* prm, const bs_grid* grid, int nsys,
+                            const double* tau0, double dtau, int steps, const double* u_in,
+                            double* u_out, void* stream) {
+    return propagate_checked(prm, grid, nsys, tau0, dtau, steps, u_in, u_out, 0.5, stream);
+}
+
+int bs_coarse_numeric(const bs_params* prm, const bs_grid* grid, int nsys, const double* tau0,
+                      double dtau, int steps, const double* u_in, double* u_out, void* stream) {
+    return propagate_checked(prm, grid, nsys, tau0, dtau, steps, u_in, u_out, 1.0, stream);
+}
+
+size_t parareal_workspace_size(const bs_grid* grid, const bs_slices* sl, int coarse_kind) {
+    if (!grid || !sl || grid->M < 1 || sl->N < 1) return 0;
+    return ws_bytes(grid->M, sl->N, coarse_kind);
+}
+
+int parareal_start(const bs_params* prm, const bs_grid* grid, const bs_slices* sl, int kind,
+                   const pinn_net* net, void* ws, size_t ws_size, double* U, void* stream) {
+    clear_error();
+    int rc = check_parareal(prm, grid, sl, kind, net, ws, ws_size, U);
+    if (rc) return rc;
+    const int M = grid->M, N = sl->N;
+    hipStream_t st = (hipStream_t)stream;
+    const OptionDev o = make_option(*prm, M);
+    const double dT = prm->T / N;
+    Workspace w = ws_layout(ws, M, N, kind);
+    if ((rc = launch_initial(o, M, grid->payoff_mode, U, st))) return rc;
+    if (kind != BS_COARSE_IE) {
+        if ((rc = launch_pinn_grid(*net, o, M, N, dT, w.Vt, st))) return rc;
+    }
+    SweepArgs a{o, M, N, 0, sl->coarse_steps, kind, 1, dT, U, w.Fv, w.Gold, w.Vt, w.result};
+    return launch_sweep(a, st);
+}
+
+static int iterate_impl(const bs_params* prm, const bs_grid* grid, const bs_slices* sl, int kind,
+                        void* ws, double* U, int k, double* defect, int* nonfinite,
+                        hipStream_t st) {
+    const int M = grid->M, N = sl->N;
+    const OptionDev o = make_option(*prm, M);
+    const double dT = prm->T / N;
+    Workspace w = ws_layout(ws, M, N, kind);
+    const int first = k - 1 < N - 1 ? k - 1 : N - 1;
+    int rc = launch_theta_batch(o, M, N - first, nullptr, 0.0, dT, first, dT / sl->fine_steps,
+                                sl->fine_steps, 0.5, 0, U + (long)first * M, M,
+                                w.Fv + (long)first * M, M, st);
+    if (rc) return rc;
+    SweepArgs a{o, M, N, first, sl->coarse_steps, kind, 0, dT, U, w.Fv, w.Gold, w.Vt, w.result};
+    if ((rc = launch_sweep(a, st))) return rc;
+    double res[2];
+    BSP_HIP(hipMemcpyAsync(res, w.result, sizeof(res), hipMemcpyDeviceToHost, st));
+    BSP_HIP(hipStreamSynchronize(st));
+    *defect = res[0];
+    *nonfinite = res[1] != 0.0;
+    if (*nonfinite) {
+        set_error("non-finite value in the Parareal state at iteration %d", k);
+        return BS_ERR_NONFINITE;
+    }
+    return BS_OK;
+}
+
+int parareal_iterate(const bs_params* prm, const bs_grid* grid, const bs_slices* sl, int kind,
+                     const pinn_net* net, void* ws, size_t ws_size, double* U, int k,
+                     double* defect, int* nonfinite, void* stream) {
+    clear_error();
+    int rc = check_parareal(prm, grid, sl, kind, net, ws, ws_size, U);
+    if (rc) return rc;
+    BSP_CHECK_ARG(k >= 1, "iteration index k must be >= 1");
+    BSP_CHECK_ARG(defect && nonfinite, "defect and nonfinite must be non-NULL host pointers");
+    return iterate_impl(prm, grid, sl, kind, ws, U, k, defect, nonfinite, (hipStream_t)stream);
+}
+
+int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* sl, int kind,
+                   double tol, const pinn_net* net, int max_iter, void* ws, size_t ws_size,
+                   double* U, int* iters, double* defect_hist, void* stream) {
+    clear_error();
+    int rc = check_parareal(prm, grid, sl, kind, net, ws, ws_size, U);
+    if (rc) return rc;
+    BSP_CHECK_ARG(iters != nullptr, "iters must be a non-NULL host pointer");
+    BSP_CHECK_ARG(max_iter >= 1, "max_iter must be >= 1");
+    BSP_CHECK_ARG(tol >= 0, "tol must be >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    if ((rc = parareal_start(prm, grid, sl, kind, net, ws, ws_size, U, stream))) return rc;
+    const int kmax = max_iter < sl->N ? max_iter : sl->N;
+    *iters = 0;
+    for (int k = 1; k <= kmax; ++k) {
+        double defect;
+        int bad;
+        rc = iterate_impl(prm, grid, sl, kind, ws, U, k, &defect, &bad, st);
+        *iters = k;
+        if (defect_hist) defect_hist[k - 1] = defect;
+        if (rc) return rc;
+        if (defect <= tol || k == sl->N) return BS_OK;
+    }
+    return BS_NOT_CONVERGED;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+// Internal declarations shared by the translation units of libbsparareal.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "bsparareal.h"
+
+namespace bsp {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define BSP_CHECK_ARG(cond, ...)           \
+    do {                                   \
+        if (!(cond)) {                     \
+            ::bsp::set_error(__VA_ARGS__); \
+            return BS_ERR_ARG;             \
+        }                                  \
+    } while (0)
+
+#define BSP_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess) {                                                         \
+            ::bsp::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),      \
+                             __FILE__, __LINE__);                                       \
+            return BS_ERR_HIP;                                                          \
+        }                                                                               \
+    } while (0)
+
+#define BSP_LAUNCHED()                                                                 \
+    do {                                                                               \
+        hipError_t e_ = hipGetLastError();                                             \
+        if (e_ != hipSuccess) {                                                        \
+            ::bsp::set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), \
+                             __FILE__, __LINE__);                                      \
+            return BS_ERR_HIP;                                                         \
+        }                                                                              \
+    } while (0)
+
+constexpr int kMaxM = 16384;
+
+// ------------------------------------------------------- model on device
+
+// Coefficients a kernel needs about one option.
+struct OptionDev {
+    double K, r, s2, s_max, dS;
+    int is_put;
+};
+
+inline OptionDev make_option(const bs_params& p, int M) {
+    OptionDev o;
+    o.K = p.K;
+    o.r = p.r;
+    o.s2 = p.sigma * p.sigma;
+    o.s_max = p.s_max;
+    o.dS = p.s_max / (double)(M + 1);
+    o.is_put = p.is_put;
+    return o;
+}
+
+// Row j (1-based) of the centred-difference operator in time to maturity,
+// dV_j/dtau = al V_{j-1} + be V_j + ga V_{j+1}.  With S_j = j dS the mesh
+// width cancels: al = (s2 j^2 - r j)/2, be = -(s2 j^2 + r), ga = (s2 j^2 + r j)/2.
+__device__ __forceinline__ void op_row(double s2, double r, double j, double& al, double& be,
+                                       double& ga) {
+    double q = s2 * j * j;
+    double p = r * j;
+    al = 0.5 * (q - p);
+    be = -(q + r);
+    ga = 0.5 * (q + p);
+}
+
+// Dirichlet data at S = 0 (lo) and S = S_max (hi) for time to maturity tau.
+__device__ __forceinline__ void dirichlet(const OptionDev& o, double disc, double& lo, double& hi) {
+    if (o.is_put) {
+        lo = o.K * disc;
+        hi = 0.0;
+    } else {
+        lo = 0.0;
+        hi = o.s_max - o.K * disc;
+    }
+}
+
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+
+// ------------------------------------------------------- launch shapes
+
+// Block shape of the tridiagonal kernels for M interior nodes: T threads,
+// MC consecutive nodes per thread (T * MC >= M).
+struct TriShape {
+    int T, MC;
+};
+TriShape tri_shape(int M);
+
+// --------------------------------------------------- internal launchers
+
+// theta-method on nsys independent systems: tau of system s = tau0[s] if
+// tau0 != nullptr else tau_start + (s + sys_offset) * tau_stride.
+// homog: zero boundary data.
+int launch_theta_batch(const OptionDev& o, int M, int nsys, const double* tau0, double tau_start,
+                       double tau_stride, int sys_offset, double dt, int steps, double theta,
+                       int homog, const double* u_in, long ld_in, double* u_out, long ld_out,
+                       hipStream_t stream);
+
+struct SweepArgs {
+    OptionDev o;
+    int M, N, n0, coarse_steps, kind, predict;
+    double dT;                     // slice length
+    double* U;                     // [N+1][M]
+    const double* Fv;              // [N][M]
+    double* Gold;                  // [N][M]
+    const double* Vt;              // [N+1][M] or nullptr
+    double* result;                // [0] defect, [1] non-finite flag (as double)
+};
+int launch_sweep(const SweepArgs& a, hipStream_t stream);
+
+int launch_initial(const OptionDev& o, int M, int payoff_mode, double* u0, hipStream_t stream);
+
+// Network evaluated on the Parareal grid: Vt[n][j] = K v(n dT, (j+1) dS / K).
+int launch_pinn_grid(const pinn_net& net, const OptionDev& o, int M, int N, double dT, double* Vt,
+                     hipStream_t stream);
+
+int check_net(const pinn_net* net);
+long net_param_count(const pinn_net& net);
+
+}  // namespace bsp

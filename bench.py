@@ -1,0 +1,182 @@
+#!/usr/bin/env python
+"""Benchmark: Parareal time-to-solution on one MI355X for the Black-Scholes
+network-coarse workload (European call K=100, r=0.05, sigma=0.2, T=1,
+S in [0, 300]; M = 1024 interior nodes, N = 32 slices, 512 Crank-Nicolson
+steps per slice, FP64 state; coarse = 4 x 64 tanh network trained on that
+call, anchoring one implicit-Euler step per slice; tol 1e-8 on the max-norm
+change of the iterate).
+
+One "step" is one whole Parareal solve from the payoff to convergence.
+Prints ONE JSON line.  `value` = fine cell-updates per second of the solve:
+Crank-Nicolson cell updates executed by all its F sweeps divided by its
+time-to-solution.  Also reported: iterations, time-to-solution, the same
+solve with the numerical coarse propagator, serial fine integration on the
+same GPU, the dominant kernel against its roofline, and the CPU oracle timed
+on this host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--coarse pinn|ie]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Parareal time-to-solution & iters (PINN vs numeric G); fine cell-updates/s"
+FP64_VALU_PEAK_TFLOPS = 78.6
+FLOPS_PER_CELL = 10.0  # one Crank-Nicolson cell update with precomputed factors
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--coarse", choices=["pinn", "ie"], default="ie")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip the comparison solves")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the slices would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2303_03848_amd as bsp
+    from workloads import PINN_CALL, option_params
+
+    cfg = PINN_CALL
+    p = option_params(cfg)
+    M, N, Sf, tol = cfg["M"], cfg["N"], cfg["fine_steps"], cfg["tol"]
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    log(f"[bench] device {torch.cuda.get_device_name(dev)}; workload {cfg['name']}")
+
+    net = None
+    kind = bsp.COARSE_IE
+    train_info = None
+    if args.coarse == "pinn":
+        from paper_2303_03848_amd.pinn import train_call_network
+        t0 = time.time()
+        net, train_info = train_call_network(cfg)
+        kind = bsp.COARSE_PINN_IE
+        log(f"[bench] network trained in {time.time() - t0:.1f}s: {train_info}")
+
+    pr = bsp.Parareal(p, M, N, Sf, 1, kind, net)
+
+    def solve():
+        return pr.solve(tol)
+
+    for w in range(args.warmup):
+        it, d, _ = solve()
+        log(f"[bench] warmup {w}: iters {it}, last defect {d[-1]:.3e}")
+
+    torch.cuda.synchronize()
+    bsp.bs_profile_enable(True)
+    iters_all = []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        it, d, _ = solve()
+        iters_all.append(it)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = bsp.bs_profile_read()
+    bsp.bs_profile_enable(False)
+    ms_per_step = 1e3 * elapsed / args.steps
+    log(f"[bench] timed {args.steps} solves: {ms_per_step:.3f} ms each, iters {iters_all}")
+
+    cells = prof["fine_cells"] / args.steps
+    value = cells / (ms_per_step / 1e3)
+    f_ms = prof["fine_ms"] / max(prof["fine_launches"], 1)
+    achieved = prof["fine_cells"] * FLOPS_PER_CELL / (prof["fine_ms"] / 1e3) / 1e12
+    sweep_ms = prof["sweep_ms"] / max(prof["sweep_launches"], 1)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "cell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "M": M, "N": N, "fine_steps": Sf,
+                   "coarse": "pinn_ie" if kind == bsp.COARSE_PINN_IE else "implicit_euler",
+                   "coarse_steps": 1, "tol": tol,
+                   "network": (f"{cfg['depth']}x{cfg['width']} tanh "
+                               f"{'bf16' if net is not None and net.precision else 'fp32'}"
+                               if net is not None else None)},
+        "iters": iters_all[-1],
+        "time_to_solution_ms": ms_per_step,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+                     "traffic": None, "kernel": "k_theta_batch (Crank-Nicolson F)",
+                     "avg_launch_ms": f_ms, "launches_per_step": prof["fine_launches"] / args.steps,
+                     "flops_per_cell": FLOPS_PER_CELL},
+        "sweep_avg_launch_ms": sweep_ms,
+    }
+    if train_info is not None:
+        out["training"] = train_info
+
+    if not args.no_compare:
+        comp = {}
+        if kind != bsp.COARSE_IE:
+            pr_ie = bsp.Parareal(p, M, N, Sf, 1, bsp.COARSE_IE)
+            pr_ie.solve(tol)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            it_ie, _, _ = pr_ie.solve(tol)
+            torch.cuda.synchronize()
+            comp["numeric_coarse"] = {"iters": it_ie,
+                                      "time_to_solution_ms": 1e3 * (time.perf_counter() - t0)}
+        # serial fine integration on the same GPU: one system, N * Sf steps
+        u0 = bsp.bs_initial(p, M).reshape(1, M)
+        tau0 = torch.zeros(1, dtype=torch.float64, device=dev)
+        bsp.bs_fine_propagate_batch(p, M, tau0, p["T"], N * Sf, u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bsp.bs_fine_propagate_batch(p, M, tau0, p["T"], N * Sf, u0)
+        torch.cuda.synchronize()
+        comp["serial_fine_gpu_ms"] = 1e3 * (time.perf_counter() - t0)
+        # speedup bound of the paper's eq. (8) with measured per-slice costs (P = N)
+        c_f = f_ms
+        c_c = sweep_ms / N
+        K_it = iters_all[-1]
+        comp["speedup_bound_eq8"] = 1.0 / ((1 + K_it / N) * c_c / c_f + K_it / N)
+        comp["speedup_vs_serial_fine"] = comp["serial_fine_gpu_ms"] / ms_per_step
+        out["comparisons"] = comp
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = min(N, cpu_cores())
+        po = oracle.params_from(p)
+        t0 = time.perf_counter()
+        r = oracle.parareal(po, M, N, Sf, 1, oracle.COARSE_IE, tol=tol, nthreads=threads)
+        dt = time.perf_counter() - t0
+        ora_cells = r["iters"] * N * Sf * M
+        out["cpu_baseline"] = {
+            "value": ora_cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": (f"one oracle Parareal solve, numerical coarse, on the full {cfg['name']} "
+                       f"grid ({r['iters']} iterations, F over slices on {threads} threads): "
+                       f"{dt:.2f} s"),
+            "time_to_solution_ms": 1e3 * dt}
+        log(f"[bench] cpu oracle: {dt:.2f}s, {r['iters']} iters, {threads} threads")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

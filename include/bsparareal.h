@@ -183,6 +183,30 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
                    int coarse_kind, double tol, const pinn_net* net, int max_iter, void* ws,
                    size_t ws_bytes, double* U, int* iters, double* defect_hist, void* stream);
 
+/* Block shape of the tridiagonal kernels (for the autotuner).  Each system is
+ * solved by one thread block of `threads` threads holding `nodes_per_thread`
+ * consecutive nodes each.  kernel 0: the batched propagator kernel (F, and G
+ * in bs_coarse_numeric); kernel 1: the serial Parareal sweep.  The setting
+ * applies to grids with M_lo <= M <= M_hi (later settings win) until
+ * bs_tune_reset().  Only built shapes are accepted (BS_ERR_ARG otherwise):
+ * (64,2) (64,4) (64,8) (64,16) (128,4) (128,8) (256,4) (256,8) (512,8), and
+ * threads * nodes_per_thread must cover M_hi.  Results do not depend on the
+ * shape beyond rounding.  Process-wide; not thread-safe. */
+int bs_tune_set_shape(int kernel, int M_lo, int M_hi, int threads, int nodes_per_thread);
+int bs_tune_reset(void);
+
+/* Kernel timing of the Parareal iteration, for measurement.
+ * bs_profile_enable(1) resets the counters and makes parareal_iterate /
+ * parareal_solve record HIP events on their stream around each launch of the
+ * fine-propagator kernel and of the sweep kernel; bs_profile_enable(0) stops
+ * recording.  Timing adds no synchronisation beyond the per-iteration one.
+ * bs_profile_read fills out[6] (host) with: total fine-kernel milliseconds,
+ * number of fine launches, fine cell-updates launched (systems x steps x M),
+ * total sweep milliseconds, number of sweep launches, 0.  Process-wide, not
+ * thread-safe: for a single measuring thread. */
+int bs_profile_enable(int on);
+int bs_profile_read(double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -30,7 +30,8 @@ PREC_FP32, PREC_BF16 = 0, 1
 
 EXPORTS = ("bs_last_error", "bs_initial", "bs_fine_propagate_batch", "bs_coarse_numeric",
            "pinn_forward", "pinn_residual_workspace_size", "pinn_residual_fwd_bwd",
-           "parareal_workspace_size", "parareal_start", "parareal_iterate", "parareal_solve")
+           "parareal_workspace_size", "parareal_start", "parareal_iterate", "parareal_solve",
+           "bs_tune_set_shape", "bs_tune_reset", "bs_profile_enable", "bs_profile_read")
 
 
 class BsError(RuntimeError):
@@ -83,6 +84,10 @@ def load_library(path: str = LIB_PATH):
         "parareal_start": (i, [P, G, S, i, N, vp, sz, vp, vp]),
         "parareal_iterate": (i, [P, G, S, i, N, vp, sz, vp, i, dp, ip, vp]),
         "parareal_solve": (i, [P, G, S, i, d, N, i, vp, sz, vp, ip, dp, vp]),
+        "bs_tune_set_shape": (i, [i, i, i, i, i]),
+        "bs_tune_reset": (i, []),
+        "bs_profile_enable": (i, [i]),
+        "bs_profile_read": (i, [dp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -232,6 +237,26 @@ class Parareal:
             float(tol), self._net(), int(max_iter), self.ws.data_ptr(), self.ws_bytes,
             self.U.data_ptr(), ctypes.byref(it), hist, _stream()))
         return it.value, list(hist)[: it.value], rc
+
+
+def bs_tune_set_shape(kernel: int, M_lo: int, M_hi: int, threads: int, nodes_per_thread: int):
+    """Use (threads, nodes_per_thread) blocks for M in [M_lo, M_hi]; kernel 0 = F/G batch, 1 = sweep."""
+    _check(load_library().bs_tune_set_shape(kernel, M_lo, M_hi, threads, nodes_per_thread))
+
+
+def bs_tune_reset():
+    _check(load_library().bs_tune_reset())
+
+
+def bs_profile_enable(on: bool = True):
+    _check(load_library().bs_profile_enable(int(bool(on))))
+
+
+def bs_profile_read() -> dict:
+    out = (ctypes.c_double * 6)()
+    _check(load_library().bs_profile_read(out))
+    return {"fine_ms": out[0], "fine_launches": int(out[1]), "fine_cells": out[2],
+            "sweep_ms": out[3], "sweep_launches": int(out[4])}
 
 
 def parareal_solve(p: dict, M: int, N: int, fine_steps: int, coarse_steps: int = 1,

@@ -116,6 +116,14 @@ static int propagate_checked(const bs_params* prm, const bs_grid* grid, int nsys
                               u_in, grid->M, u_out, grid->M, (hipStream_t)stream);
 }
 
+// ----------------------------------------------------------- profiling
+struct Profile {
+    bool on = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    double fine_ms = 0, fine_launches = 0, fine_cells = 0, sweep_ms = 0, sweep_launches = 0;
+};
+static Profile g_prof;
+
 }  // namespace bsp
 
 using namespace bsp;
@@ -123,6 +131,42 @@ using namespace bsp;
 extern "C" {
 
 const char* bs_last_error(void) { return g_err; }
+
+int bs_profile_enable(int on) {
+    clear_error();
+    if (on) {
+        for (auto& e : g_prof.ev)
+            if (!e) BSP_HIP(hipEventCreate(&e));
+    }
+    g_prof.on = on != 0;
+    if (on) {
+        g_prof.fine_ms = g_prof.fine_launches = g_prof.fine_cells = 0;
+        g_prof.sweep_ms = g_prof.sweep_launches = 0;
+    }
+    return BS_OK;
+}
+
+int bs_tune_set_shape(int kernel, int M_lo, int M_hi, int threads, int nodes_per_thread) {
+    clear_error();
+    return set_shape_override(kernel, M_lo, M_hi, threads, nodes_per_thread);
+}
+
+int bs_tune_reset(void) {
+    clear_error();
+    reset_shape_overrides();
+    return BS_OK;
+}
+
+int bs_profile_read(double* out) {
+    BSP_CHECK_ARG(out != nullptr, "out is NULL");
+    out[0] = g_prof.fine_ms;
+    out[1] = g_prof.fine_launches;
+    out[2] = g_prof.fine_cells;
+    out[3] = g_prof.sweep_ms;
+    out[4] = g_prof.sweep_launches;
+    out[5] = 0;
+    return BS_OK;
+}
 
 int bs_initial(const bs_params* prm, const bs_grid* grid, double* u0, void* stream) {
     clear_error();
@@ -176,15 +220,29 @@ static int iterate_impl(const bs_params* prm, const bs_grid* grid, const bs_slic
     const double dT = prm->T / N;
     Workspace w = ws_layout(ws, M, N, kind);
     const int first = k - 1 < N - 1 ? k - 1 : N - 1;
+    const bool prof = g_prof.on;
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[0], st));
     int rc = launch_theta_batch(o, M, N - first, nullptr, 0.0, dT, first, dT / sl->fine_steps,
                                 sl->fine_steps, 0.5, 0, U + (long)first * M, M,
                                 w.Fv + (long)first * M, M, st);
     if (rc) return rc;
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[1], st));
     SweepArgs a{o, M, N, first, sl->coarse_steps, kind, 0, dT, U, w.Fv, w.Gold, w.Vt, w.result};
     if ((rc = launch_sweep(a, st))) return rc;
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[2], st));
     double res[2];
     BSP_HIP(hipMemcpyAsync(res, w.result, sizeof(res), hipMemcpyDeviceToHost, st));
     BSP_HIP(hipStreamSynchronize(st));
+    if (prof) {
+        float f_ms = 0.f, s_ms = 0.f;
+        BSP_HIP(hipEventElapsedTime(&f_ms, g_prof.ev[0], g_prof.ev[1]));
+        BSP_HIP(hipEventElapsedTime(&s_ms, g_prof.ev[1], g_prof.ev[2]));
+        g_prof.fine_ms += f_ms;
+        g_prof.fine_launches += 1;
+        g_prof.fine_cells += (double)(N - first) * sl->fine_steps * M;
+        g_prof.sweep_ms += s_ms;
+        g_prof.sweep_launches += 1;
+    }
     *defect = res[0];
     *nonfinite = res[1] != 0.0;
     if (*nonfinite) {

@@ -95,7 +95,9 @@ constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
 struct TriShape {
     int T, MC;
 };
-TriShape tri_shape(int M);
+TriShape tri_shape(int M);  // {0, 0} if M has no kernel shape
+int set_shape_override(int kernel, int M_lo, int M_hi, int T, int MC);
+void reset_shape_overrides();
 
 // --------------------------------------------------- internal launchers
 

@@ -49,7 +49,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--coarse", choices=["pinn", "ie"], default="ie")
+    ap.add_argument("--coarse", choices=["pinn", "ie"], default="pinn")
+    ap.add_argument("--train-steps", type=int, nargs=2, default=(6000, 4000),
+                    metavar=("HI", "LO"), help="Adam steps at lr 1e-2 and 1e-3")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison solves")
     args = ap.parse_args()
@@ -63,11 +66,16 @@ def main():
     from workloads import PINN_CALL, option_params
 
     cfg = PINN_CALL
-    p = option_params(cfg)
+    p = option_params(cfg)  # the benchmark workload: 1024-node call, 32 slices
     M, N, Sf, tol = cfg["M"], cfg["N"], cfg["fine_steps"], cfg["tol"]
     torch.cuda.init()
     dev = torch.device("cuda:0")
     log(f"[bench] device {torch.cuda.get_device_name(dev)}; workload {cfg['name']}")
+
+    if not args.no_autotune:
+        from paper_2303_03848_amd import autotune
+        ent = autotune.tune_workload(cfg["name"], p, M, N, Sf, use_cache=False)
+        log(f"[bench] autotuned block shapes: fine {ent['fine']} sweep {ent['sweep']}")
 
     net = None
     kind = bsp.COARSE_IE
@@ -75,7 +83,7 @@ def main():
     if args.coarse == "pinn":
         from paper_2303_03848_amd.pinn import train_call_network
         t0 = time.time()
-        net, train_info = train_call_network(cfg)
+        net, train_info = train_call_network(cfg, *args.train_steps)
         kind = bsp.COARSE_PINN_IE
         log(f"[bench] network trained in {time.time() - t0:.1f}s: {train_info}")
 
@@ -133,15 +141,27 @@ def main():
 
     if not args.no_compare:
         comp = {}
-        if kind != bsp.COARSE_IE:
-            pr_ie = bsp.Parareal(p, M, N, Sf, 1, bsp.COARSE_IE)
-            pr_ie.solve(tol)
+
+        def timed_solve(pr_x, reps=3):
+            pr_x.solve(tol)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            it_ie, _, _ = pr_ie.solve(tol)
+            for _ in range(reps):
+                it_x, d_x, _ = pr_x.solve(tol)
             torch.cuda.synchronize()
-            comp["numeric_coarse"] = {"iters": it_ie,
-                                      "time_to_solution_ms": 1e3 * (time.perf_counter() - t0)}
+            return {"iters": it_x, "first_defect": d_x[0],
+                    "time_to_solution_ms": 1e3 * (time.perf_counter() - t0) / reps}
+
+        if kind != bsp.COARSE_IE:
+            comp["numeric_coarse"] = timed_solve(bsp.Parareal(p, M, N, Sf, 1, bsp.COARSE_IE))
+            net32 = bsp.PinnNet(net.params, net.n_in, net.depth, net.width, bsp.PREC_FP32)
+            comp["pinn_coarse_fp32_network"] = timed_solve(
+                bsp.Parareal(p, M, N, Sf, 1, bsp.COARSE_PINN_IE, net32))
+            # BF16 network against the FP32 network on the Parareal grid, price units
+            from paper_2303_03848_amd.pinn import grid_values
+            vb = grid_values(net, p, M, N).double()
+            vf = grid_values(net32, p, M, N).double()
+            comp["bf16_network_max_abs_diff_vs_fp32"] = float((vb - vf).abs().max()) * p["K"]
         # serial fine integration on the same GPU: one system, N * Sf steps
         u0 = bsp.bs_initial(p, M).reshape(1, M)
         tau0 = torch.zeros(1, dtype=torch.float64, device=dev)

@@ -156,6 +156,11 @@ def boundary_target(X, is_put, r=None):
     return np.where(lower, 0.0, x - disc)
 
 
+def _mean(a):
+    """Mean of the squared terms; an empty set of points contributes 0."""
+    return float(np.mean(a)) if a.size else 0.0
+
+
 def loss3(theta, X_f, X_e, X_b, n_in, depth, width, is_put=False, sigma=None, r=None):
     """(MSE_f, MSE_exp, MSE_b), eqs. (12)-(14); their sum is eq. (11)."""
     f = residual(theta, X_f, n_in, depth, width, sigma, r)
@@ -163,7 +168,7 @@ def loss3(theta, X_f, X_e, X_b, n_in, depth, width, is_put=False, sigma=None, r=
     vb = forward(theta, X_b, n_in, depth, width)
     ye = terminal_target(X_e, is_put)
     yb = boundary_target(X_b, is_put, r)
-    return (float(np.mean(f * f)), float(np.mean((ve - ye) ** 2)), float(np.mean((vb - yb) ** 2)))
+    return (_mean(f * f), _mean((ve - ye) ** 2), _mean((vb - yb) ** 2))
 
 
 def loss_grad(theta, X_f, X_e, X_b, n_in, depth, width, is_put=False, sigma=None, r=None):

@@ -5,6 +5,7 @@
 // points sit in LDS as [unit][point] (each thread reads its own column, no
 // bank conflicts); weights are wave-uniform and arrive through scalar loads.
 #include "bsp_common.hpp"
+#include "bsp_net.hpp"
 
 namespace bsp {
 
@@ -26,28 +27,6 @@ int check_net(const pinn_net* net) {
     BSP_CHECK_ARG(net->precision == BS_PREC_FP32 || net->precision == BS_PREC_BF16,
                   "pinn_net.precision must be BS_PREC_FP32 or BS_PREC_BF16");
     return BS_OK;
-}
-
-// Where the inputs of point i come from: an explicit [n][n_in] array, or the
-// Parareal grid (tau_n = n dT, x_j = (j+1) dS / K, i = n*M + j).
-struct NetInput {
-    const float* X;
-    int n_in;
-    int M;
-    double dT, dS_over_K, sigma, r;
-};
-
-__device__ __forceinline__ void net_input(const NetInput& in, long i, float (&x)[4]) {
-    if (in.X) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) x[c] = (c < in.n_in) ? in.X[i * in.n_in + c] : 0.0f;
-    } else {
-        const long n = i / in.M, j = i - n * in.M;
-        x[0] = (float)((double)n * in.dT);
-        x[1] = (float)((double)(j + 1) * in.dS_over_K);
-        x[2] = (float)in.sigma;
-        x[3] = (float)in.r;
-    }
 }
 
 // Output: out32[i] = v, or out64[i] = scale * v.

@@ -1,0 +1,54 @@
+// Device helpers for the network kernels: activation, bfloat16 conversion and
+// the gfx950 matrix-core instruction used for every matrix product.
+//
+// v_mfma_f32_32x32x16_bf16 (one wavefront) computes C[32x32] += A[32x16] B[16x32]
+// with bfloat16 inputs and float32 accumulation.  Lane l holds
+//   A[l % 32][8 (l / 32) + e], e = 0..7        (8 bf16)
+//   B[8 (l / 32) + e][l % 32], e = 0..7        (8 bf16)
+//   C[8 (v / 4) + 4 (l / 32) + v % 4][l % 32], v = 0..15   (16 f32)
+// (layout checked on the device against a host product).
+#pragma once
+
+#include "bsp_common.hpp"
+
+namespace bsp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float tanh_f32(float z) { return tanhf(z); }
+
+__device__ __forceinline__ f32x16 mfma32x32x16(const bf16x8& a, const bf16x8& b, const f32x16& c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+// Eight consecutive bf16 from LDS (16-byte aligned).
+__device__ __forceinline__ bf16x8 lds_frag(const __bf16* p) {
+    return *reinterpret_cast<const bf16x8*>(p);
+}
+
+// Where the inputs of point i come from: an explicit [n][n_in] array, or the
+// Parareal grid (tau_n = n dT, x_j = (j+1) dS / K, i = n*M + j).
+struct NetInput {
+    const float* X;
+    int n_in;
+    int M;
+    double dT, dS_over_K, sigma, r;
+};
+
+__device__ __forceinline__ void net_input(const NetInput& in, long i, float (&x)[4]) {
+    if (in.X) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) x[c] = (c < in.n_in) ? in.X[i * in.n_in + c] : 0.0f;
+    } else {
+        const long n = i / in.M, j = i - n * in.M;
+        x[0] = (float)((double)n * in.dT);
+        x[1] = (float)((double)(j + 1) * in.dS_over_K);
+        x[2] = (float)in.sigma;
+        x[3] = (float)in.r;
+    }
+}
+
+__device__ __forceinline__ int mfma_row(int v, int lane) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+
+}  // namespace bsp

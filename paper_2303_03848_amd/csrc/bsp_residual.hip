@@ -1,17 +1,513 @@
-// PINN loss and gradient.
+// PINN loss and its gradient (eqs. (11)-(14)) with the input derivatives the
+// residual of eq. (1) needs, differentiated by hand.
+//
+// Forward: every point carries four streams through the network,
+//   value a, d/dtau a_t, d/dx a_x, d2/dx2 a_xx.
+// For z = W a_prev + b (z_t = W a_prev_t, ...) and a = tanh(z), s = 1 - a^2:
+//   a_t = s z_t,  a_x = s z_x,  a_xx = s z_xx - 2 a s z_x^2.
+// Per layer the cache keeps (a, z_t, z_x, z_xx) for every (point, unit); the
+// input streams of the next layer are recomputed from it.
+//
+// Head: v_* = wo . a_* (+ bo for the value); residual
+//   f = v_t - sigma^2 x^2 v_xx / 2 - r x v_x + r v      (x = S/K, v = V/K),
+// terminal and boundary mismatches; the output adjoints g_* of (v, v_t, v_x,
+// v_xx) are (r, 1, -r x, -sigma^2 x^2 / 2) * 2 f / n_f at interior points and
+// (1, 0, 0, 0) * 2 (v - y) / n at terminal / boundary points.
+//
+// Backward through a = tanh(z), given the adjoints (A, At, Ax, Axx) of
+// (a, a_t, a_x, a_xx):
+//   zb_t  = s At,  zb_x = s Ax - 4 a s z_x Axx,  zb_xx = s Axx,
+//   zb    = s [A - 2 a (z_t At + z_x Ax + z_xx Axx) - 2 z_x^2 (1 - 3 a^2) Axx];
+// through the linear layer: dW += sum_s zb_s a_prev_s^T, db += sum zb, and the
+// adjoints of the previous streams are W^T zb_s.  In the first layer
+// z_t = W[:,0], z_x = W[:,1], so dW[:,0] += sum zb_t, dW[:,1] += sum zb_x.
+//
+// Buffers (workspace, float32, stream-major [4][n_pad][W]): cache per layer,
+// zbar, abar; g [4][n_pad]; per-point loss terms [n_pad].
+// Every reduction over points is a fixed-order loop or tree: results are
+// bitwise reproducible.
+#include <cmath>
+
 #include "bsp_common.hpp"
+#include "bsp_net.hpp"
+
+namespace bsp {
+
+// ------------------------------------------------------------------ layout
+
+struct NetLayout {
+    int n_in, depth, W;
+    long offW[17], offb[17];  // layer l = 1..depth
+    long off_wo, off_bo, total;
+};
+
+static NetLayout net_layout(const pinn_net& n) {
+    NetLayout L{};
+    L.n_in = n.n_in;
+    L.depth = n.depth;
+    L.W = n.width;
+    long o = 0;
+    int fan = n.n_in;
+    for (int l = 1; l <= n.depth; ++l) {
+        L.offW[l] = o;
+        o += (long)n.width * fan;
+        L.offb[l] = o;
+        o += n.width;
+        fan = n.width;
+    }
+    L.off_wo = o;
+    o += n.width;
+    L.off_bo = o;
+    o += 1;
+    L.total = o;
+    return L;
+}
+
+struct ResWs {
+    long n_pad;
+    float* cache;   // depth * 4 * n_pad * W
+    float* zbar;    // 4 * n_pad * W
+    float* abar;    // 4 * n_pad * W
+    float* g;       // 4 * n_pad
+    float* lossc;   // n_pad
+    float* part;    // MFMA path: partial gradients
+    size_t bytes;
+};
+
+constexpr int kResPartBlocks = 64;
+
+static size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static ResWs res_layout(const pinn_net& n, long npts, void* base) {
+    ResWs w{};
+    w.n_pad = (npts + 31) / 32 * 32;
+    const size_t plane = (size_t)4 * w.n_pad * n.width * sizeof(float);
+    char* p = (char*)base;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        char* q = p ? p + off : nullptr;
+        off += a256(b);
+        return q;
+    };
+    w.cache = (float*)take(plane * n.depth);
+    w.zbar = (float*)take(plane);
+    w.abar = (float*)take(plane);
+    w.g = (float*)take(sizeof(float) * 4 * w.n_pad);
+    w.lossc = (float*)take(sizeof(float) * w.n_pad);
+    w.part = (float*)take(sizeof(float) * (size_t)kResPartBlocks * net_layout(n).total);
+    w.bytes = off;
+    return w;
+}
+
+// ------------------------------------------------------------- point access
+
+struct Points {
+    const float *Xf, *Xe, *Xb;
+    int nf, ne, nb, n_in;
+    float sigma, r;   // used when n_in == 2
+    int is_put;
+};
+
+__device__ __forceinline__ const float* point_row(const Points& P, long i) {
+    if (i < P.nf) return P.Xf + i * P.n_in;
+    if (i < P.nf + P.ne) return P.Xe + (i - P.nf) * P.n_in;
+    return P.Xb + (i - P.nf - P.ne) * P.n_in;
+}
+
+// Input streams of the layer after `c` (cache of the previous layer).
+__device__ __forceinline__ void streams_from_cache(const float* c, long plane, long idx,
+                                                   float& a, float& at, float& ax, float& axx) {
+    const float av = c[idx], zt = c[plane + idx], zx = c[2 * plane + idx],
+                zxx = c[3 * plane + idx];
+    const float s = 1.0f - av * av;
+    a = av;
+    at = s * zt;
+    ax = s * zx;
+    axx = s * zxx - 2.0f * av * s * zx * zx;
+}
+
+// --------------------------------------------------------- forward kernels
+
+// First layer: z = W1 x + b1, z_t = W1[:,0], z_x = W1[:,1], z_xx = 0.
+__global__ void k_res_first(const float* __restrict__ prm, Points P, long n, long n_pad, int W,
+                            float* __restrict__ cache) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_pad * W) return;
+    const long i = t / W;
+    const int j = (int)(t - i * W);
+    const long plane = n_pad * W;
+    float a = 0.f, zt = 0.f, zx = 0.f;
+    if (i < n) {
+        const float* x = point_row(P, i);
+        const float* w = prm + (long)j * P.n_in;
+        float z = prm[(long)W * P.n_in + j];
+        for (int c = 0; c < P.n_in; ++c) z = fmaf(w[c], x[c], z);
+        a = tanh_f32(z);
+        zt = w[0];
+        zx = w[1];
+    }
+    cache[t] = a;
+    cache[plane + t] = zt;
+    cache[2 * plane + t] = zx;
+    cache[3 * plane + t] = 0.f;
+}
+
+// Layer epilogue: given z (with bias) and the three derivative streams,
+// write the cache entry (a, z_t, z_x, z_xx).
+__device__ __forceinline__ void tanh_epilogue(float z, float zt, float zx, float zxx, float* c,
+                                              long plane, long idx) {
+    c[idx] = tanh_f32(z);
+    c[plane + idx] = zt;
+    c[2 * plane + idx] = zx;
+    c[3 * plane + idx] = zxx;
+}
+
+// Hidden layer, FP32: one thread per (point, unit), four streams.
+__global__ void k_res_fwd_f32(const float* __restrict__ Wl, const float* __restrict__ bl,
+                              const float* __restrict__ cprev, float* __restrict__ cnext,
+                              long n_pad, int W) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_pad * W) return;
+    const long i = t / W;
+    const int j = (int)(t - i * W);
+    const long plane = n_pad * W;
+    float z = bl[j], zt = 0.f, zx = 0.f, zxx = 0.f;
+    const float* w = Wl + (long)j * W;
+    for (int k = 0; k < W; ++k) {
+        float a, at, ax, axx;
+        streams_from_cache(cprev, plane, i * W + k, a, at, ax, axx);
+        const float wk = w[k];
+        z = fmaf(wk, a, z);
+        zt = fmaf(wk, at, zt);
+        zx = fmaf(wk, ax, zx);
+        zxx = fmaf(wk, axx, zxx);
+    }
+    tanh_epilogue(z, zt, zx, zxx, cnext, plane, t);
+}
+
+// Output layer, loss terms and output adjoints (one thread per point).
+__global__ void k_res_head(const float* __restrict__ prm, long off_wo, long off_bo, Points P,
+                           long n, long n_pad, int W, const float* __restrict__ clast,
+                           float* __restrict__ g, float* __restrict__ lossc) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pad) return;
+    if (i >= n) {
+        g[i] = g[n_pad + i] = g[2 * n_pad + i] = g[3 * n_pad + i] = 0.f;
+        lossc[i] = 0.f;
+        return;
+    }
+    const long plane = n_pad * W;
+    const float* wo = prm + off_wo;
+    float v = prm[off_bo], vt = 0.f, vx = 0.f, vxx = 0.f;
+    for (int j = 0; j < W; ++j) {
+        float a, at, ax, axx;
+        streams_from_cache(clast, plane, i * W + j, a, at, ax, axx);
+        v = fmaf(wo[j], a, v);
+        vt = fmaf(wo[j], at, vt);
+        vx = fmaf(wo[j], ax, vx);
+        vxx = fmaf(wo[j], axx, vxx);
+    }
+    const float* x = point_row(P, i);
+    const float sig = P.n_in == 4 ? x[2] : P.sigma;
+    const float rr = P.n_in == 4 ? x[3] : P.r;
+    float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, lc;
+    if (i < P.nf) {
+        const float xx = x[1];
+        const float f = vt - 0.5f * sig * sig * xx * xx * vxx - rr * xx * vx + rr * v;
+        lc = f * f;
+        const float df = 2.0f * f / (float)P.nf;
+        g0 = rr * df;
+        g1 = df;
+        g2 = -rr * xx * df;
+        g3 = -0.5f * sig * sig * xx * xx * df;
+    } else if (i < P.nf + P.ne) {
+        const float xx = x[1];
+        const float y = P.is_put ? fmaxf(1.0f - xx, 0.0f) : fmaxf(xx - 1.0f, 0.0f);
+        lc = (v - y) * (v - y);
+        g0 = 2.0f * (v - y) / (float)P.ne;
+    } else {
+        const float tau = x[0], xx = x[1];
+        const float disc = expf(-rr * tau);
+        const bool lower = xx == 0.0f;
+        const float y = P.is_put ? (lower ? disc : 0.0f) : (lower ? 0.0f : xx - disc);
+        lc = (v - y) * (v - y);
+        g0 = 2.0f * (v - y) / (float)P.nb;
+    }
+    g[i] = g0;
+    g[n_pad + i] = g1;
+    g[2 * n_pad + i] = g2;
+    g[3 * n_pad + i] = g3;
+    lossc[i] = lc;
+}
+
+// loss3[t] = sum of lossc over the points of type t / count (one block).
+__global__ void k_res_loss(const float* __restrict__ lossc, int nf, int ne, int nb,
+                           float* __restrict__ loss3) {
+    __shared__ float red[256];
+    const int ranges[4] = {0, nf, nf + ne, nf + ne + nb};
+    for (int t = 0; t < 3; ++t) {
+        float s = 0.f;
+        for (int i = ranges[t] + threadIdx.x; i < ranges[t + 1]; i += blockDim.x) s += lossc[i];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            const int cnt = ranges[t + 1] - ranges[t];
+            loss3[t] = cnt > 0 ? red[0] / (float)cnt : 0.f;
+        }
+        __syncthreads();
+    }
+}
+
+// --------------------------------------------------------- backward kernels
+
+// zbar from the adjoints of the layer's output streams (abar, or g x wo for
+// the last hidden layer) and the layer cache.  One thread per (point, unit).
+__global__ void k_res_zbar(const float* __restrict__ c, const float* __restrict__ abar,
+                           const float* __restrict__ g, const float* __restrict__ wo,
+                           float* __restrict__ zbar, long n_pad, int W) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_pad * W) return;
+    const long plane = n_pad * W;
+    float A, At, Ax, Axx;
+    if (abar) {
+        A = abar[t];
+        At = abar[plane + t];
+        Ax = abar[2 * plane + t];
+        Axx = abar[3 * plane + t];
+    } else {
+        const long i = t / W;
+        const float w = wo[t - i * W];
+        A = g[i] * w;
+        At = g[n_pad + i] * w;
+        Ax = g[2 * n_pad + i] * w;
+        Axx = g[3 * n_pad + i] * w;
+    }
+    const float a = c[t], zt = c[plane + t], zx = c[2 * plane + t], zxx = c[3 * plane + t];
+    const float s = 1.0f - a * a;
+    zbar[plane + t] = s * At;
+    zbar[2 * plane + t] = s * Ax - 4.0f * a * s * zx * Axx;
+    zbar[3 * plane + t] = s * Axx;
+    zbar[t] = s * (A - 2.0f * a * (zt * At + zx * Ax + zxx * Axx) -
+                   2.0f * zx * zx * (1.0f - 3.0f * a * a) * Axx);
+}
+
+// abar_prev[s][i][k] = sum_j zbar[s][i][j] W[j][k]  (FP32, one thread per (i, k)).
+__global__ void k_res_bwd_data_f32(const float* __restrict__ Wl, const float* __restrict__ zbar,
+                                   float* __restrict__ abar, long n_pad, int W) {
+    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_pad * W) return;
+    const long i = t / W;
+    const int k = (int)(t - i * W);
+    const long plane = n_pad * W;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    for (int j = 0; j < W; ++j) {
+        const float w = Wl[(long)j * W + k];
+        const long idx = i * W + j;
+        s0 = fmaf(zbar[idx], w, s0);
+        s1 = fmaf(zbar[plane + idx], w, s1);
+        s2 = fmaf(zbar[2 * plane + idx], w, s2);
+        s3 = fmaf(zbar[3 * plane + idx], w, s3);
+    }
+    abar[t] = s0;
+    abar[plane + t] = s1;
+    abar[2 * plane + t] = s2;
+    abar[3 * plane + t] = s3;
+}
+
+// The gradient kernels below sum over points in chunks: block c of gridDim.x
+// takes the points [c*chunk, (c+1)*chunk) and writes one partial per output
+// to part[c][count]; k_res_reduce then sums the partials in block order.
+
+__device__ __forceinline__ void chunk_range(long n, long& lo, long& hi) {
+    const long chunk = (n + gridDim.x - 1) / gridDim.x;
+    lo = (long)blockIdx.x * chunk;
+    hi = lo + chunk < n ? lo + chunk : n;
+}
+
+// Hidden-layer weight gradient (FP32): outputs dW[j][k] (W*W) then db[j] (W).
+__global__ void k_res_gradw_f32(const float* __restrict__ zbar, const float* __restrict__ cprev,
+                                long n, long n_pad, int W, float* __restrict__ part) {
+    long lo, hi;
+    chunk_range(n, lo, hi);
+    const long plane = n_pad * W;
+    const int count = W * W + W;
+    for (int x = threadIdx.x; x < count; x += blockDim.x) {
+        float acc = 0.f;
+        if (x < W * W) {
+            const int j = x / W, k = x - j * W;
+            for (long i = lo; i < hi; ++i) {
+                float a, at, ax, axx;
+                streams_from_cache(cprev, plane, i * W + k, a, at, ax, axx);
+                const long idx = i * W + j;
+                acc = fmaf(zbar[idx], a, acc);
+                acc = fmaf(zbar[plane + idx], at, acc);
+                acc = fmaf(zbar[2 * plane + idx], ax, acc);
+                acc = fmaf(zbar[3 * plane + idx], axx, acc);
+            }
+        } else {
+            const int j = x - W * W;
+            for (long i = lo; i < hi; ++i) acc += zbar[i * W + j];
+        }
+        part[(long)blockIdx.x * count + x] = acc;
+    }
+}
+
+// First-layer gradient: dW1[j][c] = sum_i zb_ij x_ic (+ sum zb_t for c = 0,
+// + sum zb_x for c = 1), then db1[j] = sum_i zb_ij.
+__global__ void k_res_grad_first(const float* __restrict__ zbar, Points P, long n, long n_pad,
+                                 int W, float* __restrict__ part) {
+    long lo, hi;
+    chunk_range(n, lo, hi);
+    const long plane = n_pad * W;
+    const int nw = W * P.n_in, count = nw + W;
+    for (int x = threadIdx.x; x < count; x += blockDim.x) {
+        float acc = 0.f;
+        if (x < nw) {
+            const int j = x / P.n_in, c = x - j * P.n_in;
+            for (long i = lo; i < hi; ++i) {
+                const long idx = i * W + j;
+                acc = fmaf(zbar[idx], point_row(P, i)[c], acc);
+                if (c == 0) acc += zbar[plane + idx];
+                if (c == 1) acc += zbar[2 * plane + idx];
+            }
+        } else {
+            const int j = x - nw;
+            for (long i = lo; i < hi; ++i) acc += zbar[i * W + j];
+        }
+        part[(long)blockIdx.x * count + x] = acc;
+    }
+}
+
+// Output-layer gradient: dwo[j] = sum_i sum_s g_s[i] a_s[i][j], then dbo = sum_i g_0[i].
+__global__ void k_res_grad_out(const float* __restrict__ g, const float* __restrict__ clast,
+                               long n, long n_pad, int W, float* __restrict__ part) {
+    long lo, hi;
+    chunk_range(n, lo, hi);
+    const long plane = n_pad * W;
+    const int count = W + 1;
+    for (int x = threadIdx.x; x < count; x += blockDim.x) {
+        float acc = 0.f;
+        if (x < W) {
+            for (long i = lo; i < hi; ++i) {
+                float a, at, ax, axx;
+                streams_from_cache(clast, plane, i * W + x, a, at, ax, axx);
+                acc = fmaf(g[i], a, acc);
+                acc = fmaf(g[n_pad + i], at, acc);
+                acc = fmaf(g[2 * n_pad + i], ax, acc);
+                acc = fmaf(g[3 * n_pad + i], axx, acc);
+            }
+        } else {
+            for (long i = lo; i < hi; ++i) acc += g[i];
+        }
+        part[(long)blockIdx.x * count + x] = acc;
+    }
+}
+
+int launch_res_reduce(const float* part, int nblk, int count, float* out, hipStream_t st);
+
+int launch_res_gemm_bf16(int which, const float* Wl, const float* bl, const float* cin,
+                         float* cout_or_abar, const float* zbar, long n, long n_pad, int W,
+                         float* gW, float* gb, float* part, hipStream_t st);
+
+static dim3 grid_for(long work, int block) { return dim3((unsigned)((work + block - 1) / block)); }
+
+}  // namespace bsp
+
+using namespace bsp;
 
 extern "C" size_t pinn_residual_workspace_size(const pinn_net* net, int n_f, int n_e, int n_b) {
-    (void)net; (void)n_f; (void)n_e; (void)n_b;
-    return 0;
+    if (!net || net->width <= 0 || net->depth < 1 || n_f < 0 || n_e < 0 || n_b < 0) return 0;
+    return res_layout(*net, (long)n_f + n_e + n_b, nullptr).bytes;
 }
 
 extern "C" int pinn_residual_fwd_bwd(const pinn_net* net, const bs_params* prm, int n_f,
                                      const float* X_f, int n_e, const float* X_e, int n_b,
                                      const float* X_b, float* loss3, float* grad, void* ws,
                                      size_t ws_bytes, void* stream) {
-    (void)net; (void)prm; (void)n_f; (void)X_f; (void)n_e; (void)X_e; (void)n_b; (void)X_b;
-    (void)loss3; (void)grad; (void)ws; (void)ws_bytes; (void)stream;
-    bsp::set_error("not built");
-    return BS_ERR_ARG;
+    clear_error();
+    int rc = check_net(net);
+    if (rc) return rc;
+    BSP_CHECK_ARG(prm != nullptr, "bs_params is NULL");
+    BSP_CHECK_ARG(n_f >= 0 && n_e >= 0 && n_b >= 0, "point counts must be >= 0");
+    BSP_CHECK_ARG((n_f == 0 || X_f) && (n_e == 0 || X_e) && (n_b == 0 || X_b),
+                  "point arrays must be non-NULL when their count is positive");
+    BSP_CHECK_ARG(loss3 && grad, "loss3 and grad must be non-NULL");
+    BSP_CHECK_ARG(net->width <= 128 || net->precision == BS_PREC_FP32,
+                  "the bfloat16 residual path supports width <= 128");
+    const long n = (long)n_f + n_e + n_b;
+    const ResWs w = res_layout(*net, n, ws);
+    if (!ws || ws_bytes < w.bytes) {
+        set_error("workspace too small: need %zu bytes", w.bytes);
+        return BS_ERR_WORKSPACE;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const NetLayout L = net_layout(*net);
+    const int W = net->width, d = net->depth;
+    const long np = w.n_pad, plane = np * W, work = np * W;
+    const float* P0 = net->params;
+    Points P{X_f, X_e, X_b, n_f, n_e, n_b, net->n_in, (float)prm->sigma, (float)prm->r,
+             prm->is_put};
+    const bool mfma = net->precision == BS_PREC_BF16;
+    auto cache = [&](int l) { return w.cache + (size_t)(l - 1) * 4 * plane; };
+
+    hipLaunchKernelGGL(k_res_first, grid_for(work, 256), dim3(256), 0, st, P0, P, n, np, W,
+                       cache(1));
+    BSP_LAUNCHED();
+    for (int l = 2; l <= d; ++l) {
+        if (mfma) {
+            if ((rc = launch_res_gemm_bf16(0, P0 + L.offW[l], P0 + L.offb[l], cache(l - 1),
+                                           cache(l), nullptr, n, np, W, nullptr, nullptr,
+                                           nullptr, st)))
+                return rc;
+        } else {
+            hipLaunchKernelGGL(k_res_fwd_f32, grid_for(work, 256), dim3(256), 0, st,
+                               P0 + L.offW[l], P0 + L.offb[l], cache(l - 1), cache(l), np, W);
+            BSP_LAUNCHED();
+        }
+    }
+    hipLaunchKernelGGL(k_res_head, grid_for(np, 256), dim3(256), 0, st, P0, L.off_wo, L.off_bo,
+                       P, n, np, W, cache(d), w.g, w.lossc);
+    BSP_LAUNCHED();
+    hipLaunchKernelGGL(k_res_loss, dim3(1), dim3(256), 0, st, w.lossc, n_f, n_e, n_b, loss3);
+    BSP_LAUNCHED();
+    hipLaunchKernelGGL(k_res_grad_out, dim3(kResPartBlocks), dim3(256), 0, st, w.g, cache(d), n,
+                       np, W, w.part);
+    BSP_LAUNCHED();
+    // wo and bo are contiguous in the parameter packing
+    if ((rc = launch_res_reduce(w.part, kResPartBlocks, W + 1, grad + L.off_wo, st))) return rc;
+    for (int l = d; l >= 1; --l) {
+        hipLaunchKernelGGL(k_res_zbar, grid_for(work, 256), dim3(256), 0, st, cache(l),
+                           l == d ? nullptr : w.abar, w.g, P0 + L.off_wo, w.zbar, np, W);
+        BSP_LAUNCHED();
+        if (l == 1) {
+            hipLaunchKernelGGL(k_res_grad_first, dim3(kResPartBlocks), dim3(256), 0, st, w.zbar, P,
+                               n, np, W, w.part);
+            BSP_LAUNCHED();
+            // W1 and b1 are contiguous in the parameter packing
+            if ((rc = launch_res_reduce(w.part, kResPartBlocks, W * net->n_in + W,
+                                        grad + L.offW[1], st)))
+                return rc;
+            break;
+        }
+        if (mfma) {
+            if ((rc = launch_res_gemm_bf16(1, P0 + L.offW[l], nullptr, cache(l - 1), w.abar,
+                                           w.zbar, n, np, W, grad + L.offW[l], grad + L.offb[l],
+                                           w.part, st)))
+                return rc;
+        } else {
+            hipLaunchKernelGGL(k_res_bwd_data_f32, grid_for(work, 256), dim3(256), 0, st,
+                               P0 + L.offW[l], w.zbar, w.abar, np, W);
+            BSP_LAUNCHED();
+            hipLaunchKernelGGL(k_res_gradw_f32, dim3(kResPartBlocks), dim3(256), 0, st, w.zbar,
+                               cache(l - 1), n, np, W, w.part);
+            BSP_LAUNCHED();
+            if ((rc = launch_res_reduce(w.part, kResPartBlocks, W * W + W, grad + L.offW[l], st)))
+                return rc;
+        }
+    }
+    return BS_OK;
 }

@@ -140,3 +140,14 @@ def test_grid_values_layout():
         for j, s in enumerate(S):
             ref = 100.0 * mlp.forward(th, np.array([[t, s / 100.0]]), n_in, depth, width)[0]
             assert G[i, j] == pytest.approx(ref, rel=1e-15, abs=1e-13)
+
+
+def test_empty_point_sets_contribute_zero():
+    n_in, depth, width = 2, 2, 8
+    th = _theta(n_in, depth, width)
+    X_f, X_e, X_b = collocation(20, 0, 6, 1.0, 3.0, seed=9)
+    l3 = mlp.loss3(th, X_f, X_e, X_b, n_in, depth, width, False, 0.2, 0.05)
+    assert l3[1] == 0.0 and np.isfinite(l3[0]) and np.isfinite(l3[2])
+    g_empty = mlp.loss_grad(th, X_f, X_e, X_b, n_in, depth, width, False, 0.2, 0.05)
+    g_none = mlp.loss_grad(th, X_f, X_e[:0], X_b, n_in, depth, width, False, 0.2, 0.05)
+    assert np.array_equal(g_empty, g_none)

@@ -183,6 +183,34 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
                    int coarse_kind, double tol, const pinn_net* net, int max_iter, void* ws,
                    size_t ws_bytes, double* U, int* iters, double* defect_hist, void* stream);
 
+/* Bytes of device workspace parareal_solve_batch needs for these options
+ * (host arrays of n_opt entries); 0 if an argument is invalid. */
+size_t parareal_batch_workspace_size(int n_opt, const bs_params* prm, const bs_grid* grids,
+                                     const bs_slices* sl, int coarse_kind);
+
+/* Solve n_opt independent Parareal problems together (batched options with
+ * uneven grids and slice counts).  Every phase of an iteration is one launch
+ * per block-shape class covering all options of the class; options that have
+ * converged, and slices that already hold the serial fine solution, are
+ * skipped on the device, so with use_graph != 0 one iteration is captured
+ * once as a hipGraph and replayed.  Stopping rule per option as in
+ * parareal_solve (defect <= tol, k == N, or k == max_iter).
+ * prm, grids, sl: host arrays [n_opt]; all options share payoff_mode.
+ * U: device FP64; option o's state [N_o+1][M_o] starts at element offsets[o]
+ *    (host array); regions must not overlap.
+ * Network kinds: the network is evaluated on every option's grid with inputs
+ *    (tau, S/K, sigma, r) when n_in == 4 (its sigma, r come from the option)
+ *    and prices calls: a put option takes put-call parity,
+ *    V_put = K v - S + K exp(-r tau).
+ * iters (host [n_opt], out): iterations per option; defects (host [n_opt] or
+ * NULL, out): last defect per option.  SYNCHRONOUS.  Returns BS_OK,
+ * BS_NOT_CONVERGED (some option hit max_iter first), BS_ERR_NONFINITE, or an
+ * argument / workspace / HIP error. */
+int parareal_solve_batch(int n_opt, const bs_params* prm, const bs_grid* grids,
+                         const bs_slices* sl, int coarse_kind, double tol, const pinn_net* net,
+                         int max_iter, void* ws, size_t ws_bytes, double* U, const long* offsets,
+                         int* iters, double* defects, int use_graph, void* stream);
+
 /* Block shape of the tridiagonal kernels (for the autotuner).  Each system is
  * solved by one thread block of `threads` threads holding `nodes_per_thread`
  * consecutive nodes each.  kernel 0: the batched propagator kernel (F, and G

@@ -31,6 +31,7 @@ PREC_FP32, PREC_BF16 = 0, 1
 EXPORTS = ("bs_last_error", "bs_initial", "bs_fine_propagate_batch", "bs_coarse_numeric",
            "pinn_forward", "pinn_residual_workspace_size", "pinn_residual_fwd_bwd",
            "parareal_workspace_size", "parareal_start", "parareal_iterate", "parareal_solve",
+           "parareal_batch_workspace_size", "parareal_solve_batch",
            "bs_tune_set_shape", "bs_tune_reset", "bs_profile_enable", "bs_profile_read")
 
 
@@ -84,6 +85,9 @@ def load_library(path: str = LIB_PATH):
         "parareal_start": (i, [P, G, S, i, N, vp, sz, vp, vp]),
         "parareal_iterate": (i, [P, G, S, i, N, vp, sz, vp, i, dp, ip, vp]),
         "parareal_solve": (i, [P, G, S, i, d, N, i, vp, sz, vp, ip, dp, vp]),
+        "parareal_batch_workspace_size": (sz, [i, P, G, S, i]),
+        "parareal_solve_batch": (i, [i, P, G, S, i, d, N, i, vp, sz, vp,
+                                     ctypes.POINTER(ctypes.c_long), ip, dp, i, vp]),
         "bs_tune_set_shape": (i, [i, i, i, i, i]),
         "bs_tune_reset": (i, []),
         "bs_profile_enable": (i, [i]),
@@ -266,3 +270,37 @@ def parareal_solve(p: dict, M: int, N: int, fine_steps: int, coarse_steps: int =
     pr = Parareal(p, M, N, fine_steps, coarse_steps, coarse_kind, net, payoff_mode)
     iters, defects, _ = pr.solve(tol, max_iter)
     return pr.U, iters, defects
+
+
+def parareal_solve_batch(options, coarse_kind: int = COARSE_IE, tol: float = 1e-8,
+                         net: PinnNet | None = None, max_iter: int | None = None,
+                         payoff_mode: int = 1, use_graph: bool = True):
+    """Solve many options together.  `options`: dicts with K, r, sigma, T, s_max,
+    is_put, M, N, fine_steps, coarse_steps.  Returns (U_packed [cuda float64],
+    offsets, iters, defects, status); option o's state is
+    U_packed[offsets[o]: offsets[o] + (N+1)*M].reshape(N+1, M)."""
+    n = len(options)
+    Pa = (_Params * n)(*[_params(o) for o in options])
+    Ga = (_Grid * n)(*[_Grid(o["M"], payoff_mode) for o in options])
+    Sa = (_Slices * n)(*[_Slices(o["N"], o["fine_steps"], o.get("coarse_steps", 1))
+                         for o in options])
+    offs, tot = [], 0
+    for o in options:
+        offs.append(tot)
+        tot += (o["N"] + 1) * o["M"]
+    Oa = (ctypes.c_long * n)(*offs)
+    lib = load_library()
+    wsb = lib.parareal_batch_workspace_size(n, Pa, Ga, Sa, coarse_kind)
+    if wsb == 0:
+        raise BsError(BS_ERR_ARG, "invalid batch description")
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    U = torch.empty(tot, dtype=torch.float64, device="cuda")
+    it = (ctypes.c_int * n)()
+    de = (ctypes.c_double * n)()
+    if max_iter is None:
+        max_iter = max(o["N"] for o in options)
+    rc = _check(lib.parareal_solve_batch(
+        n, Pa, Ga, Sa, coarse_kind, float(tol), ctypes.byref(net.c()) if net is not None else None,
+        int(max_iter), ws.data_ptr(), wsb, U.data_ptr(), Oa, it, de, int(bool(use_graph)),
+        _stream()))
+    return U, offs, list(it), list(de), rc

@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbsparareal.so")
 BUILD_DIR = os.path.join(PKG, "_build")
 
-SOURCES = ["bsp_api.hip", "bsp_propagate.hip", "bsp_mlp.hip", "bsp_mlp_bf16.hip", "bsp_residual_mfma.hip",
+SOURCES = ["bsp_api.hip", "bsp_propagate.hip", "bsp_batch.hip", "bsp_mlp.hip", "bsp_mlp_bf16.hip", "bsp_residual_mfma.hip",
            "bsp_residual.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -96,6 +96,7 @@ struct TriShape {
     int T, MC;
 };
 TriShape tri_shape(int M);  // {0, 0} if M has no kernel shape
+TriShape shape_for(int kernel, int M);  // kernel 0: F/G batch, 1: sweep
 int set_shape_override(int kernel, int M_lo, int M_hi, int T, int MC);
 void reset_shape_overrides();
 
@@ -126,6 +127,25 @@ int launch_initial(const OptionDev& o, int M, int payoff_mode, double* u0, hipSt
 // Network evaluated on the Parareal grid: Vt[n][j] = K v(n dT, (j+1) dS / K).
 int launch_pinn_grid(const pinn_net& net, const OptionDev& o, int M, int N, double dT, double* Vt,
                      hipStream_t stream);
+
+// Batched options: one record per option (device), and the tiles of 32
+// network-grid points (each inside one option's grid).
+struct BatchOpt {
+    OptionDev o;
+    int M, N, fine_steps, coarse_steps;
+    double dT;
+    long u_off;   // option's U in the caller's packed array
+    long w_off;   // option's Fv / Gold in the workspace (N*M each)
+    long vt_off;  // option's network grid (N+1)*M in the packed grid array
+};
+struct BatchState {
+    int done, iters, bad, pad;
+    double defect;
+};
+struct BatchTile {
+    int opt, pad;
+    long base, count;  // packed index of the option's first grid point; (N+1)*M
+};
 
 int check_net(const pinn_net* net);
 long net_param_count(const pinn_net& net);

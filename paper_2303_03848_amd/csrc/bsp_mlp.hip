@@ -37,9 +37,8 @@ __global__ __launch_bounds__(64) void k_mlp_fp32(const float* __restrict__ prm, 
     __shared__ float act[2][W][64];
     const int t = threadIdx.x;
     const long i = (long)blockIdx.x * 64 + t;
-    const bool valid = i < n;
     float x[4] = {0.f, 0.f, 0.f, 0.f};
-    if (valid) net_input(in, i, x);
+    const bool valid = i < n && net_input(in, i, x);
     const int n_in = in.n_in;
 
     const float* Wl = prm;
@@ -72,10 +71,7 @@ __global__ __launch_bounds__(64) void k_mlp_fp32(const float* __restrict__ prm, 
     }
     float v = base[W];
     for (int k = 0; k < W; ++k) v = fmaf(base[k], act[cur][k][t], v);
-    if (valid) {
-        if (out32) out32[i] = v;
-        if (out64) out64[i] = scale * (double)v;
-    }
+    if (valid) net_store(in, i, v, out32, out64, scale);
 }
 
 int launch_mlp_bf16(const pinn_net& net, long n, const NetInput& in, float* out32, double* out64,
@@ -104,8 +100,14 @@ static int launch_mlp(const pinn_net& net, long n, const NetInput& in, float* ou
 
 int launch_pinn_grid(const pinn_net& net, const OptionDev& o, int M, int N, double dT, double* Vt,
                      hipStream_t stream) {
-    NetInput in{nullptr, net.n_in, M, dT, o.dS / o.K, sqrt(o.s2), o.r};
+    NetInput in{nullptr, net.n_in, M, dT, o.dS / o.K, sqrt(o.s2), o.r, nullptr, nullptr};
     return launch_mlp(net, (long)(N + 1) * M, in, nullptr, Vt, o.K, stream);
+}
+
+int launch_pinn_batch_grid(const pinn_net& net, const BatchOpt* opts, const BatchTile* tiles,
+                           long npts, double* Vt, hipStream_t stream) {
+    NetInput in{nullptr, net.n_in, 1, 0.0, 0.0, 0.0, 0.0, opts, tiles};
+    return launch_mlp(net, npts, in, nullptr, Vt, 1.0, stream);
 }
 
 }  // namespace bsp
@@ -117,6 +119,6 @@ extern "C" int pinn_forward(const pinn_net* net, int n, const float* X, float* v
     if (rc) return rc;
     BSP_CHECK_ARG(n >= 0, "n must be >= 0");
     BSP_CHECK_ARG(n == 0 || (X && v_out), "X and v_out must be non-NULL");
-    bsp::NetInput in{X, net->n_in, 1, 0.0, 0.0, 0.0, 0.0};
+    bsp::NetInput in{X, net->n_in, 1, 0.0, 0.0, 0.0, 0.0, nullptr, nullptr};
     return bsp::launch_mlp(*net, n, in, v_out, nullptr, 1.0, (hipStream_t)stream);
 }

@@ -24,6 +24,7 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(const float* __restrict__ prm,
     __shared__ __align__(16) __bf16 act[2][32 * LDA];
     __shared__ __align__(16) __bf16 ws[W * LDW];
     __shared__ float xin[32][4];
+    __shared__ int ok[32];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r32 = lane & 31, h = lane >> 5;
@@ -32,7 +33,7 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(const float* __restrict__ prm,
 
     if (tid < 32) {
         float x[4] = {0.f, 0.f, 0.f, 0.f};
-        if (base + tid < n) net_input(in, base + tid, x);
+        ok[tid] = base + tid < n && net_input(in, base + tid, x);
 #pragma unroll
         for (int c = 0; c < 4; ++c) xin[tid][c] = x[c];
     }
@@ -95,11 +96,7 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(const float* __restrict__ prm,
     s += __shfl_xor(s, 1);
     s += __shfl_xor(s, 2);
     s += __shfl_xor(s, 4);
-    if (part == 0 && base + i < n) {
-        const float v = s + prm[off + W];
-        if (out32) out32[base + i] = v;
-        if (out64) out64[base + i] = scale * (double)v;
-    }
+    if (part == 0 && ok[i]) net_store(in, base + i, s + prm[off + W], out32, out64, scale);
 }
 
 int launch_mlp_bf16(const pinn_net& net, long n, const NetInput& in, float* out32, double* out64,

@@ -29,23 +29,66 @@ __device__ __forceinline__ bf16x8 lds_frag(const __bf16* p) {
 
 // Where the inputs of point i come from: an explicit [n][n_in] array, or the
 // Parareal grid (tau_n = n dT, x_j = (j+1) dS / K, i = n*M + j).
+// Batch mode (tiles != nullptr): point i lies in tile i / 32, which names its
+// option; the option's grid is packed from tiles[i/32].base on.
 struct NetInput {
     const float* X;
     int n_in;
     int M;
     double dT, dS_over_K, sigma, r;
+    const BatchOpt* bopts;
+    const BatchTile* tiles;
 };
 
-__device__ __forceinline__ void net_input(const NetInput& in, long i, float (&x)[4]) {
+// Inputs of point i; false for the padding points of batch mode.
+__device__ __forceinline__ bool net_input(const NetInput& in, long i, float (&x)[4]) {
     if (in.X) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) x[c] = (c < in.n_in) ? in.X[i * in.n_in + c] : 0.0f;
+        return true;
+    }
+    if (in.tiles) {
+        const BatchTile t = in.tiles[i >> 5];
+        const long li = i - t.base;
+        if (li >= t.count) {
+            x[0] = x[1] = x[2] = x[3] = 0.0f;
+            return false;
+        }
+        const BatchOpt& b = in.bopts[t.opt];
+        const long n = li / b.M, j = li - n * b.M;
+        x[0] = (float)((double)n * b.dT);
+        x[1] = (float)((double)(j + 1) * (b.o.dS / b.o.K));
+        x[2] = (float)sqrt(b.o.s2);
+        x[3] = (float)b.o.r;
+        return true;
+    }
+    const long n = i / in.M, j = i - n * in.M;
+    x[0] = (float)((double)n * in.dT);
+    x[1] = (float)((double)(j + 1) * in.dS_over_K);
+    x[2] = (float)in.sigma;
+    x[3] = (float)in.r;
+    return true;
+}
+
+// Store the network value of point i: out32[i] = v, or out64[i] = scale * v;
+// in batch mode out64[i] = K v, and for a put K v - S + K exp(-r tau) (the
+// network prices calls; put-call parity gives the put).
+__device__ __forceinline__ void net_store(const NetInput& in, long i, float v, float* out32,
+                                          double* out64, double scale) {
+    if (out32) out32[i] = v;
+    if (!out64) return;
+    if (in.tiles) {
+        const BatchTile t = in.tiles[i >> 5];
+        const BatchOpt& b = in.bopts[t.opt];
+        const long li = i - t.base;
+        double V = b.o.K * (double)v;
+        if (b.o.is_put) {
+            const long n = li / b.M, j = li - n * b.M;
+            V = V - (double)(j + 1) * b.o.dS + b.o.K * exp(-b.o.r * ((double)n * b.dT));
+        }
+        out64[i] = V;
     } else {
-        const long n = i / in.M, j = i - n * in.M;
-        x[0] = (float)((double)n * in.dT);
-        x[1] = (float)((double)(j + 1) * in.dS_over_K);
-        x[2] = (float)in.sigma;
-        x[3] = (float)in.r;
+        out64[i] = scale * (double)v;
     }
 }
 

@@ -1,7 +1,7 @@
 // Propagator kernels: expiry payoff, the batched theta-method (Crank-Nicolson
 // fine F, implicit-Euler coarse G) and the serial Parareal correction sweep.
 #include "bsp_common.hpp"
-#include "bsp_tridiag.hpp"
+#include "bsp_steps.hpp"
 
 namespace bsp {
 
@@ -35,65 +35,6 @@ int launch_initial(const OptionDev& o, int M, int payoff_mode, double* u0, hipSt
     return BS_OK;
 }
 
-// ------------------------------------------------------ shared helpers
-
-template <int T, int MC>
-__device__ __forceinline__ void load_chunk(const double* __restrict__ src, int M, double (&V)[MC]) {
-    const int i0 = threadIdx.x * MC;
-#pragma unroll
-    for (int q = 0; q < MC; ++q) V[q] = (i0 + q < M) ? src[i0 + q] : 0.0;
-}
-
-template <int T, int MC>
-__device__ __forceinline__ void store_chunk(double* __restrict__ dst, int M, const double (&V)[MC]) {
-    const int i0 = threadIdx.x * MC;
-#pragma unroll
-    for (int q = 0; q < MC; ++q)
-        if (i0 + q < M) dst[i0 + q] = V[q];
-}
-
-// Steps per boundary-forcing table (two tables of this many doubles in LDS).
-constexpr int kForceChunk = 1024;
-
-// `steps` theta-steps of size dt from tau0 on the state V (this block's system).
-// The boundary forcing of each step, (1-theta) dt g(tau_m) + theta dt g(tau_{m+1})
-// at S = 0 and S = S_max, is tabulated in LDS for a chunk of steps by all
-// threads in parallel, so the sequential step loop evaluates no exponential.
-// ftab: 2 * kForceChunk doubles of LDS.
-template <int T, int MC>
-__device__ __forceinline__ void theta_steps(const BlockTri<T, MC>& S, const OptionDev& o,
-                                            double (&V)[MC], double tau0, double dt, int steps,
-                                            double theta, bool homog, double* lds, double* ftab) {
-    double hl, hr;
-    S.halo(V, hl, hr, lds);
-    const double h = theta * dt, e = (1.0 - theta) * dt;
-    for (int m0 = 0; m0 < steps; m0 += kForceChunk) {
-        const int nch = min(kForceChunk, steps - m0);
-        if (!homog) {
-            __syncthreads();  // the previous chunk's table has been consumed
-            for (int i = threadIdx.x; i < nch; i += T) {
-                const int mm = m0 + i;
-                double lo0, hi0, lo1, hi1;
-                dirichlet(o, exp(-o.r * (tau0 + (double)mm * dt)), lo0, hi0);
-                dirichlet(o, exp(-o.r * (tau0 + (double)(mm + 1) * dt)), lo1, hi1);
-                ftab[i] = fma(e, lo0, h * lo1);
-                ftab[kForceChunk + i] = fma(e, hi0, h * hi1);
-            }
-            __syncthreads();
-        }
-        double flo_n = homog ? 0.0 : ftab[0];
-        double fhi_n = homog ? 0.0 : ftab[kForceChunk];
-        for (int i = 0; i < nch; ++i) {
-            const double flo = flo_n, fhi = fhi_n;
-            if (!homog && i + 1 < nch) {
-                flo_n = ftab[i + 1];
-                fhi_n = ftab[kForceChunk + i + 1];
-            }
-            S.step(V, hl, hr, flo, fhi, lds);
-        }
-    }
-}
-
 // ------------------------------------------------ batched theta-method
 
 struct ThetaArgs {
@@ -124,102 +65,21 @@ __global__ __launch_bounds__(T) void k_theta_batch(ThetaArgs a) {
 
 // ---------------------------------------------------- Parareal sweep
 
-// Serial over slices n = n0..N-1 in one block:
-//   g = G(U[n])                       (state carried in registers)
-//   predict: U[n+1] = g, Gold[n] = g
-//   else:    U[n+1] = Fv[n] + (g - Gold[n]), Gold[n] = g,
-//            defect = max |U_new[n+1] - U_old[n+1]|, non-finite flag.
 template <int T, int MC>
 __global__ __launch_bounds__(T) void k_sweep(SweepArgs a) {
     __shared__ double lds[4 * T];
     __shared__ double ftab[2 * kForceChunk];
-    const int M = a.M;
-    const double dtc = a.dT / (double)a.coarse_steps;
     BlockTri<T, MC> S;
-    S.setup(a.o.s2, a.o.r, dtc, 0.0, M, lds);
-    const int i0 = threadIdx.x * MC;
-    const bool net = a.kind != BS_COARSE_IE;
-
-    double V[MC];
-    load_chunk<T, MC>(a.U + (long)a.n0 * M, M, V);
+    S.setup(a.o.s2, a.o.r, a.dT / (double)a.coarse_steps, 0.0, a.M, lds);
     double dmax = 0.0;
     int bad = 0;
-    for (int n = a.n0; n < a.N; ++n) {
-        double* un1 = a.U + (long)(n + 1) * M;
-        double* go = a.Gold + (long)n * M;
-        // Loads that do not depend on the coarse solve go first, so their
-        // latency overlaps it (when registers allow: small chunks).
-        constexpr bool kPrefetch = MC <= 4;
-        double fv[MC], gold[MC], uold[MC], vt0[MC], vt1[MC];
-        if (kPrefetch && !a.predict) {
-            load_chunk<T, MC>(a.Fv + (long)n * M, M, fv);
-            load_chunk<T, MC>(go, M, gold);
-            load_chunk<T, MC>(un1, M, uold);
-        }
-        if (kPrefetch && net) {
-            load_chunk<T, MC>(a.Vt + (long)(n + 1) * M, M, vt1);
-            if (a.kind == BS_COARSE_PINN_IE) load_chunk<T, MC>(a.Vt + (long)n * M, M, vt0);
-        }
-        double g[MC];
-        if (a.kind == BS_COARSE_IE) {
-#pragma unroll
-            for (int q = 0; q < MC; ++q) g[q] = V[q];
-            theta_steps<T, MC>(S, a.o, g, (double)n * a.dT, dtc, a.coarse_steps, 1.0, false, lds,
-                               ftab);
-        } else if (a.kind == BS_COARSE_PINN) {
-            if (!kPrefetch) load_chunk<T, MC>(a.Vt + (long)(n + 1) * M, M, vt1);
-#pragma unroll
-            for (int q = 0; q < MC; ++q) g[q] = vt1[q];
-        } else {
-            if (!kPrefetch) load_chunk<T, MC>(a.Vt + (long)n * M, M, vt0);
-#pragma unroll
-            for (int q = 0; q < MC; ++q) g[q] = V[q] - vt0[q];
-            theta_steps<T, MC>(S, a.o, g, (double)n * a.dT, dtc, a.coarse_steps, 1.0, true, lds,
-                               ftab);
-            if (!kPrefetch) load_chunk<T, MC>(a.Vt + (long)(n + 1) * M, M, vt1);
-#pragma unroll
-            for (int q = 0; q < MC; ++q) g[q] = vt1[q] + g[q];
-        }
-        if (!kPrefetch && !a.predict) {
-            load_chunk<T, MC>(a.Fv + (long)n * M, M, fv);
-            load_chunk<T, MC>(go, M, gold);
-            load_chunk<T, MC>(un1, M, uold);
-        }
-        if (a.predict) {
-            store_chunk<T, MC>(un1, M, g);
-            store_chunk<T, MC>(go, M, g);
-#pragma unroll
-            for (int q = 0; q < MC; ++q) V[q] = g[q];
-        } else {
-#pragma unroll
-            for (int q = 0; q < MC; ++q) {
-                const double unew = fv[q] + (g[q] - gold[q]);
-                if (i0 + q < M) {
-                    go[i0 + q] = g[q];
-                    un1[i0 + q] = unew;
-                    dmax = fmax(dmax, fabs(unew - uold[q]));
-                    bad |= !isfinite(unew);
-                }
-                V[q] = (i0 + q < M) ? unew : 0.0;
-            }
-        }
-    }
+    sweep_slices<T, MC>(S, a.o, a.M, a.N, a.n0, a.coarse_steps, a.kind, a.predict != 0, a.dT, a.U,
+                        a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad);
     if (!a.predict) {
-        // block max of the defect and OR of the flag
-        __syncthreads();
-        lds[threadIdx.x] = dmax;
-        lds[T + threadIdx.x] = bad ? 1.0 : 0.0;
-        __syncthreads();
-        for (int s = T / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) {
-                lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + s]);
-                lds[T + threadIdx.x] = fmax(lds[T + threadIdx.x], lds[T + threadIdx.x + s]);
-            }
-            __syncthreads();
-        }
+        block_defect<T>(dmax, bad, lds);
         if (threadIdx.x == 0) {
-            a.result[0] = lds[0];
-            a.result[1] = lds[T];
+            a.result[0] = dmax;
+            a.result[1] = bad ? 1.0 : 0.0;
         }
     }
 }
@@ -248,9 +108,6 @@ static TriShape default_shape(int kernel, int M) {
     return {0, 0};
 }
 
-#define BSP_TRI_SHAPES(X) \
-    X(64, 2) X(64, 4) X(64, 8) X(64, 16) X(128, 4) X(128, 8) X(256, 4) X(256, 8) X(512, 8)
-
 static bool shape_built(int T, int MC) {
 #define BSP_IS(T_, MC_) if (T == T_ && MC == MC_) return true;
     BSP_TRI_SHAPES(BSP_IS)
@@ -267,7 +124,7 @@ constexpr int kMaxOverrides = 16;
 static ShapeOverride g_over[2][kMaxOverrides];
 static int g_nover[2] = {0, 0};
 
-static TriShape shape_for(int kernel, int M) {
+TriShape shape_for(int kernel, int M) {
     for (int i = g_nover[kernel] - 1; i >= 0; --i) {
         const ShapeOverride& o = g_over[kernel][i];
         if (M >= o.M_lo && M <= o.M_hi) return o.sh;

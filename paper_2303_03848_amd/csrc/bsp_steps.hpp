@@ -1,0 +1,168 @@
+// Device building blocks shared by the single-option and batched kernels:
+// chunk loads/stores, a run of theta-steps, and the serial Parareal sweep.
+#pragma once
+
+#include "bsp_common.hpp"
+#include "bsp_tridiag.hpp"
+
+namespace bsp {
+
+// Block shapes (threads, nodes per thread) the tridiagonal kernels are built for.
+#define BSP_TRI_SHAPES(X) \
+    X(64, 2) X(64, 4) X(64, 8) X(64, 16) X(128, 4) X(128, 8) X(256, 4) X(256, 8) X(512, 8)
+
+template <int T, int MC>
+__device__ __forceinline__ void load_chunk(const double* __restrict__ src, int M, double (&V)[MC]) {
+    const int i0 = threadIdx.x * MC;
+#pragma unroll
+    for (int q = 0; q < MC; ++q) V[q] = (i0 + q < M) ? src[i0 + q] : 0.0;
+}
+
+template <int T, int MC>
+__device__ __forceinline__ void store_chunk(double* __restrict__ dst, int M, const double (&V)[MC]) {
+    const int i0 = threadIdx.x * MC;
+#pragma unroll
+    for (int q = 0; q < MC; ++q)
+        if (i0 + q < M) dst[i0 + q] = V[q];
+}
+
+// Steps per boundary-forcing table (two tables of this many doubles in LDS).
+constexpr int kForceChunk = 1024;
+
+// `steps` theta-steps of size dt from tau0 on the state V (this block's system).
+// The boundary forcing of each step, (1-theta) dt g(tau_m) + theta dt g(tau_{m+1})
+// at S = 0 and S = S_max, is tabulated in LDS for a chunk of steps by all
+// threads in parallel, so the sequential step loop evaluates no exponential.
+// ftab: 2 * kForceChunk doubles of LDS.
+template <int T, int MC>
+__device__ __forceinline__ void theta_steps(const BlockTri<T, MC>& S, const OptionDev& o,
+                                            double (&V)[MC], double tau0, double dt, int steps,
+                                            double theta, bool homog, double* lds, double* ftab) {
+    double hl, hr;
+    S.halo(V, hl, hr, lds);
+    const double h = theta * dt, e = (1.0 - theta) * dt;
+    for (int m0 = 0; m0 < steps; m0 += kForceChunk) {
+        const int nch = min(kForceChunk, steps - m0);
+        if (!homog) {
+            __syncthreads();  // the previous chunk's table has been consumed
+            for (int i = threadIdx.x; i < nch; i += T) {
+                const int mm = m0 + i;
+                double lo0, hi0, lo1, hi1;
+                dirichlet(o, exp(-o.r * (tau0 + (double)mm * dt)), lo0, hi0);
+                dirichlet(o, exp(-o.r * (tau0 + (double)(mm + 1) * dt)), lo1, hi1);
+                ftab[i] = fma(e, lo0, h * lo1);
+                ftab[kForceChunk + i] = fma(e, hi0, h * hi1);
+            }
+            __syncthreads();
+        }
+        double flo_n = homog ? 0.0 : ftab[0];
+        double fhi_n = homog ? 0.0 : ftab[kForceChunk];
+        for (int i = 0; i < nch; ++i) {
+            const double flo = flo_n, fhi = fhi_n;
+            if (!homog && i + 1 < nch) {
+                flo_n = ftab[i + 1];
+                fhi_n = ftab[kForceChunk + i + 1];
+            }
+            S.step(V, hl, hr, flo, fhi, lds);
+        }
+    }
+}
+
+// One option's serial Parareal sweep over slices n = n0..N-1 in one block:
+//   g = G(U[n])                       (state carried in registers)
+//   predict: U[n+1] = g, Gold[n] = g
+//   else:    U[n+1] = Fv[n] + (g - Gold[n]), Gold[n] = g,
+//            dmax = max |U_new[n+1] - U_old[n+1]|, bad |= non-finite.
+// S must be set up for implicit Euler with dt = dT / coarse_steps.
+template <int T, int MC>
+__device__ __forceinline__ void sweep_slices(const BlockTri<T, MC>& S, const OptionDev& o, int M,
+                                             int N, int n0, int coarse_steps, int kind, bool predict,
+                                             double dT, double* __restrict__ U,
+                                             const double* __restrict__ Fv,
+                                             double* __restrict__ Gold,
+                                             const double* __restrict__ Vt, double* lds,
+                                             double* ftab, double& dmax, int& bad) {
+    const double dtc = dT / (double)coarse_steps;
+    const int i0 = threadIdx.x * MC;
+    const bool net = kind != BS_COARSE_IE;
+    double V[MC];
+    load_chunk<T, MC>(U + (long)n0 * M, M, V);
+    for (int n = n0; n < N; ++n) {
+        double* un1 = U + (long)(n + 1) * M;
+        double* go = Gold + (long)n * M;
+        // Loads that do not depend on the coarse solve go first, so their
+        // latency overlaps it (when registers allow: small chunks).
+        constexpr bool kPrefetch = MC <= 4;
+        double fv[MC], gold[MC], uold[MC], vt0[MC], vt1[MC];
+        if (kPrefetch && !predict) {
+            load_chunk<T, MC>(Fv + (long)n * M, M, fv);
+            load_chunk<T, MC>(go, M, gold);
+            load_chunk<T, MC>(un1, M, uold);
+        }
+        if (kPrefetch && net) {
+            load_chunk<T, MC>(Vt + (long)(n + 1) * M, M, vt1);
+            if (kind == BS_COARSE_PINN_IE) load_chunk<T, MC>(Vt + (long)n * M, M, vt0);
+        }
+        double g[MC];
+        if (kind == BS_COARSE_IE) {
+#pragma unroll
+            for (int q = 0; q < MC; ++q) g[q] = V[q];
+            theta_steps<T, MC>(S, o, g, (double)n * dT, dtc, coarse_steps, 1.0, false, lds, ftab);
+        } else if (kind == BS_COARSE_PINN) {
+            if (!kPrefetch) load_chunk<T, MC>(Vt + (long)(n + 1) * M, M, vt1);
+#pragma unroll
+            for (int q = 0; q < MC; ++q) g[q] = vt1[q];
+        } else {
+            if (!kPrefetch) load_chunk<T, MC>(Vt + (long)n * M, M, vt0);
+#pragma unroll
+            for (int q = 0; q < MC; ++q) g[q] = V[q] - vt0[q];
+            theta_steps<T, MC>(S, o, g, (double)n * dT, dtc, coarse_steps, 1.0, true, lds, ftab);
+            if (!kPrefetch) load_chunk<T, MC>(Vt + (long)(n + 1) * M, M, vt1);
+#pragma unroll
+            for (int q = 0; q < MC; ++q) g[q] = vt1[q] + g[q];
+        }
+        if (!kPrefetch && !predict) {
+            load_chunk<T, MC>(Fv + (long)n * M, M, fv);
+            load_chunk<T, MC>(go, M, gold);
+            load_chunk<T, MC>(un1, M, uold);
+        }
+        if (predict) {
+            store_chunk<T, MC>(un1, M, g);
+            store_chunk<T, MC>(go, M, g);
+#pragma unroll
+            for (int q = 0; q < MC; ++q) V[q] = g[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < MC; ++q) {
+                const double unew = fv[q] + (g[q] - gold[q]);
+                if (i0 + q < M) {
+                    go[i0 + q] = g[q];
+                    un1[i0 + q] = unew;
+                    dmax = fmax(dmax, fabs(unew - uold[q]));
+                    bad |= !isfinite(unew);
+                }
+                V[q] = (i0 + q < M) ? unew : 0.0;
+            }
+        }
+    }
+}
+
+// Block max of dmax and OR of bad; the result is valid in thread 0.
+template <int T>
+__device__ __forceinline__ void block_defect(double& dmax, int& bad, double* lds) {
+    __syncthreads();
+    lds[threadIdx.x] = dmax;
+    lds[T + threadIdx.x] = bad ? 1.0 : 0.0;
+    __syncthreads();
+    for (int s = T / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + s]);
+            lds[T + threadIdx.x] = fmax(lds[T + threadIdx.x], lds[T + threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    dmax = lds[0];
+    bad = lds[T] != 0.0;
+}
+
+}  // namespace bsp

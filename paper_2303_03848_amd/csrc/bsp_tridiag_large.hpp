@@ -1,0 +1,250 @@
+// Tridiagonal block solver for large grids (M up to 16384), where the
+// per-node factorisation does not fit in registers or LDS of one compute unit.
+//
+// Same partition and truncated parallel cyclic reduction as BlockTri, with
+// three differences:
+//  * the interior LU factors and responses (l, 1/u, c/u, v, w) of every node
+//    live in a global table computed once per launch by k_large_setup and are
+//    streamed every step (coalesced: table[f][q][thread]); all systems of a
+//    launch share one table, so it stays in the L2 / infinity cache;
+//  * the explicit-operator coefficients are recomputed from j every step;
+//  * the interior solve is the unscaled LU form: forward y_q -= l_q y_{q-1},
+//    backward x_q = y_q / u_q - (c_q / u_q) x_{q+1}.
+// Per-thread interface data (PCR multipliers, interface row, stage count) is
+// a second table ptab[field][thread].
+#pragma once
+
+#include "bsp_common.hpp"
+
+namespace bsp {
+
+enum { kLgL = 0, kLgIU, kLgCU, kLgV, kLgW, kLgFields };
+// per-thread fields of ptab: aq, cq, vF, wF, invB, blo, bhi, nst, k1[16], k2[16]
+constexpr int kLgP = 8 + 32;
+
+template <int T, int MC>
+struct BlockTriG {
+    static constexpr int LOGT = ilog2(T);
+    static constexpr int NI = MC - 1;
+    static_assert(LOGT <= 16, "stage table");
+
+    const double* tab;
+    double s2, r, h, e;
+    double aq, cq, vF, wF, invB, blo, bhi;
+    int M, p, r_hi, nst;
+    bool own_lo, own_hi;
+
+    __device__ __forceinline__ double coef(int f, int q) const { return tab[((long)f * MC + q) * T + p]; }
+
+    __device__ void load(const double* tab_, const double* ptab, double s2_, double r_, double h_,
+                         double e_, int M_) {
+        tab = tab_;
+        s2 = s2_;
+        r = r_;
+        h = h_;
+        e = e_;
+        M = M_;
+        p = threadIdx.x;
+        aq = ptab[0 * T + p];
+        cq = ptab[1 * T + p];
+        vF = ptab[2 * T + p];
+        wF = ptab[3 * T + p];
+        invB = ptab[4 * T + p];
+        blo = ptab[5 * T + p];
+        bhi = ptab[6 * T + p];
+        nst = (int)ptab[7 * T + p];
+        own_lo = (p == 0);
+        own_hi = (p == (M - 1) / MC);
+        r_hi = (M - 1) % MC;
+    }
+
+    __device__ __forceinline__ void halo(const double (&V)[MC], double& hl, double& hr,
+                                         double* lds) const {
+        lds[p] = V[0];
+        lds[T + p] = V[MC - 1];
+        __syncthreads();
+        hl = (p > 0) ? lds[T + p - 1] : 0.0;
+        hr = (p + 1 < T) ? lds[p + 1] : 0.0;
+        __syncthreads();
+    }
+
+    // lds: 4*T doubles; ptab is re-read for the stage multipliers.
+    __device__ __forceinline__ void step(double (&V)[MC], double& hl, double& hr, double flo,
+                                         double fhi, double* lds, const double* ptab) const {
+        const int i0 = p * MC;
+        double d[MC];
+#pragma unroll
+        for (int q = 0; q < MC; ++q) {
+            const int g = i0 + q;
+            double al, be, ga;
+            op_row(s2, r, (double)(g + 1), al, be, ga);
+            const bool pad = g >= M;
+            const double ea = (pad || g == 0) ? 0.0 : e * al;
+            const double eb = pad ? 0.0 : 1.0 + e * be;
+            const double ec = (g >= M - 1) ? 0.0 : e * ga;
+            const double left = (q == 0) ? hl : V[q - 1];
+            const double right = (q == MC - 1) ? hr : V[q + 1];
+            d[q] = fma(ea, left, fma(eb, V[q], ec * right));
+        }
+        if (own_lo) d[0] = fma(blo, flo, d[0]);
+        if (own_hi) {
+#pragma unroll
+            for (int q = 0; q < MC; ++q)
+                if (q == r_hi) d[q] = fma(bhi, fhi, d[q]);
+        }
+#pragma unroll
+        for (int q = 1; q < NI; ++q) d[q] = fma(-coef(kLgL, q), d[q - 1], d[q]);
+        d[NI - 1] *= coef(kLgIU, NI - 1);
+#pragma unroll
+        for (int q = NI - 2; q >= 0; --q) d[q] = fma(-coef(kLgCU, q), d[q + 1], d[q] * coef(kLgIU, q));
+
+        double* ybuf = lds;
+        double* pb0 = lds + T;
+        double* pb1 = lds + 2 * T;
+        double* zbuf = lds + 3 * T;
+        ybuf[p] = d[0];
+        __syncthreads();
+        const double yF = (p + 1 < T) ? ybuf[p + 1] : 0.0;
+        double D = fma(-aq, d[NI - 1], fma(-cq, yF, d[MC - 1]));
+        for (int k = 0; k < nst; ++k) {
+            const int s = 1 << k;
+            double* buf = (k & 1) ? pb1 : pb0;
+            buf[p] = D;
+            __syncthreads();
+            const double Dm = (p - s >= 0) ? buf[p - s] : 0.0;
+            const double Dp = (p + s < T) ? buf[p + s] : 0.0;
+            D = fma(-ptab[(8 + k) * T + p], Dm, fma(-ptab[(24 + k) * T + p], Dp, D));
+        }
+        const double z = D * invB;
+        zbuf[p] = z;
+        __syncthreads();
+        const double zl = (p > 0) ? zbuf[p - 1] : 0.0;
+        const double zr = (p + 1 < T) ? zbuf[p + 1] : 0.0;
+#pragma unroll
+        for (int q = 0; q < NI; ++q) V[q] = fma(zl, coef(kLgV, q), fma(z, coef(kLgW, q), d[q]));
+        V[MC - 1] = z;
+        hl = zl;
+        hr = fma(z, vF, fma(zr, wF, yF));
+    }
+};
+
+// Builds the tables of BlockTriG<T, MC> for one (option, theta, dt): one
+// block of T threads; each thread walks its chunk sequentially in global
+// memory, then the interface system is reduced through LDS.
+template <int T, int MC>
+__global__ __launch_bounds__(T) void k_large_setup(double s2, double r, double h, int M,
+                                                   double* __restrict__ tab,
+                                                   double* __restrict__ ptab) {
+    constexpr int LOGT = ilog2(T), NI = MC - 1;
+    __shared__ double lds[3 * T];
+    const int p = threadIdx.x, i0 = p * MC;
+    auto A = [&](int g) {
+        double al, be, ga;
+        op_row(s2, r, (double)(g + 1), al, be, ga);
+        return (g >= M || g == 0) ? 0.0 : -h * al;
+    };
+    auto B = [&](int g) {
+        double al, be, ga;
+        op_row(s2, r, (double)(g + 1), al, be, ga);
+        return g >= M ? 1.0 : 1.0 - h * be;
+    };
+    auto C = [&](int g) {
+        double al, be, ga;
+        op_row(s2, r, (double)(g + 1), al, be, ga);
+        return g >= M - 1 ? 0.0 : -h * ga;
+    };
+    auto at = [&](int f, int q) -> double& { return tab[((long)f * MC + q) * T + p]; };
+    // unscaled LU of the interior rows 0..NI-1
+    double u = B(i0), iu = 1.0 / u;
+    at(kLgL, 0) = 0.0;
+    at(kLgIU, 0) = iu;
+    at(kLgCU, 0) = C(i0) * iu;
+    for (int q = 1; q < NI; ++q) {
+        const double l = A(i0 + q) * iu;
+        u = B(i0 + q) - l * C(i0 + q - 1);
+        iu = 1.0 / u;
+        at(kLgL, q) = l;
+        at(kLgIU, q) = iu;
+        at(kLgCU, q) = C(i0 + q) * iu;
+    }
+    // responses: v to -a_0 e_0, w to -c_{NI-1} e_{NI-1}
+    double t = -A(i0);
+    at(kLgV, 0) = t;
+    for (int q = 1; q < NI; ++q) {
+        t = -at(kLgL, q) * t;
+        at(kLgV, q) = t;
+    }
+    at(kLgV, NI - 1) *= at(kLgIU, NI - 1);
+    for (int q = NI - 2; q >= 0; --q)
+        at(kLgV, q) = at(kLgV, q) * at(kLgIU, q) - at(kLgCU, q) * at(kLgV, q + 1);
+    at(kLgW, NI - 1) = -C(i0 + NI - 1) * at(kLgIU, NI - 1);
+    for (int q = NI - 2; q >= 0; --q) at(kLgW, q) = -at(kLgCU, q) * at(kLgW, q + 1);
+
+    const double aq = A(i0 + MC - 1), cq = C(i0 + MC - 1), bq = B(i0 + MC - 1);
+    lds[p] = at(kLgV, 0);
+    lds[T + p] = at(kLgW, 0);
+    __syncthreads();
+    const double vF = (p + 1 < T) ? lds[p + 1] : 0.0;
+    const double wF = (p + 1 < T) ? lds[T + p + 1] : 0.0;
+    __syncthreads();
+    double Aq = aq * at(kLgV, NI - 1);
+    double Bq = bq + aq * at(kLgW, NI - 1) + cq * vF;
+    double Cq = cq * wF;
+    int nst = LOGT;
+    bool done = false;
+    for (int k = 0; k < 16; ++k) {
+        ptab[(8 + k) * T + p] = 0.0;
+        ptab[(24 + k) * T + p] = 0.0;
+    }
+    for (int k = 0; k < LOGT; ++k) {
+        const int mine = ((fabs(Aq) + fabs(Cq)) / fabs(Bq)) <= kPcrTruncationLarge;
+        const int all = __syncthreads_and(mine);
+        if (!done && all) {
+            nst = k;
+            done = true;
+        }
+        if (done) break;
+        const int s = 1 << k;
+        lds[p] = Aq;
+        lds[T + p] = Bq;
+        lds[2 * T + p] = Cq;
+        __syncthreads();
+        double Am = 0.0, Bm = 1.0, Cm = 0.0, Ap = 0.0, Bp = 1.0, Cp = 0.0;
+        if (p - s >= 0) {
+            Am = lds[p - s];
+            Bm = lds[T + p - s];
+            Cm = lds[2 * T + p - s];
+        }
+        if (p + s < T) {
+            Ap = lds[p + s];
+            Bp = lds[T + p + s];
+            Cp = lds[2 * T + p + s];
+        }
+        __syncthreads();
+        const double m1 = (p - s >= 0) ? Aq / Bm : 0.0;
+        const double m2 = (p + s < T) ? Cq / Bp : 0.0;
+        ptab[(8 + k) * T + p] = m1;
+        ptab[(24 + k) * T + p] = m2;
+        const double An = -m1 * Am, Cn = -m2 * Cp, Bn = Bq - m1 * Cm - m2 * Ap;
+        Aq = An;
+        Bq = Bn;
+        Cq = Cn;
+    }
+    double al, be, ga;
+    op_row(s2, r, 1.0, al, be, ga);
+    const double bnd_lo = al;
+    op_row(s2, r, (double)M, al, be, ga);
+    const double bnd_hi = ga;
+    const int r_hi = (M - 1) % MC;
+    ptab[0 * T + p] = aq;
+    ptab[1 * T + p] = cq;
+    ptab[2 * T + p] = vF;
+    ptab[3 * T + p] = wF;
+    ptab[4 * T + p] = 1.0 / Bq;
+    ptab[5 * T + p] = bnd_lo;   // row 0 is interior: forcing enters before the LU
+    ptab[6 * T + p] = bnd_hi;   // likewise for row M-1 (interior or interface row)
+    ptab[7 * T + p] = (double)nst;
+    (void)r_hi;
+}
+
+}  // namespace bsp

@@ -1,0 +1,133 @@
+"""Batched options on the GPU against the oracle, option by option.
+
+* A small ragged batch (grids from 1 to 2048 nodes, 1 to 12 slices, calls and
+  puts) with the numerical coarse, with and without hipGraph replay: every
+  option matches the oracle's Parareal solution to 1e-10 normwise (the
+  solution parity bar; some options are stiff, hsigma^2 M^2 ~ 400, where
+  per-step rounding is ~kappa(A) eps ~ 1e-13) with the same iteration count,
+  and the single-option GPU solve to rounding level (1e-12).
+* Network coarse (parametric 4-input network, seeded weights): after N
+  iterations every option equals the serial fine solution (finite
+  termination); with tol the iteration counts match the oracle run on the
+  oracle's own FP64 network grid (puts priced by put-call parity) within one.
+* The 512-option workload: full batch on the GPU, sampled options against
+  the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2303_03848_amd as bsp
+from oracle import mlp
+from tests.gpu_util import cuda, normwise, say, to_dev
+from workloads import OPTION_BATCH, SMALL_CALL, option_batch, option_params, perturbed, xavier_normal
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_batch():
+    base = option_params(SMALL_CALL)
+    shapes = [(1, 3, 5), (65, 4, 9), (256, 8, 16), (300, 5, 7), (513, 12, 11), (1024, 6, 20),
+              (2048, 3, 8), (128, 1, 30), (200, 10, 4), (1000, 7, 13)]
+    out = []
+    for q, (M, N, Sf) in enumerate(shapes):
+        out.append(dict(base, M=M, N=N, fine_steps=Sf, coarse_steps=1 + (q % 2),
+                        is_put=bool(q % 3 == 1), sigma=0.15 + 0.03 * q, r=0.01 * q,
+                        K=80.0 + 5 * q, s_max=3.5 * (80.0 + 5 * q)))
+    return out
+
+
+def _opt_U(U, offs, o, i):
+    return U[offs[i]: offs[i] + (o["N"] + 1) * o["M"]].reshape(o["N"] + 1, o["M"]).cpu().numpy()
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_small_batch_numeric(use_graph):
+    cuda()
+    opts = _small_batch()
+    tol = 1e-8
+    U, offs, iters, defects, rc = bsp.parareal_solve_batch(opts, bsp.COARSE_IE, tol,
+                                                           use_graph=use_graph)
+    for i, o in enumerate(opts):
+        say(f"option {i}: M={o['M']} N={o['N']} put={o['is_put']}")
+        ref = oracle.parareal(oracle.params_from(o), o["M"], o["N"], o["fine_steps"],
+                              o["coarse_steps"], oracle.COARSE_IE, tol=tol)
+        got = _opt_U(U, offs, o, i)
+        assert iters[i] == ref["iters"], (i, iters[i], ref["iters"])
+        assert normwise(got, ref["U"]) <= 1e-10, i
+        single, it1, _ = bsp.parareal_solve(o, o["M"], o["N"], o["fine_steps"], o["coarse_steps"],
+                                            bsp.COARSE_IE, tol=tol)
+        assert it1 == iters[i]
+        # separately compiled kernels may contract differently: rounding level only
+        assert normwise(single.cpu().numpy(), got) <= 1e-12, i
+
+
+def _param_net(width=32, depth=3):
+    th = perturbed(xavier_normal(4, depth, width, seed=3), 0.05, 4)
+    return th, bsp.PinnNet(to_dev(th, torch.float32), 4, depth, width, bsp.PREC_FP32)
+
+
+def _oracle_vt(th, o, width, depth):
+    po = oracle.params_from(o)
+    S = oracle.grid(po, o["M"])
+    taus = np.arange(o["N"] + 1) * (po.T / o["N"])
+    Vt = mlp.grid_values(th.astype(np.float64), 4, depth, width, po.K, taus, S, po.sigma, po.r)
+    if o["is_put"]:  # the batch's network prices calls; puts by put-call parity
+        Vt = Vt - S[None, :] + po.K * np.exp(-po.r * taus)[:, None]
+    return Vt
+
+
+@pytest.mark.parametrize("kind", [bsp.COARSE_PINN, bsp.COARSE_PINN_IE])
+def test_small_batch_network_finite_termination(kind):
+    cuda()
+    opts = _small_batch()
+    th, net = _param_net()
+    U, offs, iters, _, _ = bsp.parareal_solve_batch(opts, kind, 0.0, net=net)
+    for i, o in enumerate(opts):
+        ser = oracle.serial_fine(oracle.params_from(o), o["M"], o["N"], o["fine_steps"])
+        assert iters[i] == o["N"]
+        assert normwise(_opt_U(U, offs, o, i), ser) <= 1e-10, i
+
+
+def test_small_batch_network_iterations():
+    cuda()
+    opts = _small_batch()
+    th, net = _param_net()
+    tol = 1e-6
+    U, offs, iters, _, _ = bsp.parareal_solve_batch(opts, bsp.COARSE_PINN_IE, tol, net=net)
+    for i, o in enumerate(opts):
+        Vt = _oracle_vt(th, o, 32, 3)
+        ref = oracle.parareal(oracle.params_from(o), o["M"], o["N"], o["fine_steps"],
+                              o["coarse_steps"], oracle.COARSE_PINN_IE, Vt=Vt, tol=tol)
+        assert abs(iters[i] - ref["iters"]) <= 1, (i, iters[i], ref["iters"])
+        assert normwise(_opt_U(U, offs, o, i), ref["U"]) <= 1e-6 / max(np.abs(ref["U"]).max(), 1) + 1e-10
+
+
+@pytest.mark.parametrize("kind", [bsp.COARSE_IE, bsp.COARSE_PINN_IE])
+def test_option_batch_workload_sampled(kind):
+    """512 options (M in {256..4096}, N in 16..64, 256 CN steps/slice), one
+    batched solve; 3 options checked against the oracle."""
+    cuda()
+    cfg = OPTION_BATCH
+    opts = [dict(o, fine_steps=cfg["fine_steps"], coarse_steps=1) for o in option_batch(cfg)]
+    net = None
+    th = None
+    if kind != bsp.COARSE_IE:
+        th = perturbed(xavier_normal(4, cfg["depth"], cfg["width"], seed=5), 0.02, 6)
+        net = bsp.PinnNet(to_dev(th, torch.float32), 4, cfg["depth"], cfg["width"], bsp.PREC_BF16)
+    say(f"512-option batch, kind {kind}")
+    U, offs, iters, defects, rc = bsp.parareal_solve_batch(opts, kind, cfg["tol"], net=net)
+    say(f"iterations: min {min(iters)} max {max(iters)} mean {np.mean(iters):.2f}")
+    for i in (0, 201, 511):
+        o = opts[i]
+        po = oracle.params_from(o)
+        ser = oracle.serial_fine(po, o["M"], o["N"], o["fine_steps"])
+        got = _opt_U(U, offs, o, i)
+        # converged to tol in max norm: within a few tol of the serial fine fixed point
+        assert np.max(np.abs(got - ser)) <= 20 * cfg["tol"] + 1e-10 * np.abs(ser).max(), i
+        if kind == bsp.COARSE_IE:
+            ref = oracle.parareal(po, o["M"], o["N"], o["fine_steps"], 1, oracle.COARSE_IE,
+                                  tol=cfg["tol"], nthreads=8)
+            assert iters[i] == ref["iters"]
+            assert normwise(got, ref["U"]) <= 1e-10

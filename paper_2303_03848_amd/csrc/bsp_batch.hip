@@ -60,7 +60,7 @@ __global__ __launch_bounds__(T) void k_batch_fine(const BatchOpt* __restrict__ o
     if (it.n < k - 1) return;  // holds the serial fine solution; Fv unchanged
     const BatchOpt& b = opts[it.opt];
     const double dt = b.dT / (double)b.fine_steps;
-    BlockTri<T, MC> S;
+    Solver<T, MC> S;
     S.setup(b.o.s2, b.o.r, 0.5 * dt, 0.5 * dt, b.M, lds);
     double V[MC];
     load_chunk<T, MC>(U + b.u_off + (long)it.n * b.M, b.M, V);
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(T) void k_batch_sweep(const BatchOpt* __restrict__ 
     const BatchOpt& b = opts[oi];
     const int k = predict ? 0 : *kglob;
     const int n0 = predict ? 0 : (k - 1 < b.N - 1 ? k - 1 : b.N - 1);
-    BlockTri<T, MC> S;
+    Solver<T, MC> S;
     S.setup(b.o.s2, b.o.r, b.dT / (double)b.coarse_steps, 0.0, b.M, lds);
     double dmax = 0.0;
     int bad = 0;

@@ -2,6 +2,7 @@
 // fine F, implicit-Euler coarse G) and the serial Parareal correction sweep.
 #include "bsp_common.hpp"
 #include "bsp_steps.hpp"
+#include "bsp_tridiag_large.hpp"
 
 namespace bsp {
 
@@ -53,7 +54,7 @@ __global__ __launch_bounds__(T) void k_theta_batch(ThetaArgs a) {
     __shared__ double lds[4 * T];
     __shared__ double ftab[2 * kForceChunk];
     const int sys = blockIdx.x;
-    BlockTri<T, MC> S;
+    Solver<T, MC> S;
     S.setup(a.o.s2, a.o.r, a.theta * a.dt, (1.0 - a.theta) * a.dt, a.M, lds);
     const double tau0 =
         a.tau0 ? a.tau0[sys] : a.tau_start + (double)(sys + a.sys_offset) * a.tau_stride;
@@ -69,7 +70,7 @@ template <int T, int MC>
 __global__ __launch_bounds__(T) void k_sweep(SweepArgs a) {
     __shared__ double lds[4 * T];
     __shared__ double ftab[2 * kForceChunk];
-    BlockTri<T, MC> S;
+    Solver<T, MC> S;
     S.setup(a.o.s2, a.o.r, a.dT / (double)a.coarse_steps, 0.0, a.M, lds);
     double dmax = 0.0;
     int bad = 0;
@@ -82,6 +83,75 @@ __global__ __launch_bounds__(T) void k_sweep(SweepArgs a) {
             a.result[1] = bad ? 1.0 : 0.0;
         }
     }
+}
+
+// ------------------------------------------------------- large grids
+
+// Shapes with 16 nodes per thread use the streamed-coefficient solver.
+static bool is_large(TriShape sh) { return sh.MC == 16 && sh.T >= 512; }
+
+template <int T, int MC>
+__global__ __launch_bounds__(T) void k_large_theta(ThetaArgs a, const double* __restrict__ tab,
+                                                   const double* __restrict__ ptab) {
+    __shared__ double lds[4 * T];
+    __shared__ double ftab[2 * kForceChunk];
+    const int sys = blockIdx.x;
+    BlockTriG<T, MC> S;
+    S.load(tab, ptab, a.o.s2, a.o.r, a.theta * a.dt, (1.0 - a.theta) * a.dt, a.M);
+    const double tau0 =
+        a.tau0 ? a.tau0[sys] : a.tau_start + (double)(sys + a.sys_offset) * a.tau_stride;
+    double V[MC];
+    load_chunk<T, MC>(a.u_in + (long)sys * a.ld_in, a.M, V);
+    theta_steps<T, MC>(S, a.o, V, tau0, a.dt, a.steps, a.theta, a.homog != 0, lds, ftab);
+    store_chunk<T, MC>(a.u_out + (long)sys * a.ld_out, a.M, V);
+}
+
+template <int T, int MC>
+__global__ __launch_bounds__(T) void k_large_sweep(SweepArgs a, const double* __restrict__ tab,
+                                                   const double* __restrict__ ptab) {
+    __shared__ double lds[4 * T];
+    __shared__ double ftab[2 * kForceChunk];
+    BlockTriG<T, MC> S;
+    S.load(tab, ptab, a.o.s2, a.o.r, a.dT / (double)a.coarse_steps, 0.0, a.M);
+    double dmax = 0.0;
+    int bad = 0;
+    sweep_slices<T, MC>(S, a.o, a.M, a.N, a.n0, a.coarse_steps, a.kind, a.predict != 0, a.dT, a.U,
+                        a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad);
+    if (!a.predict) {
+        block_defect<T>(dmax, bad, lds);
+        if (threadIdx.x == 0) {
+            a.result[0] = dmax;
+            a.result[1] = bad ? 1.0 : 0.0;
+        }
+    }
+}
+
+// Coefficient tables of the large-grid solver: one slot per kernel kind
+// (0: F / G batch, 1: sweep), owned by the library for each device and kept
+// until the process ends.  Calls with M > 4096 on one device therefore must
+// not overlap in time (they are ordered on one stream in normal use).
+constexpr long kLargeTab = 5L * 16 * 1024, kLargePtab = (long)kLgP * 1024;
+static double* g_large[16] = {nullptr};
+
+static int large_tables(int slot, double** tab, double** ptab) {
+    int dev = 0;
+    BSP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 16) {
+        set_error("device index %d out of range", dev);
+        return BS_ERR_ARG;
+    }
+    if (!g_large[dev]) BSP_HIP(hipMalloc(&g_large[dev], sizeof(double) * 2 * (kLargeTab + kLargePtab)));
+    *tab = g_large[dev] + (long)slot * (kLargeTab + kLargePtab);
+    *ptab = *tab + kLargeTab;
+    return BS_OK;
+}
+
+template <int T>
+static int launch_large_setup(const OptionDev& o, int M, double h, double* tab, double* ptab,
+                              hipStream_t st) {
+    hipLaunchKernelGGL((k_large_setup<T, 16>), dim3(1), dim3(T), 0, st, o.s2, o.r, h, M, tab, ptab);
+    BSP_LAUNCHED();
+    return BS_OK;
 }
 
 // ------------------------------------------------------------ dispatch
@@ -97,6 +167,8 @@ static TriShape default_shape(int kernel, int M) {
         if (M <= 1024) return {64, 16};
         if (M <= 2048) return {256, 8};
         if (M <= 4096) return {512, 8};
+        if (M <= 8192) return {512, 16};
+        if (M <= 16384) return {1024, 16};
     } else {
         if (M <= 128) return {64, 2};
         if (M <= 256) return {64, 4};
@@ -104,6 +176,8 @@ static TriShape default_shape(int kernel, int M) {
         if (M <= 1024) return {256, 4};
         if (M <= 2048) return {256, 8};
         if (M <= 4096) return {512, 8};
+        if (M <= 8192) return {512, 16};
+        if (M <= 16384) return {1024, 16};
     }
     return {0, 0};
 }
@@ -158,6 +232,20 @@ int launch_theta_batch(const OptionDev& o, int M, int nsys, const double* tau0, 
     const TriShape sh = shape_for(0, M);
     ThetaArgs a{o, M, steps, homog, sys_offset, tau0, tau_start, tau_stride, dt, theta, u_in, ld_in,
                 u_out, ld_out};
+    if (is_large(sh)) {
+        double *tab, *ptab;
+        int rc = large_tables(0, &tab, &ptab);
+        if (rc) return rc;
+        if (sh.T == 512) {
+            if ((rc = launch_large_setup<512>(o, M, theta * dt, tab, ptab, stream))) return rc;
+            hipLaunchKernelGGL((k_large_theta<512, 16>), dim3(nsys), dim3(512), 0, stream, a, tab, ptab);
+        } else {
+            if ((rc = launch_large_setup<1024>(o, M, theta * dt, tab, ptab, stream))) return rc;
+            hipLaunchKernelGGL((k_large_theta<1024, 16>), dim3(nsys), dim3(1024), 0, stream, a, tab, ptab);
+        }
+        BSP_LAUNCHED();
+        return BS_OK;
+    }
 #define BSP_CASE(T_, MC_)                                                                   \
     if (sh.T == T_ && sh.MC == MC_) {                                                       \
         hipLaunchKernelGGL((k_theta_batch<T_, MC_>), dim3(nsys), dim3(T_), 0, stream, a);   \
@@ -172,6 +260,21 @@ int launch_theta_batch(const OptionDev& o, int M, int nsys, const double* tau0, 
 
 int launch_sweep(const SweepArgs& a, hipStream_t stream) {
     const TriShape sh = shape_for(1, a.M);
+    if (is_large(sh)) {
+        double *tab, *ptab;
+        int rc = large_tables(1, &tab, &ptab);
+        if (rc) return rc;
+        const double h = a.dT / (double)a.coarse_steps;
+        if (sh.T == 512) {
+            if ((rc = launch_large_setup<512>(a.o, a.M, h, tab, ptab, stream))) return rc;
+            hipLaunchKernelGGL((k_large_sweep<512, 16>), dim3(1), dim3(512), 0, stream, a, tab, ptab);
+        } else {
+            if ((rc = launch_large_setup<1024>(a.o, a.M, h, tab, ptab, stream))) return rc;
+            hipLaunchKernelGGL((k_large_sweep<1024, 16>), dim3(1), dim3(1024), 0, stream, a, tab, ptab);
+        }
+        BSP_LAUNCHED();
+        return BS_OK;
+    }
 #define BSP_CASE(T_, MC_)                                                        \
     if (sh.T == T_ && sh.MC == MC_) {                                            \
         hipLaunchKernelGGL((k_sweep<T_, MC_>), dim3(1), dim3(T_), 0, stream, a); \

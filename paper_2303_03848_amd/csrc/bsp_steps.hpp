@@ -4,8 +4,22 @@
 
 #include "bsp_common.hpp"
 #include "bsp_tridiag.hpp"
+#include "bsp_tridiag_hier.hpp"
 
 namespace bsp {
+
+// Solver of a block shape: one wavefront -> BlockTri (lane exchanges only);
+// several wavefronts -> BlockTriH (one block barrier per step).
+template <int T, int MC>
+struct SolverSel {
+    using type = BlockTriH<T / 64, MC>;
+};
+template <int MC>
+struct SolverSel<64, MC> {
+    using type = BlockTri<64, MC>;
+};
+template <int T, int MC>
+using Solver = typename SolverSel<T, MC>::type;
 
 // Block shapes (threads, nodes per thread) the tridiagonal kernels are built for.
 #define BSP_TRI_SHAPES(X) \
@@ -34,8 +48,8 @@ constexpr int kForceChunk = 1024;
 // at S = 0 and S = S_max, is tabulated in LDS for a chunk of steps by all
 // threads in parallel, so the sequential step loop evaluates no exponential.
 // ftab: 2 * kForceChunk doubles of LDS.
-template <int T, int MC>
-__device__ __forceinline__ void theta_steps(const BlockTri<T, MC>& S, const OptionDev& o,
+template <int T, int MC, class Solver>
+__device__ __forceinline__ void theta_steps(const Solver& S, const OptionDev& o,
                                             double (&V)[MC], double tau0, double dt, int steps,
                                             double theta, bool homog, double* lds, double* ftab) {
     double hl, hr;
@@ -73,9 +87,10 @@ __device__ __forceinline__ void theta_steps(const BlockTri<T, MC>& S, const Opti
 //   predict: U[n+1] = g, Gold[n] = g
 //   else:    U[n+1] = Fv[n] + (g - Gold[n]), Gold[n] = g,
 //            dmax = max |U_new[n+1] - U_old[n+1]|, bad |= non-finite.
-// S must be set up for implicit Euler with dt = dT / coarse_steps.
-template <int T, int MC>
-__device__ __forceinline__ void sweep_slices(const BlockTri<T, MC>& S, const OptionDev& o, int M,
+// S (BlockTri or BlockTriG) must be set up for implicit Euler with
+// dt = dT / coarse_steps.
+template <int T, int MC, class Solver>
+__device__ __forceinline__ void sweep_slices(const Solver& S, const OptionDev& o, int M,
                                              int N, int n0, int coarse_steps, int kind, bool predict,
                                              double dT, double* __restrict__ U,
                                              const double* __restrict__ Fv,
@@ -94,14 +109,16 @@ __device__ __forceinline__ void sweep_slices(const BlockTri<T, MC>& S, const Opt
         // latency overlaps it (when registers allow: small chunks).
         constexpr bool kPrefetch = MC <= 4;
         double fv[MC], gold[MC], uold[MC], vt0[MC], vt1[MC];
-        if (kPrefetch && !predict) {
-            load_chunk<T, MC>(Fv + (long)n * M, M, fv);
-            load_chunk<T, MC>(go, M, gold);
-            load_chunk<T, MC>(un1, M, uold);
-        }
-        if (kPrefetch && net) {
-            load_chunk<T, MC>(Vt + (long)(n + 1) * M, M, vt1);
-            if (kind == BS_COARSE_PINN_IE) load_chunk<T, MC>(Vt + (long)n * M, M, vt0);
+        if constexpr (kPrefetch) {
+            if (!predict) {
+                load_chunk<T, MC>(Fv + (long)n * M, M, fv);
+                load_chunk<T, MC>(go, M, gold);
+                load_chunk<T, MC>(un1, M, uold);
+            }
+            if (net) {
+                load_chunk<T, MC>(Vt + (long)(n + 1) * M, M, vt1);
+                if (kind == BS_COARSE_PINN_IE) load_chunk<T, MC>(Vt + (long)n * M, M, vt0);
+            }
         }
         double g[MC];
         if (kind == BS_COARSE_IE) {
@@ -109,22 +126,20 @@ __device__ __forceinline__ void sweep_slices(const BlockTri<T, MC>& S, const Opt
             for (int q = 0; q < MC; ++q) g[q] = V[q];
             theta_steps<T, MC>(S, o, g, (double)n * dT, dtc, coarse_steps, 1.0, false, lds, ftab);
         } else if (kind == BS_COARSE_PINN) {
-            if (!kPrefetch) load_chunk<T, MC>(Vt + (long)(n + 1) * M, M, vt1);
+            const double* vn1 = Vt + (long)(n + 1) * M;
 #pragma unroll
-            for (int q = 0; q < MC; ++q) g[q] = vt1[q];
+            for (int q = 0; q < MC; ++q)
+                g[q] = kPrefetch ? vt1[q] : ((i0 + q < M) ? vn1[i0 + q] : 0.0);
         } else {
-            if (!kPrefetch) load_chunk<T, MC>(Vt + (long)n * M, M, vt0);
+            const double* vn0 = Vt + (long)n * M;
+            const double* vn1 = Vt + (long)(n + 1) * M;
 #pragma unroll
-            for (int q = 0; q < MC; ++q) g[q] = V[q] - vt0[q];
+            for (int q = 0; q < MC; ++q)
+                g[q] = V[q] - (kPrefetch ? vt0[q] : ((i0 + q < M) ? vn0[i0 + q] : 0.0));
             theta_steps<T, MC>(S, o, g, (double)n * dT, dtc, coarse_steps, 1.0, true, lds, ftab);
-            if (!kPrefetch) load_chunk<T, MC>(Vt + (long)(n + 1) * M, M, vt1);
 #pragma unroll
-            for (int q = 0; q < MC; ++q) g[q] = vt1[q] + g[q];
-        }
-        if (!kPrefetch && !predict) {
-            load_chunk<T, MC>(Fv + (long)n * M, M, fv);
-            load_chunk<T, MC>(go, M, gold);
-            load_chunk<T, MC>(un1, M, uold);
+            for (int q = 0; q < MC; ++q)
+                g[q] = (kPrefetch ? vt1[q] : ((i0 + q < M) ? vn1[i0 + q] : 0.0)) + g[q];
         }
         if (predict) {
             store_chunk<T, MC>(un1, M, g);
@@ -132,16 +147,22 @@ __device__ __forceinline__ void sweep_slices(const BlockTri<T, MC>& S, const Opt
 #pragma unroll
             for (int q = 0; q < MC; ++q) V[q] = g[q];
         } else {
+            const double* fvn = Fv + (long)n * M;
 #pragma unroll
             for (int q = 0; q < MC; ++q) {
-                const double unew = fv[q] + (g[q] - gold[q]);
                 if (i0 + q < M) {
+                    const double f = kPrefetch ? fv[q] : fvn[i0 + q];
+                    const double gl = kPrefetch ? gold[q] : go[i0 + q];
+                    const double uo = kPrefetch ? uold[q] : un1[i0 + q];
+                    const double unew = f + (g[q] - gl);
                     go[i0 + q] = g[q];
                     un1[i0 + q] = unew;
-                    dmax = fmax(dmax, fabs(unew - uold[q]));
+                    dmax = fmax(dmax, fabs(unew - uo));
                     bad |= !isfinite(unew);
+                    V[q] = unew;
+                } else {
+                    V[q] = 0.0;
                 }
-                V[q] = (i0 + q < M) ? unew : 0.0;
             }
         }
     }

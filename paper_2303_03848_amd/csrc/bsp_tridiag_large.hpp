@@ -18,6 +18,8 @@
 
 namespace bsp {
 
+constexpr double kPcrTruncationLarge = 8.673617379884035e-19;  // 2^-60
+
 enum { kLgL = 0, kLgIU, kLgCU, kLgV, kLgW, kLgFields };
 // per-thread fields of ptab: aq, cq, vF, wF, invB, blo, bhi, nst, k1[16], k2[16]
 constexpr int kLgP = 8 + 32;
@@ -29,16 +31,20 @@ struct BlockTriG {
     static_assert(LOGT <= 16, "stage table");
 
     const double* tab;
+    const double* ptab;
     double s2, r, h, e;
     double aq, cq, vF, wF, invB, blo, bhi;
     int M, p, r_hi, nst;
     bool own_lo, own_hi;
 
-    __device__ __forceinline__ double coef(int f, int q) const { return tab[((long)f * MC + q) * T + p]; }
+    __device__ __forceinline__ double coef(const double* tb, int f, int q) const {
+        return tb[((long)f * MC + q) * T + p];
+    }
 
-    __device__ void load(const double* tab_, const double* ptab, double s2_, double r_, double h_,
+    __device__ void load(const double* tab_, const double* ptab_, double s2_, double r_, double h_,
                          double e_, int M_) {
         tab = tab_;
+        ptab = ptab_;
         s2 = s2_;
         r = r_;
         h = h_;
@@ -68,20 +74,27 @@ struct BlockTriG {
         __syncthreads();
     }
 
-    // lds: 4*T doubles; ptab is re-read for the stage multipliers.
+    // lds: 4*T doubles; the stage multipliers are re-read from ptab.
     __device__ __forceinline__ void step(double (&V)[MC], double& hl, double& hr, double flo,
-                                         double fhi, double* lds, const double* ptab) const {
+                                         double fhi, double* lds) const {
         const int i0 = p * MC;
+        // Opaque per step: the compiler must neither hoist the table loads
+        // nor keep the recomputed coefficients across steps (that is the
+        // register footprint this solver exists to avoid).
+        const double* tb = tab;
+        const double* pt = ptab;
+        double ee = e, ss2 = s2, rr = r;
+        asm volatile("" : "+v"(tb), "+v"(pt), "+v"(ee), "+v"(ss2), "+v"(rr));
         double d[MC];
 #pragma unroll
         for (int q = 0; q < MC; ++q) {
             const int g = i0 + q;
             double al, be, ga;
-            op_row(s2, r, (double)(g + 1), al, be, ga);
+            op_row(ss2, rr, (double)(g + 1), al, be, ga);
             const bool pad = g >= M;
-            const double ea = (pad || g == 0) ? 0.0 : e * al;
-            const double eb = pad ? 0.0 : 1.0 + e * be;
-            const double ec = (g >= M - 1) ? 0.0 : e * ga;
+            const double ea = (pad || g == 0) ? 0.0 : ee * al;
+            const double eb = pad ? 0.0 : 1.0 + ee * be;
+            const double ec = (g >= M - 1) ? 0.0 : ee * ga;
             const double left = (q == 0) ? hl : V[q - 1];
             const double right = (q == MC - 1) ? hr : V[q + 1];
             d[q] = fma(ea, left, fma(eb, V[q], ec * right));
@@ -93,10 +106,11 @@ struct BlockTriG {
                 if (q == r_hi) d[q] = fma(bhi, fhi, d[q]);
         }
 #pragma unroll
-        for (int q = 1; q < NI; ++q) d[q] = fma(-coef(kLgL, q), d[q - 1], d[q]);
-        d[NI - 1] *= coef(kLgIU, NI - 1);
+        for (int q = 1; q < NI; ++q) d[q] = fma(-coef(tb, kLgL, q), d[q - 1], d[q]);
+        d[NI - 1] *= coef(tb, kLgIU, NI - 1);
 #pragma unroll
-        for (int q = NI - 2; q >= 0; --q) d[q] = fma(-coef(kLgCU, q), d[q + 1], d[q] * coef(kLgIU, q));
+        for (int q = NI - 2; q >= 0; --q)
+            d[q] = fma(-coef(tb, kLgCU, q), d[q + 1], d[q] * coef(tb, kLgIU, q));
 
         double* ybuf = lds;
         double* pb0 = lds + T;
@@ -113,7 +127,7 @@ struct BlockTriG {
             __syncthreads();
             const double Dm = (p - s >= 0) ? buf[p - s] : 0.0;
             const double Dp = (p + s < T) ? buf[p + s] : 0.0;
-            D = fma(-ptab[(8 + k) * T + p], Dm, fma(-ptab[(24 + k) * T + p], Dp, D));
+            D = fma(-pt[(8 + k) * T + p], Dm, fma(-pt[(24 + k) * T + p], Dp, D));
         }
         const double z = D * invB;
         zbuf[p] = z;
@@ -121,7 +135,7 @@ struct BlockTriG {
         const double zl = (p > 0) ? zbuf[p - 1] : 0.0;
         const double zr = (p + 1 < T) ? zbuf[p + 1] : 0.0;
 #pragma unroll
-        for (int q = 0; q < NI; ++q) V[q] = fma(zl, coef(kLgV, q), fma(z, coef(kLgW, q), d[q]));
+        for (int q = 0; q < NI; ++q) V[q] = fma(zl, coef(tb, kLgV, q), fma(z, coef(tb, kLgW, q), d[q]));
         V[MC - 1] = z;
         hl = zl;
         hr = fma(z, vF, fma(zr, wF, yF));

@@ -129,3 +129,44 @@ def test_network_coarse_full_size_converges_to_fine():
     say(f"gpu iters {iters} oracle iters {ref['iters']}")
     assert abs(iters - ref["iters"]) <= 1
     assert normwise(U.cpu().numpy(), ref["U"]) <= 1e-10
+
+
+def test_large_grid_iterates():
+    """A grid beyond 4096 nodes (streamed-coefficient solver) through every
+    Parareal iterate against the oracle."""
+    cuda()
+    cfg = dict(SMALL_CALL, M=9000, N=4, fine_steps=6, is_put=True)
+    M, N, Sf = cfg["M"], cfg["N"], cfg["fine_steps"]
+    ref = oracle.parareal(_oracle_params(cfg), M, N, Sf, 1, oracle.COARSE_IE, tol=0.0,
+                          keep_iterates=True)
+    pr = bsp.Parareal(option_params(cfg), M, N, Sf, 1, bsp.COARSE_IE)
+    assert normwise(pr.start().cpu().numpy(), ref["iterates"][0]) <= 1e-11
+    for k in range(1, N + 1):
+        pr.iterate(k)
+        assert normwise(pr.U.cpu().numpy(), ref["iterates"][k]) <= 1e-11, k
+
+
+def test_large_put_workload_sampled():
+    """The large put (M = 16384, N = 256 slices, 2048 CN steps per slice,
+    256 x 6 BF16 network coarse, tol 1e-10) at full size: the converged
+    iterate satisfies the fine fixed point U_{n+1} = F(U_n) on sampled slices
+    (oracle F), and U_0 is the oracle payoff."""
+    from workloads import LARGE_PUT
+    cuda()
+    cfg = LARGE_PUT
+    M, N, Sf = cfg["M"], cfg["N"], cfg["fine_steps"]
+    th = perturbed(xavier_normal(2, cfg["depth"], cfg["width"], seed=7), 0.02, 8)
+    net = bsp.PinnNet(to_dev(th, torch.float32), 2, cfg["depth"], cfg["width"], bsp.PREC_BF16)
+    say("large put: M=16384 N=256 Sf=2048")
+    U, iters, defects = bsp.parareal_solve(option_params(cfg), M, N, Sf, 1, bsp.COARSE_PINN_IE,
+                                           tol=cfg["tol"], net=net)
+    say(f"large put: {iters} iterations, last defect {defects[-1]:.2e}")
+    U = U.cpu().numpy()
+    po = _oracle_params(cfg)
+    assert np.array_equal(U[0], oracle.initial(po, M))
+    dT = po.T / N
+    scale = np.abs(U).max()
+    for n in (0, 137, N - 1):
+        Fn = oracle.fine(po, M, n * dT, dT, Sf, U[n])
+        # at convergence the iterate is the fine fixed point up to the stopping tolerance
+        assert np.max(np.abs(U[n + 1] - Fn)) <= 100 * cfg["tol"] + 1e-10 * scale, n

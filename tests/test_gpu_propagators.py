@@ -6,7 +6,15 @@ contraction) than the oracle's textbook Thomas algorithm.  Both are backward
 stable on these strictly diagonally dominant matrices and the propagators
 are contractive, so each step adds O(eps) relative error; over at most a few
 thousand steps the normwise difference stays below steps * 16 * eps, which
-is under 1e-11 for every case here.  The payoff is a few operations: 1e-15.
+is under 1e-11 for the grids up to 4096 nodes here.  On finer grids the
+step's conditioning takes over: the explicit half (I + (1-theta) dt L) has
+norm up to 1 + (1-theta) dt max|beta_j|, and the implicit matrix
+I - theta dt L has condition number up to 1 + theta dt max|beta_j|, with
+max|beta_j| ~ sigma^2 M^2 (dt sigma^2 M^2 is about 5e4 for M = 8192 here).
+Either amplifies a rounding error of one step in the smooth modes, which
+the step does not damp, so the bound per step is
+16 * eps * (1 + dt sigma^2 M^2) (large_tol).
+The payoff is a few operations: 1e-15.
 """
 import numpy as np
 import pytest
@@ -105,3 +113,27 @@ def test_argument_errors(bad):
                                      None)
     assert rc == bsp.BS_ERR_ARG
     assert len(lib.bs_last_error()) > 0
+
+
+LARGE = [4097, 6000, 8192, 8193, 12001, 16384]
+
+
+def large_tol(p, M, dt, steps):
+    """Normwise bound for `steps` theta-steps of size dt on M nodes."""
+    amp = 1.0 + dt * (p["sigma"] * M) ** 2
+    return max(1e-11, 16 * np.finfo(np.float64).eps * steps * amp)
+
+
+@pytest.mark.parametrize("M", LARGE)
+def test_fine_batch_large_grid(M):
+    """Grids beyond 4096 nodes use the streamed-coefficient solver."""
+    cuda()
+    _check_batch(bsp.bs_fine_propagate_batch, oracle.fine, CALL, M, 5,
+                 large_tol(CALL, M, 0.1 / 5, 5))
+
+
+@pytest.mark.parametrize("M", LARGE)
+def test_coarse_batch_large_grid(M):
+    cuda()
+    _check_batch(bsp.bs_coarse_numeric, oracle.coarse_ie, PUT, M, 2,
+                 large_tol(PUT, M, 0.1 / 2, 2))

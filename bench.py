@@ -44,6 +44,38 @@ def cpu_cores() -> int:
         return os.cpu_count() or 1
 
 
+# Sources of the F kernel; a traffic figure taken from counters is reported
+# only while they are unchanged since the counters were taken.
+F_KERNEL_SOURCES = ["bsp_propagate.hip", "bsp_steps.hpp", "bsp_tridiag.hpp",
+                    "bsp_tridiag_hier.hpp", "bsp_tridiag_large.hpp", "bsp_common.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_theta_batch_pinn_call_M1024_N32_traffic.json")
+
+
+def f_kernel_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in F_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2303_03848_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(shapes, M):
+    """HBM bytes per F system from the committed counter summary, if it was
+    taken on the current F sources with the block shape in use."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != f_kernel_hash() or t.get("M") != M:
+        return None
+    if shapes is None or list(shapes.get("fine") or []) != t.get("fine_shape"):
+        return None
+    return {"bytes_per_system": t["hbm_bytes_per_system"],
+            "source": os.path.relpath(TRAFFIC_FILE, ROOT)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +87,13 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison solves")
+    ap.add_argument("--fine-shape", type=int, nargs=2, metavar=("T", "MC"),
+                    help="pin the F block shape (threads, nodes per thread) instead of tuning")
+    ap.add_argument("--sweep-shape", type=int, nargs=2, metavar=("T", "MC"),
+                    help="pin the sweep block shape instead of tuning")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one plain elementwise copy of MIB MiB (float64) so a "
+                         "counter profile of this command has a copy kernel of known size")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -72,9 +111,26 @@ def main():
     dev = torch.device("cuda:0")
     log(f"[bench] device {torch.cuda.get_device_name(dev)}; workload {cfg['name']}")
 
-    if not args.no_autotune:
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.rand(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)  # reads 8n bytes, writes 8n bytes
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {n} doubles ({8 * n} bytes read, {8 * n} written)")
+        del src, dst
+
+    shapes = None
+    if args.fine_shape or args.sweep_shape:
+        if args.fine_shape:
+            bsp.bs_tune_set_shape(0, M, M, *args.fine_shape)
+        if args.sweep_shape:
+            bsp.bs_tune_set_shape(1, M, M, *args.sweep_shape)
+        shapes = {"fine": args.fine_shape, "sweep": args.sweep_shape, "source": "pinned"}
+    elif not args.no_autotune:
         from paper_2303_03848_amd import autotune
         ent = autotune.tune_workload(cfg["name"], p, M, N, Sf, use_cache=False)
+        shapes = {"fine": list(ent["fine"]), "sweep": list(ent["sweep"]), "source": "autotuned"}
         log(f"[bench] autotuned block shapes: fine {ent['fine']} sweep {ent['sweep']}")
 
     net = None
@@ -114,6 +170,11 @@ def main():
     value = cells / (ms_per_step / 1e3)
     f_ms = prof["fine_ms"] / max(prof["fine_launches"], 1)
     achieved = prof["fine_cells"] * FLOPS_PER_CELL / (prof["fine_ms"] / 1e3) / 1e12
+    # algorithmic HBM bytes of one F launch: each system reads its slice state
+    # and writes F of it, M doubles each way
+    sys_per_launch = prof["fine_cells"] / (M * Sf) / max(prof["fine_launches"], 1)
+    alg_bytes = 16.0 * M * sys_per_launch
+    traffic = measured_traffic(shapes, M)
     sweep_ms = prof["sweep_ms"] / max(prof["sweep_launches"], 1)
 
     out = {
@@ -131,9 +192,14 @@ def main():
         "time_to_solution_ms": ms_per_step,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "k_theta_batch (Crank-Nicolson F)",
+                     "traffic": (None if traffic is None
+                                 else traffic["bytes_per_system"] * sys_per_launch),
+                     "kernel": "k_theta_batch (Crank-Nicolson F)",
                      "avg_launch_ms": f_ms, "launches_per_step": prof["fine_launches"] / args.steps,
-                     "flops_per_cell": FLOPS_PER_CELL},
+                     "systems_per_launch": sys_per_launch, "flops_per_cell": FLOPS_PER_CELL,
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "traffic_source": None if traffic is None else traffic["source"]},
+        "block_shapes": shapes,
         "sweep_avg_launch_ms": sweep_ms,
     }
     if train_info is not None:
@@ -183,17 +249,25 @@ def main():
         import oracle
         threads = min(N, cpu_cores())
         po = oracle.params_from(p)
-        t0 = time.perf_counter()
-        r = oracle.parareal(po, M, N, Sf, 1, oracle.COARSE_IE, tol=tol, nthreads=threads)
-        dt = time.perf_counter() - t0
+        # whole oracle solves, repeated until about 10 s of CPU time (at most 30 s)
+        reps, t_all = 0, 0.0
+        while t_all < 10.0 and reps < 200:
+            t0 = time.perf_counter()
+            r = oracle.parareal(po, M, N, Sf, 1, oracle.COARSE_IE, tol=tol, nthreads=threads)
+            t_all += time.perf_counter() - t0
+            reps += 1
+            if t_all > 30.0:
+                break
+        dt = t_all / reps
         ora_cells = r["iters"] * N * Sf * M
         out["cpu_baseline"] = {
             "value": ora_cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": (f"one oracle Parareal solve, numerical coarse, on the full {cfg['name']} "
-                       f"grid ({r['iters']} iterations, F over slices on {threads} threads): "
-                       f"{dt:.2f} s"),
+            "sample": (f"{reps} oracle Parareal solves, numerical coarse, on the full "
+                       f"{cfg['name']} grid ({r['iters']} iterations each, F over slices on "
+                       f"{threads} threads): {t_all:.2f} s in all, {dt * 1e3:.1f} ms each"),
             "time_to_solution_ms": 1e3 * dt}
-        log(f"[bench] cpu oracle: {dt:.2f}s, {r['iters']} iters, {threads} threads")
+        log(f"[bench] cpu oracle: {reps} solves in {t_all:.2f}s, {r['iters']} iters, "
+            f"{threads} threads")
 
     print(json.dumps(out), flush=True)
 

@@ -195,7 +195,8 @@ size_t parareal_batch_workspace_size(int n_opt, const bs_params* prm, const bs_g
  * skipped on the device, so with use_graph != 0 one iteration is captured
  * once as a hipGraph and replayed.  Stopping rule per option as in
  * parareal_solve (defect <= tol, k == N, or k == max_iter).
- * prm, grids, sl: host arrays [n_opt]; all options share payoff_mode.
+ * prm, grids, sl: host arrays [n_opt]; all options share payoff_mode; each
+ *    grid has 1 <= M <= 4096 nodes (BS_ERR_ARG otherwise).
  * U: device FP64; option o's state [N_o+1][M_o] starts at element offsets[o]
  *    (host array); regions must not overlap.
  * Network kinds: the network is evaluated on every option's grid with inputs

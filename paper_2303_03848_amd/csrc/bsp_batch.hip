@@ -18,6 +18,10 @@
 
 namespace bsp {
 
+// Largest grid of a batched option: the batch kernels keep the whole
+// factorisation in registers (no streamed-coefficient variant).
+constexpr int kMaxBatchM = 4096;
+
 struct FItem {
     int opt, n;
 };
@@ -52,20 +56,22 @@ __global__ __launch_bounds__(T) void k_batch_fine(const BatchOpt* __restrict__ o
                                                   const int* __restrict__ kglob,
                                                   const double* __restrict__ U,
                                                   double* __restrict__ Fv) {
-    __shared__ double lds[4 * T];
-    __shared__ double ftab[2 * kForceChunk];
+    __shared__ double smem[smem_doubles<T>()];
+    double* lds = smem;
+    double* ftab = smem + 4 * T;
     const FItem it = items[blockIdx.x];
     if (state[it.opt].done) return;
     const int k = *kglob;
     if (it.n < k - 1) return;  // holds the serial fine solution; Fv unchanged
     const BatchOpt& b = opts[it.opt];
     const double dt = b.dT / (double)b.fine_steps;
+    double V[MC];
+    load_system<T, MC>(U + b.u_off + (long)it.n * b.M, b.M, V, smem);
     Solver<T, MC> S;
     S.setup(b.o.s2, b.o.r, 0.5 * dt, 0.5 * dt, b.M, lds);
-    double V[MC];
-    load_chunk<T, MC>(U + b.u_off + (long)it.n * b.M, b.M, V);
-    theta_steps<T, MC>(S, b.o, V, (double)it.n * b.dT, dt, b.fine_steps, 0.5, false, lds, ftab);
-    store_chunk<T, MC>(Fv + b.w_off + (long)it.n * b.M, b.M, V);
+    theta_steps<T, MC, true>(S, b.o, V, (double)it.n * b.dT, dt, b.fine_steps, 0.5, false, lds,
+                             ftab);
+    store_system<T, MC>(Fv + b.w_off + (long)it.n * b.M, b.M, V, smem);
 }
 
 // Serial sweep of every unconverged option of one class; decides convergence.
@@ -179,8 +185,8 @@ static int make_plan(int n_opt, const bs_params* prm, const bs_grid* grids, cons
         BSP_CHECK_ARG(p.K > 0 && p.sigma > 0 && p.r >= 0 && p.T > 0 && p.s_max > 0,
                       "option %d: parameters out of range", i);
         const int M = grids[i].M, N = sl[i].N;
-        BSP_CHECK_ARG(M >= 1 && M <= kMaxM && tri_shape(M).T > 0, "option %d: M = %d unsupported",
-                      i, M);
+        BSP_CHECK_ARG(M >= 1 && M <= kMaxBatchM && tri_shape(M).T > 0,
+                      "option %d: M = %d outside 1..%d", i, M, kMaxBatchM);
         BSP_CHECK_ARG(N >= 1 && sl[i].fine_steps >= 1 && sl[i].coarse_steps >= 1,
                       "option %d: slices out of range", i);
         BSP_CHECK_ARG(grids[i].payoff_mode == grids[0].payoff_mode,

@@ -51,17 +51,21 @@ struct ThetaArgs {
 
 template <int T, int MC>
 __global__ __launch_bounds__(T) void k_theta_batch(ThetaArgs a) {
-    __shared__ double lds[4 * T];
-    __shared__ double ftab[2 * kForceChunk];
+    __shared__ double smem[smem_doubles<T>()];
+    double* lds = smem;
+    double* ftab = smem + 4 * T;
     const int sys = blockIdx.x;
+    double V[MC];
+    load_system<T, MC>(a.u_in + (long)sys * a.ld_in, a.M, V, smem);
     Solver<T, MC> S;
     S.setup(a.o.s2, a.o.r, a.theta * a.dt, (1.0 - a.theta) * a.dt, a.M, lds);
     const double tau0 =
         a.tau0 ? a.tau0[sys] : a.tau_start + (double)(sys + a.sys_offset) * a.tau_stride;
-    double V[MC];
-    load_chunk<T, MC>(a.u_in + (long)sys * a.ld_in, a.M, V);
-    theta_steps<T, MC>(S, a.o, V, tau0, a.dt, a.steps, a.theta, a.homog != 0, lds, ftab);
-    store_chunk<T, MC>(a.u_out + (long)sys * a.ld_out, a.M, V);
+    if (a.theta == 1.0)
+        theta_steps<T, MC, false>(S, a.o, V, tau0, a.dt, a.steps, 1.0, a.homog != 0, lds, ftab);
+    else
+        theta_steps<T, MC, true>(S, a.o, V, tau0, a.dt, a.steps, a.theta, a.homog != 0, lds, ftab);
+    store_system<T, MC>(a.u_out + (long)sys * a.ld_out, a.M, V, smem);
 }
 
 // ---------------------------------------------------- Parareal sweep
@@ -87,8 +91,9 @@ __global__ __launch_bounds__(T) void k_sweep(SweepArgs a) {
 
 // ------------------------------------------------------- large grids
 
-// Shapes with 16 nodes per thread use the streamed-coefficient solver.
-static bool is_large(TriShape sh) { return sh.MC == 16 && sh.T >= 512; }
+// 512-thread shapes with 16 or 32 nodes per thread (grids beyond 4096 nodes)
+// use the streamed-coefficient solver.
+static bool is_large(TriShape sh) { return sh.T == 512 && sh.MC >= 16; }
 
 template <int T, int MC>
 __global__ __launch_bounds__(T) void k_large_theta(ThetaArgs a, const double* __restrict__ tab,
@@ -102,7 +107,10 @@ __global__ __launch_bounds__(T) void k_large_theta(ThetaArgs a, const double* __
         a.tau0 ? a.tau0[sys] : a.tau_start + (double)(sys + a.sys_offset) * a.tau_stride;
     double V[MC];
     load_chunk<T, MC>(a.u_in + (long)sys * a.ld_in, a.M, V);
-    theta_steps<T, MC>(S, a.o, V, tau0, a.dt, a.steps, a.theta, a.homog != 0, lds, ftab);
+    if (a.theta == 1.0)
+        theta_steps<T, MC, false>(S, a.o, V, tau0, a.dt, a.steps, 1.0, a.homog != 0, lds, ftab);
+    else
+        theta_steps<T, MC, true>(S, a.o, V, tau0, a.dt, a.steps, a.theta, a.homog != 0, lds, ftab);
     store_chunk<T, MC>(a.u_out + (long)sys * a.ld_out, a.M, V);
 }
 
@@ -130,7 +138,7 @@ __global__ __launch_bounds__(T) void k_large_sweep(SweepArgs a, const double* __
 // (0: F / G batch, 1: sweep), owned by the library for each device and kept
 // until the process ends.  Calls with M > 4096 on one device therefore must
 // not overlap in time (they are ordered on one stream in normal use).
-constexpr long kLargeTab = 5L * 16 * 1024, kLargePtab = (long)kLgP * 1024;
+constexpr long kLargeTab = 5L * 32 * 512, kLargePtab = (long)kLgP * 512;
 static double* g_large[16] = {nullptr};
 
 static int large_tables(int slot, double** tab, double** ptab) {
@@ -146,10 +154,11 @@ static int large_tables(int slot, double** tab, double** ptab) {
     return BS_OK;
 }
 
-template <int T>
-static int launch_large_setup(const OptionDev& o, int M, double h, double* tab, double* ptab,
-                              hipStream_t st) {
-    hipLaunchKernelGGL((k_large_setup<T, 16>), dim3(1), dim3(T), 0, st, o.s2, o.r, h, M, tab, ptab);
+template <int T, int MC>
+static int launch_large_setup(const OptionDev& o, int M, double h, double e, double* tab,
+                              double* ptab, hipStream_t st) {
+    hipLaunchKernelGGL((k_large_setup<T, MC>), dim3(1), dim3(T), 0, st, o.s2, o.r, h, e, M, tab,
+                       ptab);
     BSP_LAUNCHED();
     return BS_OK;
 }
@@ -168,7 +177,7 @@ static TriShape default_shape(int kernel, int M) {
         if (M <= 2048) return {256, 8};
         if (M <= 4096) return {512, 8};
         if (M <= 8192) return {512, 16};
-        if (M <= 16384) return {1024, 16};
+        if (M <= 16384) return {512, 32};
     } else {
         if (M <= 128) return {64, 2};
         if (M <= 256) return {64, 4};
@@ -177,7 +186,7 @@ static TriShape default_shape(int kernel, int M) {
         if (M <= 2048) return {256, 8};
         if (M <= 4096) return {512, 8};
         if (M <= 8192) return {512, 16};
-        if (M <= 16384) return {1024, 16};
+        if (M <= 16384) return {512, 32};
     }
     return {0, 0};
 }
@@ -236,12 +245,13 @@ int launch_theta_batch(const OptionDev& o, int M, int nsys, const double* tau0, 
         double *tab, *ptab;
         int rc = large_tables(0, &tab, &ptab);
         if (rc) return rc;
-        if (sh.T == 512) {
-            if ((rc = launch_large_setup<512>(o, M, theta * dt, tab, ptab, stream))) return rc;
+        const double h = theta * dt, e = (1.0 - theta) * dt;
+        if (sh.MC == 16) {
+            if ((rc = launch_large_setup<512, 16>(o, M, h, e, tab, ptab, stream))) return rc;
             hipLaunchKernelGGL((k_large_theta<512, 16>), dim3(nsys), dim3(512), 0, stream, a, tab, ptab);
         } else {
-            if ((rc = launch_large_setup<1024>(o, M, theta * dt, tab, ptab, stream))) return rc;
-            hipLaunchKernelGGL((k_large_theta<1024, 16>), dim3(nsys), dim3(1024), 0, stream, a, tab, ptab);
+            if ((rc = launch_large_setup<512, 32>(o, M, h, e, tab, ptab, stream))) return rc;
+            hipLaunchKernelGGL((k_large_theta<512, 32>), dim3(nsys), dim3(512), 0, stream, a, tab, ptab);
         }
         BSP_LAUNCHED();
         return BS_OK;
@@ -265,12 +275,12 @@ int launch_sweep(const SweepArgs& a, hipStream_t stream) {
         int rc = large_tables(1, &tab, &ptab);
         if (rc) return rc;
         const double h = a.dT / (double)a.coarse_steps;
-        if (sh.T == 512) {
-            if ((rc = launch_large_setup<512>(a.o, a.M, h, tab, ptab, stream))) return rc;
+        if (sh.MC == 16) {
+            if ((rc = launch_large_setup<512, 16>(a.o, a.M, h, 0.0, tab, ptab, stream))) return rc;
             hipLaunchKernelGGL((k_large_sweep<512, 16>), dim3(1), dim3(512), 0, stream, a, tab, ptab);
         } else {
-            if ((rc = launch_large_setup<1024>(a.o, a.M, h, tab, ptab, stream))) return rc;
-            hipLaunchKernelGGL((k_large_sweep<1024, 16>), dim3(1), dim3(1024), 0, stream, a, tab, ptab);
+            if ((rc = launch_large_setup<512, 32>(a.o, a.M, h, 0.0, tab, ptab, stream))) return rc;
+            hipLaunchKernelGGL((k_large_sweep<512, 32>), dim3(1), dim3(512), 0, stream, a, tab, ptab);
         }
         BSP_LAUNCHED();
         return BS_OK;

@@ -43,17 +43,59 @@ __device__ __forceinline__ void store_chunk(double* __restrict__ dst, int M, con
 // Steps per boundary-forcing table (two tables of this many doubles in LDS).
 constexpr int kForceChunk = 1024;
 
+// Shared memory of a tridiagonal kernel: the solver's 4T doubles followed by
+// the two forcing tables.  Loads and stores of a whole system are staged
+// through it so that consecutive lanes touch consecutive doubles (whole
+// 128-byte lines per wavefront access) instead of MC-strided chunks.
+template <int T>
+constexpr int smem_doubles() {
+    return 4 * T + 2 * kForceChunk;
+}
+
+// Whole-system load through shared memory.  Uses all of smem: call it before
+// the solver's setup.
+template <int T, int MC>
+__device__ __forceinline__ void load_system(const double* __restrict__ src, int M, double (&V)[MC],
+                                            double* smem) {
+    static_assert(T * MC <= smem_doubles<T>(), "staging area too small");
+    const int p = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < MC; ++k) {
+        const int i = k * T + p;
+        smem[i] = (i < M) ? src[i] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MC; ++q) V[q] = smem[p * MC + q];
+    __syncthreads();
+}
+
+// Whole-system store through shared memory, once the solver is done with it.
+template <int T, int MC>
+__device__ __forceinline__ void store_system(double* __restrict__ dst, int M, const double (&V)[MC],
+                                             double* smem) {
+    const int p = threadIdx.x;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MC; ++q) smem[p * MC + q] = V[q];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < MC; ++k) {
+        const int i = k * T + p;
+        if (i < M) dst[i] = smem[i];
+    }
+}
+
 // `steps` theta-steps of size dt from tau0 on the state V (this block's system).
+// EX: theta < 1 (the step has an explicit part); false for implicit Euler.
 // The boundary forcing of each step, (1-theta) dt g(tau_m) + theta dt g(tau_{m+1})
 // at S = 0 and S = S_max, is tabulated in LDS for a chunk of steps by all
 // threads in parallel, so the sequential step loop evaluates no exponential.
 // ftab: 2 * kForceChunk doubles of LDS.
-template <int T, int MC, class Solver>
+template <int T, int MC, bool EX, class Solver>
 __device__ __forceinline__ void theta_steps(const Solver& S, const OptionDev& o,
                                             double (&V)[MC], double tau0, double dt, int steps,
                                             double theta, bool homog, double* lds, double* ftab) {
-    double hl, hr;
-    S.halo(V, hl, hr, lds);
     const double h = theta * dt, e = (1.0 - theta) * dt;
     for (int m0 = 0; m0 < steps; m0 += kForceChunk) {
         const int nch = min(kForceChunk, steps - m0);
@@ -77,7 +119,7 @@ __device__ __forceinline__ void theta_steps(const Solver& S, const OptionDev& o,
                 flo_n = ftab[i + 1];
                 fhi_n = ftab[kForceChunk + i + 1];
             }
-            S.step(V, hl, hr, flo, fhi, lds);
+            S.template step<EX>(V, flo, fhi, lds);
         }
     }
 }
@@ -87,7 +129,7 @@ __device__ __forceinline__ void theta_steps(const Solver& S, const OptionDev& o,
 //   predict: U[n+1] = g, Gold[n] = g
 //   else:    U[n+1] = Fv[n] + (g - Gold[n]), Gold[n] = g,
 //            dmax = max |U_new[n+1] - U_old[n+1]|, bad |= non-finite.
-// S (BlockTri or BlockTriG) must be set up for implicit Euler with
+// S (BlockTri, BlockTriH or BlockTriG) must be set up for implicit Euler with
 // dt = dT / coarse_steps.
 template <int T, int MC, class Solver>
 __device__ __forceinline__ void sweep_slices(const Solver& S, const OptionDev& o, int M,
@@ -124,7 +166,8 @@ __device__ __forceinline__ void sweep_slices(const Solver& S, const OptionDev& o
         if (kind == BS_COARSE_IE) {
 #pragma unroll
             for (int q = 0; q < MC; ++q) g[q] = V[q];
-            theta_steps<T, MC>(S, o, g, (double)n * dT, dtc, coarse_steps, 1.0, false, lds, ftab);
+            theta_steps<T, MC, false>(S, o, g, (double)n * dT, dtc, coarse_steps, 1.0, false, lds,
+                                      ftab);
         } else if (kind == BS_COARSE_PINN) {
             const double* vn1 = Vt + (long)(n + 1) * M;
 #pragma unroll
@@ -136,7 +179,8 @@ __device__ __forceinline__ void sweep_slices(const Solver& S, const OptionDev& o
 #pragma unroll
             for (int q = 0; q < MC; ++q)
                 g[q] = V[q] - (kPrefetch ? vt0[q] : ((i0 + q < M) ? vn0[i0 + q] : 0.0));
-            theta_steps<T, MC>(S, o, g, (double)n * dT, dtc, coarse_steps, 1.0, true, lds, ftab);
+            theta_steps<T, MC, false>(S, o, g, (double)n * dT, dtc, coarse_steps, 1.0, true, lds,
+                                      ftab);
 #pragma unroll
             for (int q = 0; q < MC; ++q)
                 g[q] = (kPrefetch ? vt1[q] : ((i0 + q < M) ? vn1[i0 + q] : 0.0)) + g[q];

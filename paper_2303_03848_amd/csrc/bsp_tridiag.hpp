@@ -1,21 +1,28 @@
-// Block-level solver for the tridiagonal systems of the theta-method
-//   (I - theta dt L) V^{m+1} = (I + (1 - theta) dt L) V^m + boundary terms,
+// One-wavefront solver for the tridiagonal systems of the theta-method
+//   (I - h L) V^{m+1} = (I + e L) V^m + f,   h = theta dt,  e = (1 - theta) dt,
 // one system per thread block, the state kept in registers for all steps.
+//
+// Implicit form of a step.  With A = I - h L, the explicit operator is
+//   I + e L = kappa I - mu A,   kappa = 1 + e/h,  mu = e/h,
+// so a step is V^{m+1} = A^{-1} (kappa V^m + f) - mu V^m: one solve with A and
+// no product with the explicit stencil (Crank-Nicolson: kappa = 2, mu = 1;
+// implicit Euler: kappa = 1, mu = 0).  This is the same linear map as the
+// textbook evaluation, with less work per node and no neighbour values.
 //
 // The matrix is the same at every step (the coefficients of the
 // Black-Scholes operator do not depend on time), so everything but the
 // right-hand side is factored once in `setup`.
 //
-// Partition: thread p owns the MC consecutive unknowns i0 = p*MC .. i0+MC-1.
+// Partition: lane p owns the MC consecutive unknowns i0 = p*MC .. i0+MC-1.
 // Its last unknown z_p is an interface unknown; the MC-1 interior unknowns
 // depend on the two neighbouring interface unknowns only:
-//     x_int = y + z_{p-1} v + z_p w,
-// where y solves the interior block with the actual right-hand side and v, w
+//     x_int = d + z_{p-1} v + z_p w,
+// where d solves the interior block with the actual right-hand side and v, w
 // are its (constant) responses to unit coupling at the two ends.  Substituting
-// into the interface rows gives a tridiagonal system of T unknowns
+// into the interface rows gives a tridiagonal system of 64 unknowns
 //     A_p z_{p-1} + B_p z_p + C_p z_{p+1} = D_p,
-// solved by parallel cyclic reduction (PCR).  The reduction multipliers are
-// constant and kept per thread.
+// solved by parallel cyclic reduction (PCR) across the lanes.  The reduction
+// multipliers are constant and kept per lane.
 //
 // Truncated PCR: the interface system is strictly diagonally dominant and each
 // PCR stage squares the relative size of the off-diagonal couplings
@@ -24,24 +31,27 @@
 // run only those stages.  The neglected terms are below the rounding error of
 // the result, so the solve stays exact to working precision.
 //
-// Interior rows use a scaled LU: with pivots u_q, the forward sweep works on
-// d_q / u_q (the right-hand-side coefficients are pre-divided by u_q), so one
-// step costs per node 3 operations for the right-hand side, 1 forward, 1
-// backward and 2 for the interface correction.
+// Interior rows use the LU factors l_q = a_q / u_{q-1} (unit lower) and
+// u_q (upper, super-diagonal c_q), with kappa folded into the backward sweep:
+// per node a step costs 1 forward, 2 backward and 3 update operations.
 //
-// Exchanges between threads: with T = 64 the block is one wavefront; unit
-// shifts use DPP lane moves and longer strides ds_bpermute, with no LDS and no
-// barrier.  With T > 64 exchanges go through LDS with block barriers.
-// Nodes beyond M are padding rows of the identity, decoupled from the rest.
+// Exchanges: unit shifts use DPP lane moves and longer strides ds_bpermute,
+// with no LDS and no barrier.  Lanes whose partner lies outside the
+// wavefront carry a zero PCR multiplier, so the (wrapped, finite) value they
+// fetch does not contribute.  Nodes beyond M are identity rows, decoupled
+// from the rest, and keep their value (kappa - mu = 1).
 #pragma once
 
 #include "bsp_common.hpp"
 
 namespace bsp {
 
-// Value of `v` held by lane `src` of this wavefront (src taken modulo 64).
+// Value of `v` held by lane `src` of this wavefront, src taken modulo 64.
+// The wrap is explicit: a byte address outside the wavefront (including one
+// the compiler forms with the instruction's offset field) does not wrap in
+// hardware and returns undefined data.
 __device__ __forceinline__ double lane_fetch(double v, int src) {
-    const int addr = src << 2;
+    const int addr = (src & 63) << 2;
     const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
     const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
     return __hiloint2double(hi, lo);
@@ -60,134 +70,155 @@ __device__ __forceinline__ double dpp_from_next(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// Wavefront-uniform copy of an int (lives in a scalar register).
+__device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
 constexpr double kPcrTruncation = 8.673617379884035e-19;  // 2^-60
 
-template <int T, int MC>
-struct BlockTri {
-    static_assert(MC >= 2, "at least one interior row per chunk");
-    static constexpr int LOGT = ilog2(T);
+// Interior block of one chunk: LU factors, kappa-scaled backward sweep, and
+// the responses v, w.  Shared by the one- and multi-wavefront solvers.
+template <int MC>
+struct ChunkLU {
     static constexpr int NI = MC - 1;
-    static constexpr bool WAVE = (T == 64);
+    double l[NI], ku[NI], cu[NI];  // l_q = a_q/u_{q-1}, ku_q = kappa/u_q, cu_q = c_q/u_q
+    double v[NI], w[NI];           // interior responses to z_{p-1}, z_p
 
-    double ea[MC], eb[MC], ec[MC];  // explicit part (I + (1-theta) dt L), interior rows / u_q
-    double m[NI], cu[NI];           // scaled interior LU: a_q/u_q, c_q/u_q
-    double v[NI], w[NI];            // interior responses to z_{p-1}, z_p
-    double aq, cq;                  // interface row: implicit sub/super diagonal
-    double vF, wF;                  // v[0], w[0] of the next chunk
-    double k1[LOGT > 0 ? LOGT : 1], k2[LOGT > 0 ? LOGT : 1], invB;
-    double blo, bhi;                // boundary-forcing coefficients (scaled like their row)
-    int p, r_hi, nst;
-    bool own_lo, own_hi;
-
-    // --- exchanges: value held by thread p - s (up) / p + s (down), 0 outside [0, T)
-    __device__ __forceinline__ double wave_up(double x, int s) const {
-        if (s == 1) return dpp_from_prev(x);
-        const double y = lane_fetch(x, p - s);
-        return (p - s >= 0) ? y : 0.0;
-    }
-    __device__ __forceinline__ double wave_down(double x, int s) const {
-        if (s == 1) return dpp_from_next(x);
-        const double y = lane_fetch(x, p + s);
-        return (p + s < T) ? y : 0.0;
-    }
-
-    // Forward/backward sweep of the scaled interior LU on a right-hand side
-    // already divided by the pivots.
-    __device__ __forceinline__ void interior_solve(double (&t)[MC]) const {
-#pragma unroll
-        for (int q = 1; q < NI; ++q) t[q] = fma(-m[q], t[q - 1], t[q]);
-#pragma unroll
-        for (int q = NI - 2; q >= 0; --q) t[q] = fma(-cu[q], t[q + 1], t[q]);
-    }
-
-    // h = theta*dt (implicit weight), e = (1-theta)*dt (explicit weight).
-    // lds: at least 3*T doubles (unused when T == 64).  Contains block barriers.
-    __device__ void setup(double s2, double r, double h, double e, int M, double* lds) {
-        p = threadIdx.x;
-        const int i0 = p * MC;
-        double a[MC], b[MC], c[MC];
-#pragma unroll
-        for (int q = 0; q < MC; ++q) {
-            const int g = i0 + q;
-            double al, be, ga;
-            op_row(s2, r, (double)(g + 1), al, be, ga);
-            const bool pad = g >= M;
-            a[q] = (pad || g == 0) ? 0.0 : -h * al;
-            b[q] = pad ? 1.0 : 1.0 - h * be;
-            c[q] = (g >= M - 1) ? 0.0 : -h * ga;
-            ea[q] = (pad || g == 0) ? 0.0 : e * al;
-            eb[q] = pad ? 0.0 : 1.0 + e * be;
-            ec[q] = (g >= M - 1) ? 0.0 : e * ga;
-        }
-        double bnd_lo, bnd_hi;
-        {
-            double al, be, ga;
-            op_row(s2, r, 1.0, al, be, ga);
-            bnd_lo = al;
-            op_row(s2, r, (double)M, al, be, ga);
-            bnd_hi = ga;
-        }
-        own_lo = (p == 0);
-        own_hi = (p == (M - 1) / MC);
-        r_hi = (M - 1) % MC;
-
-        // scaled LU of the interior block
+    // Factor the interior rows a, b, c (first NI entries used).
+    __device__ __forceinline__ void factor(const double (&a)[MC], const double (&b)[MC],
+                                           const double (&c)[MC], double kappa) {
         double iu[NI];
         double u = b[0];
         iu[0] = 1.0 / u;
-        m[0] = 0.0;
-        cu[0] = c[0] * iu[0];
+        l[0] = 0.0;
 #pragma unroll
         for (int q = 1; q < NI; ++q) {
-            u = b[q] - (a[q] * iu[q - 1]) * c[q - 1];
+            l[q] = a[q] * iu[q - 1];
+            u = b[q] - l[q] * c[q - 1];
             iu[q] = 1.0 / u;
-            m[q] = a[q] * iu[q];
-            cu[q] = c[q] * iu[q];
-        }
-        {
-            double t[MC];
-#pragma unroll
-            for (int q = 0; q < MC; ++q) t[q] = 0.0;
-            t[0] = -a[0] * iu[0];
-            interior_solve(t);
-#pragma unroll
-            for (int q = 0; q < NI; ++q) v[q] = t[q];
-#pragma unroll
-            for (int q = 0; q < MC; ++q) t[q] = 0.0;
-            t[NI - 1] = -c[NI - 1] * iu[NI - 1];
-            interior_solve(t);
-#pragma unroll
-            for (int q = 0; q < NI; ++q) w[q] = t[q];
         }
 #pragma unroll
         for (int q = 0; q < NI; ++q) {
-            ea[q] *= iu[q];
-            eb[q] *= iu[q];
-            ec[q] *= iu[q];
+            ku[q] = kappa * iu[q];
+            cu[q] = c[q] * iu[q];
         }
-        blo = bnd_lo * iu[0];
-        bhi = bnd_hi;
+        // v = A_int^{-1} (-a_0 e_0),  w = A_int^{-1} (-c_{NI-1} e_{NI-1})
+        double t[NI];
+        t[0] = -a[0];
 #pragma unroll
-        for (int q = 0; q < NI; ++q)
-            if (q == r_hi) bhi = bnd_hi * iu[q];
+        for (int q = 1; q < NI; ++q) t[q] = -l[q] * t[q - 1];
+        t[NI - 1] *= iu[NI - 1];
+#pragma unroll
+        for (int q = NI - 2; q >= 0; --q) t[q] = fma(-cu[q], t[q + 1], t[q] * iu[q]);
+#pragma unroll
+        for (int q = 0; q < NI; ++q) v[q] = t[q];
+        w[NI - 1] = -c[NI - 1] * iu[NI - 1];
+#pragma unroll
+        for (int q = NI - 2; q >= 0; --q) w[q] = -cu[q] * w[q + 1];
+    }
+
+    // d <- kappa A_int^{-1} d  (forward, then kappa-scaled backward sweep).
+    __device__ __forceinline__ void solve(double (&d)[MC]) const {
+#pragma unroll
+        for (int q = 1; q < NI; ++q) d[q] = fma(-l[q], d[q - 1], d[q]);
+        d[NI - 1] *= ku[NI - 1];
+#pragma unroll
+        for (int q = NI - 2; q >= 0; --q) d[q] = fma(-cu[q], d[q + 1], ku[q] * d[q]);
+    }
+};
+
+// Matrix rows of chunk p (global rows p*MC ..), implicit weight h.  Rows at or
+// beyond M are identity rows.  Also the boundary coefficients alpha_1
+// (S = dS row, coupling to S = 0) and gamma_M (coupling to S = S_max).
+template <int MC>
+__device__ __forceinline__ void chunk_rows(double s2, double r, double h, int M, int p,
+                                           double (&a)[MC], double (&b)[MC], double (&c)[MC],
+                                           double& alpha1, double& gammaM) {
+#pragma unroll
+    for (int q = 0; q < MC; ++q) {
+        const int g = p * MC + q;
+        double al, be, ga;
+        op_row(s2, r, (double)(g + 1), al, be, ga);
+        const bool pad = g >= M;
+        a[q] = (pad || g == 0) ? 0.0 : -h * al;
+        b[q] = pad ? 1.0 : 1.0 - h * be;
+        c[q] = (g >= M - 1) ? 0.0 : -h * ga;
+    }
+    double al, be, ga;
+    op_row(s2, r, 1.0, al, be, ga);
+    alpha1 = al;
+    op_row(s2, r, (double)M, al, be, ga);
+    gammaM = ga;
+}
+
+// Boundary forcing of chunk p.  Row 0 is interior row 0 of chunk 0:
+// r_0 += blo * flo.  Row M-1 is either the interface row of its chunk
+// (D += bhiD * fhi, no per-node work) or an interior row (hi_in, r_{r_hi} +=
+// bhi * fhi).  Coefficients are zero on the chunks they do not concern.
+struct Forcing {
+    double blo, bhiD, bhi;
+    int r_hi;
+    bool hi_in;
+    __device__ __forceinline__ void init(int p, int MC, int M, double alpha1, double gammaM,
+                                         double kappa) {
+        blo = (p == 0) ? alpha1 / kappa : 0.0;
+        const bool owner = p == (M - 1) / MC;
+        r_hi = (M - 1) % MC;
+        hi_in = owner && r_hi < MC - 1;
+        bhiD = (owner && r_hi == MC - 1) ? gammaM : 0.0;
+        bhi = gammaM / kappa;
+    }
+    // Right-hand side of the interior rows: V (+ forcing / kappa).
+    template <int MC>
+    __device__ __forceinline__ void rhs(const double (&V)[MC], double flo, double fhi,
+                                        double (&d)[MC]) const {
+#pragma unroll
+        for (int q = 0; q < MC; ++q) d[q] = V[q];
+        d[0] = fma(blo, flo, d[0]);
+        if (hi_in) {
+#pragma unroll
+            for (int q = 0; q < MC - 1; ++q)
+                if (q == r_hi) d[q] = fma(bhi, fhi, d[q]);
+        }
+    }
+};
+
+template <int T, int MC>
+struct BlockTri {
+    static_assert(T == 64, "one wavefront (several: BlockTriH)");
+    static_assert(MC >= 2, "at least one interior row per chunk");
+    static constexpr int LOGT = 6;
+    static constexpr int NI = MC - 1;
+
+    ChunkLU<MC> lu;
+    Forcing fc;
+    double aq, cq, kap, mu;         // interface row: sub/super diagonal; step constants
+    double k1[LOGT], k2[LOGT], invB;
+    int p, nst;
+
+    __device__ __forceinline__ double up(double x, int s) const {
+        return s == 1 ? dpp_from_prev(x) : lane_fetch(x, p - s);
+    }
+    __device__ __forceinline__ double down(double x, int s) const {
+        return s == 1 ? dpp_from_next(x) : lane_fetch(x, p + s);
+    }
+
+    // h = theta*dt > 0 (implicit weight), e = (1-theta)*dt (explicit weight).
+    // lds is not used (kept for a common interface).
+    __device__ void setup(double s2, double r, double h, double e, int M, double* lds) {
+        (void)lds;
+        p = threadIdx.x;
+        kap = 1.0 + e / h;
+        mu = e / h;
+        double a[MC], b[MC], c[MC], alpha1, gammaM;
+        chunk_rows<MC>(s2, r, h, M, p, a, b, c, alpha1, gammaM);
+        lu.factor(a, b, c, kap);
+        fc.init(p, MC, M, alpha1, gammaM, kap);
         aq = a[MC - 1];
         cq = c[MC - 1];
-        const double bq = b[MC - 1];
-
-        if constexpr (WAVE) {
-            vF = wave_down(v[0], 1);
-            wF = wave_down(w[0], 1);
-        } else {
-            lds[p] = v[0];
-            lds[T + p] = w[0];
-            __syncthreads();
-            vF = (p + 1 < T) ? lds[p + 1] : 0.0;
-            wF = (p + 1 < T) ? lds[T + p + 1] : 0.0;
-            __syncthreads();
-        }
-
-        double A = aq * v[NI - 1];
-        double B = bq + aq * w[NI - 1] + cq * vF;
+        const double vF = dpp_from_next(lu.v[0]);
+        const double wF = dpp_from_next(lu.w[0]);
+        double A = aq * lu.v[NI - 1];
+        double B = b[MC - 1] + aq * lu.w[NI - 1] + cq * vF;
         double C = cq * wF;
         nst = LOGT;
         bool done = false;
@@ -195,157 +226,66 @@ struct BlockTri {
         for (int k = 0; k < LOGT; ++k) {
             k1[k] = 0.0;
             k2[k] = 0.0;
-            if (!done) {
-                // stop once every coupling is negligible (uniform decision over the block)
-                const double rel = (fabs(A) + fabs(C)) / fabs(B);
-                if (block_all_below(rel, lds)) {
-                    nst = k;
-                    done = true;
-                }
+            if (!done && __all(((fabs(A) + fabs(C)) / fabs(B)) <= kPcrTruncation)) {
+                nst = k;
+                done = true;
             }
             if (!done) {
                 const int s = 1 << k;
-                double Am, Bm, Cm, Ap, Bp, Cp;
-                if constexpr (WAVE) {
-                    Am = wave_up(A, s);
-                    Bm = wave_up(B, s);
-                    Cm = wave_up(C, s);
-                    Ap = wave_down(A, s);
-                    Bp = wave_down(B, s);
-                    Cp = wave_down(C, s);
-                    if (p - s < 0) Bm = 1.0;
-                    if (p + s >= T) Bp = 1.0;
-                } else {
-                    lds[p] = A;
-                    lds[T + p] = B;
-                    lds[2 * T + p] = C;
-                    __syncthreads();
-                    Am = 0.0, Bm = 1.0, Cm = 0.0, Ap = 0.0, Bp = 1.0, Cp = 0.0;
-                    if (p - s >= 0) {
-                        Am = lds[p - s];
-                        Bm = lds[T + p - s];
-                        Cm = lds[2 * T + p - s];
-                    }
-                    if (p + s < T) {
-                        Ap = lds[p + s];
-                        Bp = lds[T + p + s];
-                        Cp = lds[2 * T + p + s];
-                    }
-                    __syncthreads();
-                }
-                const double m1 = (p - s >= 0) ? A / Bm : 0.0;
-                const double m2 = (p + s < T) ? C / Bp : 0.0;
+                // exchanges first, on every lane (a DPP or bpermute under a
+                // partial exec mask reads nothing from the disabled lanes)
+                const bool lo = p - s >= 0, hi = p + s < T;
+                const double Au = up(A, s), Bu = up(B, s), Cu = up(C, s);
+                const double Ad = down(A, s), Bd = down(B, s), Cd = down(C, s);
+                const double Am = lo ? Au : 0.0, Bm = lo ? Bu : 1.0, Cm = lo ? Cu : 0.0;
+                const double Ap = hi ? Ad : 0.0, Bp = hi ? Bd : 1.0, Cp = hi ? Cd : 0.0;
+                const double m1 = lo ? A / Bm : 0.0;
+                const double m2 = hi ? C / Bp : 0.0;
                 k1[k] = m1;
                 k2[k] = m2;
-                const double An = -m1 * Am;
-                const double Cn = -m2 * Cp;
-                const double Bn = B - m1 * Cm - m2 * Ap;
+                const double An = -m1 * Am, Cn = -m2 * Cp, Bn = B - m1 * Cm - m2 * Ap;
                 A = An;
                 B = Bn;
                 C = Cn;
             }
         }
         invB = 1.0 / B;
+        nst = wave_uniform(nst);
     }
 
-    // True on every thread iff x <= kPcrTruncation on every thread of the block.
-    __device__ __forceinline__ bool block_all_below(double x, double* lds) const {
-        const bool mine = x <= kPcrTruncation;
-        if constexpr (WAVE) {
-            return __all(mine);
-        } else {
-            __syncthreads();
-            const int ok = __syncthreads_and(mine ? 1 : 0);
-            (void)lds;
-            return ok != 0;
-        }
-    }
-
-    // Initial halo: left = last node of chunk p-1, right = first node of chunk p+1.
-    __device__ __forceinline__ void halo(const double (&V)[MC], double& hl, double& hr,
+    // One step.  V: this chunk (in/out).  flo, fhi: boundary forcing
+    // e g(tau_old) + h g(tau_new) at S = 0 and S = S_max.  EX: the step has
+    // an explicit part (mu != 0); without it V is dead once the solve starts.
+    template <bool EX>
+    __device__ __forceinline__ void step(double (&V)[MC], double flo, double fhi,
                                          double* lds) const {
-        if constexpr (WAVE) {
-            hl = wave_up(V[MC - 1], 1);
-            hr = wave_down(V[0], 1);
-        } else {
-            lds[p] = V[0];
-            lds[T + p] = V[MC - 1];
-            __syncthreads();
-            hl = (p > 0) ? lds[T + p - 1] : 0.0;
-            hr = (p + 1 < T) ? lds[p + 1] : 0.0;
-            __syncthreads();
-        }
-    }
-
-    // One step.  V: this chunk (in/out); hl, hr: halo values (in/out, kept
-    // current for the next step).  flo, fhi: boundary forcing, i.e.
-    // (1-theta) dt g(tau_old) + theta dt g(tau_new) at S = 0 and S = S_max.
-    // lds: at least 4*T doubles (unused when T == 64).
-    __device__ __forceinline__ void step(double (&V)[MC], double& hl, double& hr, double flo,
-                                         double fhi, double* lds) const {
+        (void)lds;
         double d[MC];
+        fc.rhs(V, flo, fhi, d);
+        lu.solve(d);
+        const double yF = dpp_from_next(d[0]);
+        double D = fma(kap, V[MC - 1], fma(fc.bhiD, fhi, fma(-aq, d[NI - 1], -cq * yF)));
+        // explicit remainder -mu V, off the critical path of the reduction
+        double rz = 0.0;
+        if constexpr (EX) {
 #pragma unroll
-        for (int q = 0; q < MC; ++q) {
-            const double left = (q == 0) ? hl : V[q - 1];
-            const double right = (q == MC - 1) ? hr : V[q + 1];
-            d[q] = fma(ea[q], left, fma(eb[q], V[q], ec[q] * right));
+            for (int q = 0; q < NI; ++q) d[q] = fma(-mu, V[q], d[q]);
+            rz = -mu * V[MC - 1];
         }
-        if (own_lo) d[0] = fma(blo, flo, d[0]);
-        if (own_hi) {
 #pragma unroll
-            for (int q = 0; q < MC; ++q)
-                if (q == r_hi) d[q] = fma(bhi, fhi, d[q]);
-        }
-        interior_solve(d);
-
-        double yF, z, zl, zr;
-        if constexpr (WAVE) {
-            yF = wave_down(d[0], 1);
-            double D = fma(-aq, d[NI - 1], fma(-cq, yF, d[MC - 1]));
-#pragma unroll
-            for (int k = 0; k < LOGT; ++k) {
-                if (k < nst) {
-                    const int s = 1 << k;
-                    const double Dm = wave_up(D, s);
-                    const double Dp = wave_down(D, s);
-                    D = fma(-k1[k], Dm, fma(-k2[k], Dp, D));
-                }
+        for (int k = 0; k < LOGT; ++k) {
+            if (k < nst) {
+                const int s = 1 << k;
+                const double Dm = up(D, s);
+                const double Dp = down(D, s);
+                D = fma(-k1[k], Dm, fma(-k2[k], Dp, D));
             }
-            z = D * invB;
-            zl = wave_up(z, 1);
-            zr = wave_down(z, 1);
-        } else {
-            double* ybuf = lds;
-            double* pb0 = lds + T;
-            double* pb1 = lds + 2 * T;
-            double* zbuf = lds + 3 * T;
-            ybuf[p] = d[0];
-            __syncthreads();
-            yF = (p + 1 < T) ? ybuf[p + 1] : 0.0;
-            double D = fma(-aq, d[NI - 1], fma(-cq, yF, d[MC - 1]));
-#pragma unroll
-            for (int k = 0; k < LOGT; ++k) {
-                if (k < nst) {
-                    const int s = 1 << k;
-                    double* buf = (k & 1) ? pb1 : pb0;
-                    buf[p] = D;
-                    __syncthreads();
-                    const double Dm = (p - s >= 0) ? buf[p - s] : 0.0;
-                    const double Dp = (p + s < T) ? buf[p + s] : 0.0;
-                    D = fma(-k1[k], Dm, fma(-k2[k], Dp, D));
-                }
-            }
-            z = D * invB;
-            zbuf[p] = z;
-            __syncthreads();
-            zl = (p > 0) ? zbuf[p - 1] : 0.0;
-            zr = (p + 1 < T) ? zbuf[p + 1] : 0.0;
         }
+        const double z = D * invB;
+        const double zl = dpp_from_prev(z);
 #pragma unroll
-        for (int q = 0; q < NI; ++q) V[q] = fma(zl, v[q], fma(z, w[q], d[q]));
-        V[MC - 1] = z;
-        hl = zl;
-        hr = fma(z, vF, fma(zr, wF, yF));
+        for (int q = 0; q < NI; ++q) V[q] = fma(zl, lu.v[q], fma(z, lu.w[q], d[q]));
+        V[MC - 1] = z + rz;
     }
 };
 

@@ -18,6 +18,7 @@
 #pragma once
 
 #include "bsp_common.hpp"
+#include "bsp_tridiag.hpp"
 
 namespace bsp {
 
@@ -29,35 +30,23 @@ struct BlockTriH {
     static constexpr int NI = MC - 1;
     static constexpr int NS = 6;  // intra-wavefront reduction stages (strides 1..32)
 
-    double ea[MC], eb[MC], ec[MC];  // explicit part, interior rows scaled by 1/u_q
-    double m[NI], cu[NI];           // scaled interior LU
-    double v[NI], w[NI];            // interior responses to z_{c-1}, z_c
-    double aq, cq, vF, wF, blo, bhi;
+    ChunkLU<MC> lu;
+    Forcing fc;
+    double aq, cq, kap, mu;
     double k1[NS], k2[NS], invB2, vt, wt;  // level 2
-    double A63, vt0n, wt0n;                // lane 63: own row's A, next wavefront's lane-0 responses
-    int p, lane, wave, r_hi, nst2;
+    double A63;                            // lane 63: its own row's A
+    int p, lane, wave, nst2;
     mutable int par;  // step parity: double-buffered exchange slots
-    bool own_lo, own_hi;
 
     __device__ __forceinline__ double up(double x, int s) const {
-        if (s == 1) return dpp_from_prev(x);
-        const double y = lane_fetch(x, lane - s);
-        return (lane - s >= 0) ? y : 0.0;
+        return s == 1 ? dpp_from_prev(x) : lane_fetch(x, lane - s);
     }
     __device__ __forceinline__ double down(double x, int s) const {
-        if (s == 1) return dpp_from_next(x);
-        const double y = lane_fetch(x, lane + s);
-        return (lane + s < 64) ? y : 0.0;
+        return s == 1 ? dpp_from_next(x) : lane_fetch(x, lane + s);
     }
 
-    __device__ __forceinline__ void interior_solve(double (&t)[MC]) const {
-#pragma unroll
-        for (int q = 1; q < NI; ++q) t[q] = fma(-m[q], t[q - 1], t[q]);
-#pragma unroll
-        for (int q = NI - 2; q >= 0; --q) t[q] = fma(-cu[q], t[q + 1], t[q]);
-    }
-
-    // Level-2 reduction of one right-hand side (zero at lane 63).
+    // Level-2 reduction of one right-hand side (zero at lane 63).  Lanes whose
+    // partner lies outside the wavefront have zero multipliers.
     __device__ __forceinline__ double wave_reduce(double D) const {
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
@@ -71,90 +60,33 @@ struct BlockTriH {
         return D;
     }
 
-    // LDS regions (doubles): setup scratch [0, 3T); halo() uses [0, 2T);
-    // exchange slots [2T, 2T + 6W); level-3 constants [3T, 3T + 5W).
+    // LDS regions (doubles): setup scratch [0, 2T); exchange slots
+    // [2T, 2T + 6W); level-3 constants [3T, 3T + 5W).  The last two persist
+    // between steps.
     __device__ void setup(double s2, double r, double h, double e, int M, double* lds) {
         p = threadIdx.x;
         lane = p & 63;
-        wave = p >> 6;
+        wave = wave_uniform(p >> 6);
         par = 0;
-        const int i0 = p * MC;
-        double a[MC], b[MC], c[MC];
-#pragma unroll
-        for (int q = 0; q < MC; ++q) {
-            const int g = i0 + q;
-            double al, be, ga;
-            op_row(s2, r, (double)(g + 1), al, be, ga);
-            const bool pad = g >= M;
-            a[q] = (pad || g == 0) ? 0.0 : -h * al;
-            b[q] = pad ? 1.0 : 1.0 - h * be;
-            c[q] = (g >= M - 1) ? 0.0 : -h * ga;
-            ea[q] = (pad || g == 0) ? 0.0 : e * al;
-            eb[q] = pad ? 0.0 : 1.0 + e * be;
-            ec[q] = (g >= M - 1) ? 0.0 : e * ga;
-        }
-        double bnd_lo, bnd_hi;
-        {
-            double al, be, ga;
-            op_row(s2, r, 1.0, al, be, ga);
-            bnd_lo = al;
-            op_row(s2, r, (double)M, al, be, ga);
-            bnd_hi = ga;
-        }
-        own_lo = (p == 0);
-        own_hi = (p == (M - 1) / MC);
-        r_hi = (M - 1) % MC;
-        double iu[NI];
-        double u = b[0];
-        iu[0] = 1.0 / u;
-        m[0] = 0.0;
-        cu[0] = c[0] * iu[0];
-#pragma unroll
-        for (int q = 1; q < NI; ++q) {
-            u = b[q] - (a[q] * iu[q - 1]) * c[q - 1];
-            iu[q] = 1.0 / u;
-            m[q] = a[q] * iu[q];
-            cu[q] = c[q] * iu[q];
-        }
-        {
-            double t[MC];
-#pragma unroll
-            for (int q = 0; q < MC; ++q) t[q] = 0.0;
-            t[0] = -a[0] * iu[0];
-            interior_solve(t);
-#pragma unroll
-            for (int q = 0; q < NI; ++q) v[q] = t[q];
-#pragma unroll
-            for (int q = 0; q < MC; ++q) t[q] = 0.0;
-            t[NI - 1] = -c[NI - 1] * iu[NI - 1];
-            interior_solve(t);
-#pragma unroll
-            for (int q = 0; q < NI; ++q) w[q] = t[q];
-        }
-#pragma unroll
-        for (int q = 0; q < NI; ++q) {
-            ea[q] *= iu[q];
-            eb[q] *= iu[q];
-            ec[q] *= iu[q];
-        }
-        blo = bnd_lo * iu[0];
-        bhi = bnd_hi;
-#pragma unroll
-        for (int q = 0; q < NI; ++q)
-            if (q == r_hi) bhi = bnd_hi * iu[q];
+        kap = 1.0 + e / h;
+        mu = e / h;
+        double a[MC], b[MC], c[MC], alpha1, gammaM;
+        chunk_rows<MC>(s2, r, h, M, p, a, b, c, alpha1, gammaM);
+        lu.factor(a, b, c, kap);
+        fc.init(p, MC, M, alpha1, gammaM, kap);
         aq = a[MC - 1];
         cq = c[MC - 1];
         const double bq = b[MC - 1];
 
         // level-1 row of chunk p (needs the next chunk's v[0], w[0])
-        lds[p] = v[0];
-        lds[T + p] = w[0];
+        lds[p] = lu.v[0];
+        lds[T + p] = lu.w[0];
         __syncthreads();
-        vF = (p + 1 < T) ? lds[p + 1] : 0.0;
-        wF = (p + 1 < T) ? lds[T + p + 1] : 0.0;
+        const double vF = (p + 1 < T) ? lds[p + 1] : 0.0;
+        const double wF = (p + 1 < T) ? lds[T + p + 1] : 0.0;
         __syncthreads();
-        const double A = aq * v[NI - 1];
-        const double B = bq + aq * w[NI - 1] + cq * vF;
+        const double A = aq * lu.v[NI - 1];
+        const double B = bq + aq * lu.w[NI - 1] + cq * vF;
         const double C = cq * wF;
 
         // level 2: lanes 0..62 without their couplings outside the wavefront;
@@ -179,12 +111,15 @@ struct BlockTriH {
             }
             if (!done) {
                 const int s = 1 << k;
-                const double Am = up(A2, s), Cm = up(C2, s), Ap = down(A2, s), Cp = down(C2, s);
-                double Bm = up(B2, s), Bp = down(B2, s);
-                if (lane - s < 0) Bm = 1.0;
-                if (lane + s >= 64) Bp = 1.0;
-                const double m1 = (lane - s >= 0) ? A2 / Bm : 0.0;
-                const double m2 = (lane + s < 64) ? C2 / Bp : 0.0;
+                // exchanges first, on every lane (a DPP or bpermute under a
+                // partial exec mask reads nothing from the disabled lanes)
+                const bool lo = lane - s >= 0, hi = lane + s < 64;
+                const double Au = up(A2, s), Bu = up(B2, s), Cu = up(C2, s);
+                const double Ad = down(A2, s), Bd = down(B2, s), Cd = down(C2, s);
+                const double Am = lo ? Au : 0.0, Bm = lo ? Bu : 1.0, Cm = lo ? Cu : 0.0;
+                const double Ap = hi ? Ad : 0.0, Bp = hi ? Bd : 1.0, Cp = hi ? Cd : 0.0;
+                const double m1 = lo ? A2 / Bm : 0.0;
+                const double m2 = hi ? C2 / Bp : 0.0;
                 k1[k] = m1;
                 k2[k] = m2;
                 const double An = -m1 * Am, Cn = -m2 * Cp, Bn = B2 - m1 * Cm - m2 * Ap;
@@ -193,6 +128,7 @@ struct BlockTriH {
                 C2 = Cn;
             }
         }
+        nst2 = wave_uniform(nst2);
         invB2 = 1.0 / B2;
         vt = wave_reduce(lane == 0 ? -A : 0.0) * invB2;
         wt = wave_reduce(lane == 62 ? -C : 0.0) * invB2;
@@ -203,15 +139,14 @@ struct BlockTriH {
 
         // level 3: the interface rows of the wavefronts
         const double vt62 = dpp_from_prev(vt), wt62 = dpp_from_prev(wt);
-        __syncthreads();
         if (lane == 0) {
             lds[2 * wave] = vt;
             lds[2 * wave + 1] = wt;
         }
         __syncthreads();
         A63 = A;
-        vt0n = (wave + 1 < W) ? lds[2 * (wave + 1)] : 0.0;
-        wt0n = (wave + 1 < W) ? lds[2 * (wave + 1) + 1] : 0.0;
+        const double vt0n = (wave + 1 < W) ? lds[2 * (wave + 1)] : 0.0;
+        const double wt0n = (wave + 1 < W) ? lds[2 * (wave + 1) + 1] : 0.0;
         __syncthreads();
         double* pub = lds + 2 * T;  // alpha, beta, gamma, cq63, C63 per wavefront
         if (lane == 63) {
@@ -242,36 +177,17 @@ struct BlockTriH {
         __syncthreads();
     }
 
-    __device__ __forceinline__ void halo(const double (&V)[MC], double& hl, double& hr,
+    // One step (see BlockTri::step).  Contains one block barrier.
+    template <bool EX>
+    __device__ __forceinline__ void step(double (&V)[MC], double flo, double fhi,
                                          double* lds) const {
-        lds[p] = V[0];
-        lds[T + p] = V[MC - 1];
-        __syncthreads();
-        hl = (p > 0) ? lds[T + p - 1] : 0.0;
-        hr = (p + 1 < T) ? lds[p + 1] : 0.0;
-        __syncthreads();
-    }
-
-    __device__ __forceinline__ void step(double (&V)[MC], double& hl, double& hr, double flo,
-                                         double fhi, double* lds) const {
         double d[MC];
-#pragma unroll
-        for (int q = 0; q < MC; ++q) {
-            const double left = (q == 0) ? hl : V[q - 1];
-            const double right = (q == MC - 1) ? hr : V[q + 1];
-            d[q] = fma(ea[q], left, fma(eb[q], V[q], ec[q] * right));
-        }
-        if (own_lo) d[0] = fma(blo, flo, d[0]);
-        if (own_hi) {
-#pragma unroll
-            for (int q = 0; q < MC; ++q)
-                if (q == r_hi) d[q] = fma(bhi, fhi, d[q]);
-        }
-        interior_solve(d);
+        fc.rhs(V, flo, fhi, d);
+        lu.solve(d);
 
         // level 1 -> level 2
         const double yF = dpp_from_next(d[0]);  // lane 63: 0, its term enters at level 3
-        const double D = fma(-aq, d[NI - 1], fma(-cq, yF, d[MC - 1]));
+        const double D = fma(kap, V[MC - 1], fma(fc.bhiD, fhi, fma(-aq, d[NI - 1], -cq * yF)));
         const double yt = wave_reduce(lane == 63 ? 0.0 : D) * invB2;
         const double yt62 = dpp_from_prev(yt);
 
@@ -283,9 +199,15 @@ struct BlockTriH {
             slot[W + wave] = d[0];
             slot[2 * W + wave] = yt;
         }
+        double rz = 0.0;
+        if constexpr (EX) {
+#pragma unroll
+            for (int q = 0; q < NI; ++q) d[q] = fma(-mu, V[q], d[q]);
+            rz = -mu * V[MC - 1];
+        }
         __syncthreads();
         const double* L3 = lds + 3 * T;
-        double Z[W], Yn = 0.0, Ytn = 0.0;
+        double Z[W];
         double rp = 0.0;
 #pragma unroll
         for (int q = 0; q < W; ++q) {
@@ -298,30 +220,20 @@ struct BlockTriH {
         Z[W - 1] *= L3[W + W - 1];
 #pragma unroll
         for (int q = W - 2; q >= 0; --q) Z[q] = (Z[q] - L3[2 * W + q] * Z[q + 1]) * L3[W + q];
-        double Zm = 0.0, Z0 = 0.0, Zp = 0.0;
+        double Zm = 0.0, Z0 = 0.0;
 #pragma unroll
         for (int q = 0; q < W; ++q) {
             if (q == wave - 1) Zm = Z[q];
             if (q == wave) Z0 = Z[q];
-            if (q == wave + 1) Zp = Z[q];
-        }
-        if (wave + 1 < W) {
-            Yn = slot[W + wave + 1];
-            Ytn = slot[2 * W + wave + 1];
         }
 
         // back-substitution
         const double z = (lane == 63) ? Z0 : fma(Zm, vt, fma(Z0, wt, yt));
         double zl = dpp_from_prev(z);
-        double zr = dpp_from_next(z);
         if (lane == 0) zl = Zm;
-        if (lane == 63) zr = fma(Z0, vt0n, fma(Zp, wt0n, Ytn));
-        const double yFe = (lane == 63) ? Yn : yF;
 #pragma unroll
-        for (int q = 0; q < NI; ++q) V[q] = fma(zl, v[q], fma(z, w[q], d[q]));
-        V[MC - 1] = z;
-        hl = zl;
-        hr = fma(z, vF, fma(zr, wF, yFe));
+        for (int q = 0; q < NI; ++q) V[q] = fma(zl, lu.v[q], fma(z, lu.w[q], d[q]));
+        V[MC - 1] = z + rz;
     }
 };
 

@@ -1,27 +1,28 @@
 // Tridiagonal block solver for large grids (M up to 16384), where the
 // per-node factorisation does not fit in registers or LDS of one compute unit.
 //
-// Same partition and truncated parallel cyclic reduction as BlockTri, with
-// three differences:
-//  * the interior LU factors and responses (l, 1/u, c/u, v, w) of every node
-//    live in a global table computed once per launch by k_large_setup and are
-//    streamed every step (coalesced: table[f][q][thread]); all systems of a
-//    launch share one table, so it stays in the L2 / infinity cache;
-//  * the explicit-operator coefficients are recomputed from j every step;
-//  * the interior solve is the unscaled LU form: forward y_q -= l_q y_{q-1},
-//    backward x_q = y_q / u_q - (c_q / u_q) x_{q+1}.
+// Same partition, implicit step form and truncated parallel cyclic reduction
+// as BlockTri, with two differences:
+//  * the interior LU factors and responses (l, kappa/u, c/u, v, w) of every
+//    node live in a global table computed once per launch by k_large_setup
+//    and are streamed every step (coalesced: table[f][q][thread]); all
+//    systems of a launch share one table, so it stays in the L2 / infinity
+//    cache;
+//  * the interface system of the T threads is reduced through LDS with one
+//    barrier per PCR stage.
 // Per-thread interface data (PCR multipliers, interface row, stage count) is
 // a second table ptab[field][thread].
 #pragma once
 
 #include "bsp_common.hpp"
+#include "bsp_tridiag.hpp"
 
 namespace bsp {
 
 constexpr double kPcrTruncationLarge = 8.673617379884035e-19;  // 2^-60
 
-enum { kLgL = 0, kLgIU, kLgCU, kLgV, kLgW, kLgFields };
-// per-thread fields of ptab: aq, cq, vF, wF, invB, blo, bhi, nst, k1[16], k2[16]
+enum { kLgL = 0, kLgKU, kLgCU, kLgV, kLgW, kLgFields };
+// per-thread fields of ptab: aq, cq, invB, nst, (4 spare), k1[16], k2[16]
 constexpr int kLgP = 8 + 32;
 
 template <int T, int MC>
@@ -32,85 +33,53 @@ struct BlockTriG {
 
     const double* tab;
     const double* ptab;
-    double s2, r, h, e;
-    double aq, cq, vF, wF, invB, blo, bhi;
-    int M, p, r_hi, nst;
-    bool own_lo, own_hi;
+    Forcing fc;
+    double aq, cq, invB, kap, mu;
+    int p, nst;
 
     __device__ __forceinline__ double coef(const double* tb, int f, int q) const {
         return tb[((long)f * MC + q) * T + p];
     }
 
-    __device__ void load(const double* tab_, const double* ptab_, double s2_, double r_, double h_,
-                         double e_, int M_) {
+    // h = theta*dt > 0, e = (1-theta)*dt; tables built by k_large_setup for
+    // the same (s2, r, h, e, M).
+    __device__ void load(const double* tab_, const double* ptab_, double s2, double r, double h,
+                         double e, int M) {
         tab = tab_;
         ptab = ptab_;
-        s2 = s2_;
-        r = r_;
-        h = h_;
-        e = e_;
-        M = M_;
         p = threadIdx.x;
+        kap = 1.0 + e / h;
+        mu = e / h;
         aq = ptab[0 * T + p];
         cq = ptab[1 * T + p];
-        vF = ptab[2 * T + p];
-        wF = ptab[3 * T + p];
-        invB = ptab[4 * T + p];
-        blo = ptab[5 * T + p];
-        bhi = ptab[6 * T + p];
-        nst = (int)ptab[7 * T + p];
-        own_lo = (p == 0);
-        own_hi = (p == (M - 1) / MC);
-        r_hi = (M - 1) % MC;
+        invB = ptab[2 * T + p];
+        nst = wave_uniform((int)ptab[3 * T + p]);
+        double al, be, ga, gammaM;
+        op_row(s2, r, 1.0, al, be, ga);
+        const double alpha1 = al;
+        op_row(s2, r, (double)M, al, be, ga);
+        gammaM = ga;
+        fc.init(p, MC, M, alpha1, gammaM, kap);
     }
 
-    __device__ __forceinline__ void halo(const double (&V)[MC], double& hl, double& hr,
+    // One step (see BlockTri::step).  lds: 4*T doubles; the stage multipliers
+    // are re-read from ptab.
+    template <bool EX>
+    __device__ __forceinline__ void step(double (&V)[MC], double flo, double fhi,
                                          double* lds) const {
-        lds[p] = V[0];
-        lds[T + p] = V[MC - 1];
-        __syncthreads();
-        hl = (p > 0) ? lds[T + p - 1] : 0.0;
-        hr = (p + 1 < T) ? lds[p + 1] : 0.0;
-        __syncthreads();
-    }
-
-    // lds: 4*T doubles; the stage multipliers are re-read from ptab.
-    __device__ __forceinline__ void step(double (&V)[MC], double& hl, double& hr, double flo,
-                                         double fhi, double* lds) const {
-        const int i0 = p * MC;
-        // Opaque per step: the compiler must neither hoist the table loads
-        // nor keep the recomputed coefficients across steps (that is the
-        // register footprint this solver exists to avoid).
+        // Opaque per step: the compiler must not hoist the table loads out of
+        // the step loop (that is the register footprint this solver avoids).
         const double* tb = tab;
         const double* pt = ptab;
-        double ee = e, ss2 = s2, rr = r;
-        asm volatile("" : "+v"(tb), "+v"(pt), "+v"(ee), "+v"(ss2), "+v"(rr));
+        asm volatile("" : "+v"(tb), "+v"(pt));
         double d[MC];
-#pragma unroll
-        for (int q = 0; q < MC; ++q) {
-            const int g = i0 + q;
-            double al, be, ga;
-            op_row(ss2, rr, (double)(g + 1), al, be, ga);
-            const bool pad = g >= M;
-            const double ea = (pad || g == 0) ? 0.0 : ee * al;
-            const double eb = pad ? 0.0 : 1.0 + ee * be;
-            const double ec = (g >= M - 1) ? 0.0 : ee * ga;
-            const double left = (q == 0) ? hl : V[q - 1];
-            const double right = (q == MC - 1) ? hr : V[q + 1];
-            d[q] = fma(ea, left, fma(eb, V[q], ec * right));
-        }
-        if (own_lo) d[0] = fma(blo, flo, d[0]);
-        if (own_hi) {
-#pragma unroll
-            for (int q = 0; q < MC; ++q)
-                if (q == r_hi) d[q] = fma(bhi, fhi, d[q]);
-        }
+        fc.rhs(V, flo, fhi, d);
 #pragma unroll
         for (int q = 1; q < NI; ++q) d[q] = fma(-coef(tb, kLgL, q), d[q - 1], d[q]);
-        d[NI - 1] *= coef(tb, kLgIU, NI - 1);
+        d[NI - 1] *= coef(tb, kLgKU, NI - 1);
 #pragma unroll
         for (int q = NI - 2; q >= 0; --q)
-            d[q] = fma(-coef(tb, kLgCU, q), d[q + 1], d[q] * coef(tb, kLgIU, q));
+            d[q] = fma(-coef(tb, kLgCU, q), d[q + 1], d[q] * coef(tb, kLgKU, q));
 
         double* ybuf = lds;
         double* pb0 = lds + T;
@@ -119,7 +88,14 @@ struct BlockTriG {
         ybuf[p] = d[0];
         __syncthreads();
         const double yF = (p + 1 < T) ? ybuf[p + 1] : 0.0;
-        double D = fma(-aq, d[NI - 1], fma(-cq, yF, d[MC - 1]));
+        double D = fma(kap, V[MC - 1], fma(fc.bhiD, fhi, fma(-aq, d[NI - 1], -cq * yF)));
+        // explicit remainder -mu V; V is dead from here on
+        double rz = 0.0;
+        if constexpr (EX) {
+#pragma unroll
+            for (int q = 0; q < NI; ++q) d[q] = fma(-mu, V[q], d[q]);
+            rz = -mu * V[MC - 1];
+        }
         for (int k = 0; k < nst; ++k) {
             const int s = 1 << k;
             double* buf = (k & 1) ? pb1 : pb0;
@@ -133,12 +109,10 @@ struct BlockTriG {
         zbuf[p] = z;
         __syncthreads();
         const double zl = (p > 0) ? zbuf[p - 1] : 0.0;
-        const double zr = (p + 1 < T) ? zbuf[p + 1] : 0.0;
 #pragma unroll
-        for (int q = 0; q < NI; ++q) V[q] = fma(zl, coef(tb, kLgV, q), fma(z, coef(tb, kLgW, q), d[q]));
-        V[MC - 1] = z;
-        hl = zl;
-        hr = fma(z, vF, fma(zr, wF, yF));
+        for (int q = 0; q < NI; ++q)
+            V[q] = fma(zl, coef(tb, kLgV, q), fma(z, coef(tb, kLgW, q), d[q]));
+        V[MC - 1] = z + rz;
     }
 };
 
@@ -146,12 +120,13 @@ struct BlockTriG {
 // block of T threads; each thread walks its chunk sequentially in global
 // memory, then the interface system is reduced through LDS.
 template <int T, int MC>
-__global__ __launch_bounds__(T) void k_large_setup(double s2, double r, double h, int M,
-                                                   double* __restrict__ tab,
+__global__ __launch_bounds__(T) void k_large_setup(double s2, double r, double h, double e,
+                                                   int M, double* __restrict__ tab,
                                                    double* __restrict__ ptab) {
     constexpr int LOGT = ilog2(T), NI = MC - 1;
     __shared__ double lds[3 * T];
     const int p = threadIdx.x, i0 = p * MC;
+    const double kappa = 1.0 + e / h;
     auto A = [&](int g) {
         double al, be, ga;
         op_row(s2, r, (double)(g + 1), al, be, ga);
@@ -168,18 +143,18 @@ __global__ __launch_bounds__(T) void k_large_setup(double s2, double r, double h
         return g >= M - 1 ? 0.0 : -h * ga;
     };
     auto at = [&](int f, int q) -> double& { return tab[((long)f * MC + q) * T + p]; };
-    // unscaled LU of the interior rows 0..NI-1
-    double u = B(i0), iu = 1.0 / u;
+    // LU of the interior rows 0..NI-1: l_q = a_q/u_{q-1}; KU holds 1/u_q until
+    // the responses are done, then kappa/u_q
+    double u = B(i0);
     at(kLgL, 0) = 0.0;
-    at(kLgIU, 0) = iu;
-    at(kLgCU, 0) = C(i0) * iu;
+    at(kLgKU, 0) = 1.0 / u;
+    at(kLgCU, 0) = C(i0) / u;
     for (int q = 1; q < NI; ++q) {
-        const double l = A(i0 + q) * iu;
+        const double l = A(i0 + q) / u;
         u = B(i0 + q) - l * C(i0 + q - 1);
-        iu = 1.0 / u;
         at(kLgL, q) = l;
-        at(kLgIU, q) = iu;
-        at(kLgCU, q) = C(i0 + q) * iu;
+        at(kLgKU, q) = 1.0 / u;
+        at(kLgCU, q) = C(i0 + q) / u;
     }
     // responses: v to -a_0 e_0, w to -c_{NI-1} e_{NI-1}
     double t = -A(i0);
@@ -188,11 +163,12 @@ __global__ __launch_bounds__(T) void k_large_setup(double s2, double r, double h
         t = -at(kLgL, q) * t;
         at(kLgV, q) = t;
     }
-    at(kLgV, NI - 1) *= at(kLgIU, NI - 1);
+    at(kLgV, NI - 1) *= at(kLgKU, NI - 1);
     for (int q = NI - 2; q >= 0; --q)
-        at(kLgV, q) = at(kLgV, q) * at(kLgIU, q) - at(kLgCU, q) * at(kLgV, q + 1);
-    at(kLgW, NI - 1) = -C(i0 + NI - 1) * at(kLgIU, NI - 1);
+        at(kLgV, q) = fma(-at(kLgCU, q), at(kLgV, q + 1), at(kLgV, q) * at(kLgKU, q));
+    at(kLgW, NI - 1) = -C(i0 + NI - 1) * at(kLgKU, NI - 1);
     for (int q = NI - 2; q >= 0; --q) at(kLgW, q) = -at(kLgCU, q) * at(kLgW, q + 1);
+    for (int q = 0; q < NI; ++q) at(kLgKU, q) *= kappa;
 
     const double aq = A(i0 + MC - 1), cq = C(i0 + MC - 1), bq = B(i0 + MC - 1);
     lds[p] = at(kLgV, 0);
@@ -244,21 +220,11 @@ __global__ __launch_bounds__(T) void k_large_setup(double s2, double r, double h
         Bq = Bn;
         Cq = Cn;
     }
-    double al, be, ga;
-    op_row(s2, r, 1.0, al, be, ga);
-    const double bnd_lo = al;
-    op_row(s2, r, (double)M, al, be, ga);
-    const double bnd_hi = ga;
-    const int r_hi = (M - 1) % MC;
     ptab[0 * T + p] = aq;
     ptab[1 * T + p] = cq;
-    ptab[2 * T + p] = vF;
-    ptab[3 * T + p] = wF;
-    ptab[4 * T + p] = 1.0 / Bq;
-    ptab[5 * T + p] = bnd_lo;   // row 0 is interior: forcing enters before the LU
-    ptab[6 * T + p] = bnd_hi;   // likewise for row M-1 (interior or interface row)
-    ptab[7 * T + p] = (double)nst;
-    (void)r_hi;
+    ptab[2 * T + p] = 1.0 / Bq;
+    ptab[3 * T + p] = (double)nst;
+    for (int f = 4; f < 8; ++f) ptab[f * T + p] = 0.0;
 }
 
 }  // namespace bsp

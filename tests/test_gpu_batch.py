@@ -131,3 +131,12 @@ def test_option_batch_workload_sampled(kind):
                                   tol=cfg["tol"], nthreads=8)
             assert iters[i] == ref["iters"]
             assert normwise(got, ref["U"]) <= 1e-10
+
+
+def test_batch_rejects_grids_beyond_limit():
+    """Batched options keep the factorisation in registers: at most 4096 nodes."""
+    cuda()
+    opts = _small_batch()
+    big = dict(opts[0], M=4097)
+    with pytest.raises(bsp.BsError):
+        bsp.parareal_solve_batch([opts[1], big], bsp.COARSE_IE, 1e-8)

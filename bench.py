@@ -73,6 +73,7 @@ def measured_traffic(shapes, M):
     if shapes is None or list(shapes.get("fine") or []) != t.get("fine_shape"):
         return None
     return {"bytes_per_system": t["hbm_bytes_per_system"],
+            "bytes_per_launch": t.get("hbm_bytes_per_launch", 0.0),
             "source": os.path.relpath(TRAFFIC_FILE, ROOT)}
 
 
@@ -112,12 +113,18 @@ def main():
     log(f"[bench] device {torch.cuda.get_device_name(dev)}; workload {cfg['name']}")
 
     if args.calibrate_copy > 0:
+        # Two plain copies of known size: the vectorised one (16+ bytes per
+        # lane) and, through a buffer offset by one element, the scalar one
+        # (8 bytes per lane, consecutive lanes on consecutive doubles: the
+        # access pattern of the solver's staged loads and stores).
         n = args.calibrate_copy * (1 << 20) // 8
-        src = torch.rand(n, dtype=torch.float64, device=dev)
+        src = torch.rand(n + 1, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
-        torch.neg(src, out=dst)  # reads 8n bytes, writes 8n bytes
+        torch.neg(src[:n], out=dst[:n])
         torch.cuda.synchronize()
-        log(f"[bench] calibration copy: {n} doubles ({8 * n} bytes read, {8 * n} written)")
+        torch.neg(src[1:], out=dst[1:])
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copies: {n} doubles each ({8 * n} bytes read, {8 * n} written)")
         del src, dst
 
     shapes = None
@@ -174,6 +181,8 @@ def main():
     # and writes F of it, M doubles each way
     sys_per_launch = prof["fine_cells"] / (M * Sf) / max(prof["fine_launches"], 1)
     alg_bytes = 16.0 * M * sys_per_launch
+    # the launch queued after the converged iteration propagates nothing
+    real_frac = sum(iters_all) / max(prof["fine_launches"], 1)
     traffic = measured_traffic(shapes, M)
     sweep_ms = prof["sweep_ms"] / max(prof["sweep_launches"], 1)
 
@@ -192,8 +201,11 @@ def main():
         "time_to_solution_ms": ms_per_step,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
+                     # scaled HBM bytes per F launch: per-system bytes x systems per
+                     # launch + the per-launch bytes of the propagating launches
                      "traffic": (None if traffic is None
-                                 else traffic["bytes_per_system"] * sys_per_launch),
+                                 else traffic["bytes_per_system"] * sys_per_launch
+                                 + traffic["bytes_per_launch"] * real_frac),
                      "kernel": "k_theta_batch (Crank-Nicolson F)",
                      "avg_launch_ms": f_ms, "launches_per_step": prof["fine_launches"] / args.steps,
                      "systems_per_launch": sys_per_launch, "flops_per_cell": FLOPS_PER_CELL,

@@ -3,6 +3,7 @@
 // launch, one 16-byte read-back of the defect per iteration).
 #include <cmath>
 #include <cstdarg>
+#include <vector>
 #include <cstdio>
 #include <cstring>
 
@@ -117,12 +118,37 @@ static int propagate_checked(const bs_params* prm, const bs_grid* grid, int nsys
 }
 
 // ----------------------------------------------------------- profiling
+// F and sweep launches of parareal_iterate / parareal_solve are bracketed by
+// events on the solve's stream (three per enqueued iteration), read back once
+// the call has synchronised.
 struct Profile {
     bool on = false;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    std::vector<hipEvent_t> ev;
     double fine_ms = 0, fine_launches = 0, fine_cells = 0, sweep_ms = 0, sweep_launches = 0;
 };
 static Profile g_prof;
+
+static int prof_reserve(int slots) {
+    while ((int)g_prof.ev.size() < 3 * slots) {
+        hipEvent_t e;
+        BSP_HIP(hipEventCreate(&e));
+        g_prof.ev.push_back(e);
+    }
+    return BS_OK;
+}
+
+// Adds iteration slot `slot` to the profile; cells: fine cell updates it did.
+static int prof_collect(int slot, double cells) {
+    float f_ms = 0.f, s_ms = 0.f;
+    BSP_HIP(hipEventElapsedTime(&f_ms, g_prof.ev[3 * slot], g_prof.ev[3 * slot + 1]));
+    BSP_HIP(hipEventElapsedTime(&s_ms, g_prof.ev[3 * slot + 1], g_prof.ev[3 * slot + 2]));
+    g_prof.fine_ms += f_ms;
+    g_prof.fine_launches += 1;
+    g_prof.fine_cells += cells;
+    g_prof.sweep_ms += s_ms;
+    g_prof.sweep_launches += 1;
+    return BS_OK;
+}
 
 }  // namespace bsp
 
@@ -135,8 +161,8 @@ const char* bs_last_error(void) { return g_err; }
 int bs_profile_enable(int on) {
     clear_error();
     if (on) {
-        for (auto& e : g_prof.ev)
-            if (!e) BSP_HIP(hipEventCreate(&e));
+        int rc = prof_reserve(1);
+        if (rc) return rc;
     }
     g_prof.on = on != 0;
     if (on) {
@@ -212,42 +238,83 @@ int parareal_start(const bs_params* prm, const bs_grid* grid, const bs_slices* s
     return launch_sweep(a, st);
 }
 
-static int iterate_impl(const bs_params* prm, const bs_grid* grid, const bs_slices* sl, int kind,
-                        void* ws, double* U, int k, double* defect, int* nonfinite,
-                        hipStream_t st) {
+// Enqueues iteration k (F over the slices that still change, then the
+// sweep) on st.  stop/hist/tol: device-side stopping of the asynchronous
+// solve (null for a single synchronous iteration).  slot: profiling slot.
+static int enqueue_iteration(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,
+                             int kind, void* ws, double* U, int k, int* stop, double* hist,
+                             double tol, int slot, hipStream_t st) {
     const int M = grid->M, N = sl->N;
     const OptionDev o = make_option(*prm, M);
     const double dT = prm->T / N;
     Workspace w = ws_layout(ws, M, N, kind);
     const int first = k - 1 < N - 1 ? k - 1 : N - 1;
     const bool prof = g_prof.on;
-    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[0], st));
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[3 * slot], st));
     int rc = launch_theta_batch(o, M, N - first, nullptr, 0.0, dT, first, dT / sl->fine_steps,
                                 sl->fine_steps, 0.5, 0, U + (long)first * M, M,
-                                w.Fv + (long)first * M, M, st);
+                                w.Fv + (long)first * M, M, st, stop);
     if (rc) return rc;
-    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[1], st));
-    SweepArgs a{o, M, N, first, sl->coarse_steps, kind, 0, dT, U, w.Fv, w.Gold, w.Vt, w.result};
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[3 * slot + 1], st));
+    SweepArgs a{o,      M,      N,      first,    sl->coarse_steps, kind, 0, dT, U, w.Fv,
+                w.Gold, w.Vt,   w.result, stop,   hist,             tol,  k};
     if ((rc = launch_sweep(a, st))) return rc;
-    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[2], st));
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[3 * slot + 2], st));
+    return BS_OK;
+}
+
+// Fine cell updates of iteration k.
+static double iteration_cells(const bs_grid* grid, const bs_slices* sl, int k) {
+    const int first = k - 1 < sl->N - 1 ? k - 1 : sl->N - 1;
+    return (double)(sl->N - first) * sl->fine_steps * grid->M;
+}
+
+static int iterate_impl(const bs_params* prm, const bs_grid* grid, const bs_slices* sl, int kind,
+                        void* ws, double* U, int k, double* defect, int* nonfinite,
+                        hipStream_t st) {
+    Workspace w = ws_layout(ws, grid->M, sl->N, kind);
+    int rc = enqueue_iteration(prm, grid, sl, kind, ws, U, k, nullptr, nullptr, 0.0, 0, st);
+    if (rc) return rc;
     double res[2];
     BSP_HIP(hipMemcpyAsync(res, w.result, sizeof(res), hipMemcpyDeviceToHost, st));
     BSP_HIP(hipStreamSynchronize(st));
-    if (prof) {
-        float f_ms = 0.f, s_ms = 0.f;
-        BSP_HIP(hipEventElapsedTime(&f_ms, g_prof.ev[0], g_prof.ev[1]));
-        BSP_HIP(hipEventElapsedTime(&s_ms, g_prof.ev[1], g_prof.ev[2]));
-        g_prof.fine_ms += f_ms;
-        g_prof.fine_launches += 1;
-        g_prof.fine_cells += (double)(N - first) * sl->fine_steps * M;
-        g_prof.sweep_ms += s_ms;
-        g_prof.sweep_launches += 1;
-    }
+    if (g_prof.on && (rc = prof_collect(0, iteration_cells(grid, sl, k)))) return rc;
     *defect = res[0];
     *nonfinite = res[1] != 0.0;
     if (*nonfinite) {
         set_error("non-finite value in the Parareal state at iteration %d", k);
         return BS_ERR_NONFINITE;
+    }
+    return BS_OK;
+}
+
+// Host-side state of the asynchronous solve, one per host thread (a solve
+// is synchronous, so a thread runs one at a time): the per-iteration record
+// in mapped pinned host memory that the sweep writes, and completion events.
+struct SolveState {
+    double* hist = nullptr;  // host view
+    double* hist_dev = nullptr;
+    size_t cap = 0;
+    std::vector<hipEvent_t> done;
+};
+static thread_local SolveState t_solve;
+
+static int solve_reserve(int kmax) {
+    SolveState& S = t_solve;
+    const size_t need = 2 * (size_t)(kmax + 1);
+    if (S.cap < need) {
+        if (S.hist) BSP_HIP(hipHostFree(S.hist));
+        S.hist = nullptr;
+        S.cap = 0;
+        BSP_HIP(hipHostMalloc((void**)&S.hist, need * sizeof(double),
+                              hipHostMallocMapped | hipHostMallocCoherent));
+        BSP_HIP(hipHostGetDevicePointer((void**)&S.hist_dev, S.hist, 0));
+        S.cap = need;
+    }
+    while ((int)S.done.size() < kmax + 1) {
+        hipEvent_t e;
+        BSP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        S.done.push_back(e);
     }
     return BS_OK;
 }
@@ -273,19 +340,64 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
     BSP_CHECK_ARG(max_iter >= 1, "max_iter must be >= 1");
     BSP_CHECK_ARG(tol >= 0, "tol must be >= 0");
     hipStream_t st = (hipStream_t)stream;
-    if ((rc = parareal_start(prm, grid, sl, kind, net, ws, ws_size, U, stream))) return rc;
-    const int kmax = max_iter < sl->N ? max_iter : sl->N;
+    const int N = sl->N;
+    const int kmax = max_iter < N ? max_iter : N;
     *iters = 0;
-    for (int k = 1; k <= kmax; ++k) {
-        double defect;
-        int bad;
-        rc = iterate_impl(prm, grid, sl, kind, ws, U, k, &defect, &bad, st);
-        *iters = k;
-        if (defect_hist) defect_hist[k - 1] = defect;
-        if (rc) return rc;
-        if (defect <= tol || k == sl->N) return BS_OK;
+    if ((rc = solve_reserve(kmax))) return rc;
+    if (g_prof.on && (rc = prof_reserve(kmax))) return rc;
+    SolveState& S = t_solve;
+    for (size_t i = 0; i < 2 * (size_t)(kmax + 1); ++i) S.hist[i] = 0.0;
+    Workspace w = ws_layout(ws, grid->M, N, kind);
+    int* stop = reinterpret_cast<int*>(w.result + 4);
+    if ((rc = parareal_start(prm, grid, sl, kind, net, ws, ws_size, U, stream))) return rc;
+    if ((rc = launch_set_int(stop, 0, st))) return rc;
+
+    // Iteration k+1 is queued before the host looks at iteration k, so the
+    // stream never waits for the host; the sweep that meets the stopping
+    // rule sets the device flag, which turns the one queued iteration after
+    // it into an empty launch pair.
+    const volatile double* hist = S.hist;
+    int status = BS_NOT_CONVERGED, last = 0, enq = 0;
+    auto decide = [&](int j) {
+        const double d = hist[2 * j], bad = hist[2 * j + 1];
+        if (defect_hist) defect_hist[j - 1] = d;
+        last = j;
+        if (bad != 0.0) {
+            status = BS_ERR_NONFINITE;
+            return true;
+        }
+        if (d <= tol || j == N) {
+            status = BS_OK;
+            return true;
+        }
+        return j == kmax;  // BS_NOT_CONVERGED
+    };
+    bool decided = false;
+    for (int k = 1; k <= kmax && !decided; ++k) {
+        if ((rc = enqueue_iteration(prm, grid, sl, kind, ws, U, k, stop, S.hist_dev, tol, k - 1,
+                                    st)))
+            return rc;
+        BSP_HIP(hipEventRecord(S.done[k], st));
+        enq = k;
+        if (k >= 2) {
+            BSP_HIP(hipEventSynchronize(S.done[k - 1]));
+            decided = decide(k - 1);
+        }
     }
-    return BS_NOT_CONVERGED;
+    if (!decided) {
+        BSP_HIP(hipEventSynchronize(S.done[enq]));
+        decide(enq);
+    }
+    BSP_HIP(hipStreamSynchronize(st));
+    *iters = last;
+    if (g_prof.on) {
+        for (int k = 1; k <= enq; ++k)
+            if ((rc = prof_collect(k - 1, k <= last ? iteration_cells(grid, sl, k) : 0.0)))
+                return rc;
+    }
+    if (status == BS_ERR_NONFINITE)
+        set_error("non-finite value in the Parareal state at iteration %d", last);
+    return status;
 }
 
 }  // extern "C"

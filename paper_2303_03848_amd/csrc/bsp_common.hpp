@@ -108,7 +108,8 @@ void reset_shape_overrides();
 int launch_theta_batch(const OptionDev& o, int M, int nsys, const double* tau0, double tau_start,
                        double tau_stride, int sys_offset, double dt, int steps, double theta,
                        int homog, const double* u_in, long ld_in, double* u_out, long ld_out,
-                       hipStream_t stream);
+                       hipStream_t stream,
+                       const int* stop = nullptr);
 
 struct SweepArgs {
     OptionDev o;
@@ -119,8 +120,18 @@ struct SweepArgs {
     double* Gold;                  // [N][M]
     const double* Vt;              // [N+1][M] or nullptr
     double* result;                // [0] defect, [1] non-finite flag (as double)
+    // Device-side stopping (asynchronous solve; all three may be null):
+    // the sweep returns at once while *stop is set, and on finishing
+    // iteration k it writes hist[2k] = defect, hist[2k+1] = non-finite and
+    // sets *stop when the iteration is the last one (defect <= tol or
+    // non-finite).
+    int* stop;
+    double* hist;
+    double tol;
+    int k;
 };
 int launch_sweep(const SweepArgs& a, hipStream_t stream);
+int launch_set_int(int* p, int v, hipStream_t stream);  // *p = v in stream order
 
 int launch_initial(const OptionDev& o, int M, int payoff_mode, double* u0, hipStream_t stream);
 

@@ -47,13 +47,39 @@ struct ThetaArgs {
     long ld_in;
     double* u_out;
     long ld_out;
+    const int* stop;  // when non-null and set, the launch does nothing
 };
+
+__device__ __forceinline__ bool stopped(const int* stop) {
+    return stop && *(volatile const int*)stop;
+}
+
+__global__ void k_set_int(int* p, int v) { *p = v; }
+
+int launch_set_int(int* p, int v, hipStream_t stream) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, stream, p, v);
+    BSP_LAUNCHED();
+    return BS_OK;
+}
+
+// Iteration record of the asynchronous solve (thread 0, after block_defect).
+__device__ __forceinline__ void sweep_record(const SweepArgs& a, double dmax, int bad) {
+    a.result[0] = dmax;
+    a.result[1] = bad ? 1.0 : 0.0;
+    if (a.hist) {  // host memory: visible to the host once the launch completes
+        a.hist[2 * a.k] = dmax;
+        a.hist[2 * a.k + 1] = bad ? 1.0 : 0.0;
+        __threadfence_system();
+    }
+    if (a.stop && (bad || dmax <= a.tol)) *a.stop = 1;
+}
 
 template <int T, int MC>
 __global__ __launch_bounds__(T) void k_theta_batch(ThetaArgs a) {
     __shared__ double smem[smem_doubles<T>()];
     double* lds = smem;
     double* ftab = smem + 4 * T;
+    if (stopped(a.stop)) return;
     const int sys = blockIdx.x;
     double V[MC];
     load_system<T, MC>(a.u_in + (long)sys * a.ld_in, a.M, V, smem);
@@ -74,6 +100,7 @@ template <int T, int MC>
 __global__ __launch_bounds__(T) void k_sweep(SweepArgs a) {
     __shared__ double lds[4 * T];
     __shared__ double ftab[2 * kForceChunk];
+    if (stopped(a.stop)) return;
     Solver<T, MC> S;
     S.setup(a.o.s2, a.o.r, a.dT / (double)a.coarse_steps, 0.0, a.M, lds);
     double dmax = 0.0;
@@ -82,10 +109,7 @@ __global__ __launch_bounds__(T) void k_sweep(SweepArgs a) {
                         a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad);
     if (!a.predict) {
         block_defect<T>(dmax, bad, lds);
-        if (threadIdx.x == 0) {
-            a.result[0] = dmax;
-            a.result[1] = bad ? 1.0 : 0.0;
-        }
+        if (threadIdx.x == 0) sweep_record(a, dmax, bad);
     }
 }
 
@@ -100,6 +124,7 @@ __global__ __launch_bounds__(T) void k_large_theta(ThetaArgs a, const double* __
                                                    const double* __restrict__ ptab) {
     __shared__ double lds[4 * T];
     __shared__ double ftab[2 * kForceChunk];
+    if (stopped(a.stop)) return;
     const int sys = blockIdx.x;
     BlockTriG<T, MC> S;
     S.load(tab, ptab, a.o.s2, a.o.r, a.theta * a.dt, (1.0 - a.theta) * a.dt, a.M);
@@ -119,6 +144,7 @@ __global__ __launch_bounds__(T) void k_large_sweep(SweepArgs a, const double* __
                                                    const double* __restrict__ ptab) {
     __shared__ double lds[4 * T];
     __shared__ double ftab[2 * kForceChunk];
+    if (stopped(a.stop)) return;
     BlockTriG<T, MC> S;
     S.load(tab, ptab, a.o.s2, a.o.r, a.dT / (double)a.coarse_steps, 0.0, a.M);
     double dmax = 0.0;
@@ -127,10 +153,7 @@ __global__ __launch_bounds__(T) void k_large_sweep(SweepArgs a, const double* __
                         a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad);
     if (!a.predict) {
         block_defect<T>(dmax, bad, lds);
-        if (threadIdx.x == 0) {
-            a.result[0] = dmax;
-            a.result[1] = bad ? 1.0 : 0.0;
-        }
+        if (threadIdx.x == 0) sweep_record(a, dmax, bad);
     }
 }
 
@@ -236,11 +259,11 @@ void reset_shape_overrides() { g_nover[0] = g_nover[1] = 0; }
 int launch_theta_batch(const OptionDev& o, int M, int nsys, const double* tau0, double tau_start,
                        double tau_stride, int sys_offset, double dt, int steps, double theta,
                        int homog, const double* u_in, long ld_in, double* u_out, long ld_out,
-                       hipStream_t stream) {
+                       hipStream_t stream, const int* stop) {
     if (nsys == 0) return BS_OK;
     const TriShape sh = shape_for(0, M);
-    ThetaArgs a{o, M, steps, homog, sys_offset, tau0, tau_start, tau_stride, dt, theta, u_in, ld_in,
-                u_out, ld_out};
+    ThetaArgs a{o,     M,           steps, homog, sys_offset, tau0, tau_start,
+                tau_stride, dt, theta, u_in,  ld_in, u_out,     ld_out, stop};
     if (is_large(sh)) {
         double *tab, *ptab;
         int rc = large_tables(0, &tab, &ptab);

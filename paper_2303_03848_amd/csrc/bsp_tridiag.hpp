@@ -35,8 +35,8 @@
 // u_q (upper, super-diagonal c_q), with kappa folded into the backward sweep:
 // per node a step costs 1 forward, 2 backward and 3 update operations.
 //
-// Exchanges: unit shifts use DPP lane moves and longer strides ds_bpermute,
-// with no LDS and no barrier.  Lanes whose partner lies outside the
+// Exchanges: strides 1, 2, 4 use (chained) DPP lane moves, longer strides
+// ds_bpermute, with no LDS and no barrier.  Lanes whose partner lies outside the
 // wavefront carry a zero PCR multiplier, so the (wrapped, finite) value they
 // fetch does not contribute.  Nodes beyond M are identity rows, decoupled
 // from the rest, and keep their value (kappa - mu = 1).
@@ -58,16 +58,30 @@ __device__ __forceinline__ double lane_fetch(double v, int src) {
 }
 
 // DPP wavefront shifts by one lane: lane i receives lane i-1 (from_prev) or
-// lane i+1 (from_next); the lane without a source receives 0.
+// lane i+1 (from_next); the lane without a source receives 0 (bound control).
+// Shifts by 2 and 4 chain these moves: a few cycles each, against a round
+// trip through the LDS crossbar for ds_bpermute.
 __device__ __forceinline__ double dpp_from_prev(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double dpp_from_next(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
+}
+template <int S>
+__device__ __forceinline__ double dpp_prev_n(double v) {
+#pragma unroll
+    for (int i = 0; i < S; ++i) v = dpp_from_prev(v);
+    return v;
+}
+template <int S>
+__device__ __forceinline__ double dpp_next_n(double v) {
+#pragma unroll
+    for (int i = 0; i < S; ++i) v = dpp_from_next(v);
+    return v;
 }
 
 // Wavefront-uniform copy of an int (lives in a scalar register).
@@ -196,10 +210,16 @@ struct BlockTri {
     int p, nst;
 
     __device__ __forceinline__ double up(double x, int s) const {
-        return s == 1 ? dpp_from_prev(x) : lane_fetch(x, p - s);
+        if (s == 1) return dpp_from_prev(x);
+        if (s == 2) return dpp_prev_n<2>(x);
+        if (s == 4) return dpp_prev_n<4>(x);
+        return lane_fetch(x, p - s);
     }
     __device__ __forceinline__ double down(double x, int s) const {
-        return s == 1 ? dpp_from_next(x) : lane_fetch(x, p + s);
+        if (s == 1) return dpp_from_next(x);
+        if (s == 2) return dpp_next_n<2>(x);
+        if (s == 4) return dpp_next_n<4>(x);
+        return lane_fetch(x, p + s);
     }
 
     // h = theta*dt > 0 (implicit weight), e = (1-theta)*dt (explicit weight).

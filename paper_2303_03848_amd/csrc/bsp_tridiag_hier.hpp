@@ -39,10 +39,16 @@ struct BlockTriH {
     mutable int par;  // step parity: double-buffered exchange slots
 
     __device__ __forceinline__ double up(double x, int s) const {
-        return s == 1 ? dpp_from_prev(x) : lane_fetch(x, lane - s);
+        if (s == 1) return dpp_from_prev(x);
+        if (s == 2) return dpp_prev_n<2>(x);
+        if (s == 4) return dpp_prev_n<4>(x);
+        return lane_fetch(x, lane - s);
     }
     __device__ __forceinline__ double down(double x, int s) const {
-        return s == 1 ? dpp_from_next(x) : lane_fetch(x, lane + s);
+        if (s == 1) return dpp_from_next(x);
+        if (s == 2) return dpp_next_n<2>(x);
+        if (s == 4) return dpp_next_n<4>(x);
+        return lane_fetch(x, lane + s);
     }
 
     // Level-2 reduction of one right-hand side (zero at lane 63).  Lanes whose

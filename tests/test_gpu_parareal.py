@@ -170,3 +170,26 @@ def test_large_put_workload_sampled():
         Fn = oracle.fine(po, M, n * dT, dT, Sf, U[n])
         # at convergence the iterate is the fine fixed point up to the stopping tolerance
         assert np.max(np.abs(U[n + 1] - Fn)) <= 100 * cfg["tol"] + 1e-10 * scale, n
+
+
+def test_solve_stops_at_max_iter_and_repeats():
+    """The queued-ahead solve: a max_iter cut returns BS_NOT_CONVERGED with the
+    iterate of exactly that iteration (the queued iteration after it does
+    nothing), and a second solve on the same object repeats the first."""
+    cuda()
+    cfg = SMALL_CALL
+    M, N, Sf = cfg["M"], cfg["N"], cfg["fine_steps"]
+    say("solve max_iter=3 and repeat, small call")
+    ref = oracle.parareal(_oracle_params(cfg), M, N, Sf, 1, oracle.COARSE_IE, tol=0.0, max_iter=3)
+    pr = bsp.Parareal(option_params(cfg), M, N, Sf, 1, bsp.COARSE_IE)
+    for _ in range(2):
+        iters, defects, rc = pr.solve(0.0, max_iter=3)
+        assert iters == 3 and rc == bsp.BS_NOT_CONVERGED
+        np.testing.assert_allclose(defects, ref["defects"][:3], rtol=0,
+                                   atol=1e-12 * np.abs(ref["U"]).max())
+        assert normwise(pr.U.cpu().numpy(), ref["U"]) <= 1e-12
+    # then to convergence on the same object
+    iters, _, rc = pr.solve(cfg["tol"])
+    ref2 = oracle.parareal(_oracle_params(cfg), M, N, Sf, 1, oracle.COARSE_IE, tol=cfg["tol"])
+    assert rc == bsp.BS_OK and iters == ref2["iters"]
+    assert normwise(pr.U.cpu().numpy(), ref2["U"]) <= 1e-12

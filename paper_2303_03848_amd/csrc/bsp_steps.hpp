@@ -2,6 +2,8 @@
 // chunk loads/stores, a run of theta-steps, and the serial Parareal sweep.
 #pragma once
 
+#include <type_traits>
+
 #include "bsp_common.hpp"
 #include "bsp_tridiag.hpp"
 #include "bsp_tridiag_hier.hpp"
@@ -92,10 +94,77 @@ __device__ __forceinline__ void store_system(double* __restrict__ dst, int M, co
 // at S = 0 and S = S_max, is tabulated in LDS for a chunk of steps by all
 // threads in parallel, so the sequential step loop evaluates no exponential.
 // ftab: 2 * kForceChunk doubles of LDS.
+template <class S>
+struct IsWaveSolver : std::false_type {};
+template <int MC>
+struct IsWaveSolver<BlockTri<64, MC>> : std::true_type {};
+
+// One-wavefront blocks: the pipelined steps of BlockTri (pipe_begin /
+// pipe_step / pipe_end), with the reduction stage count as a compile-time
+// constant so that the reduction and the next forward sweep share one
+// straight-line block.  The forcing tables here hold steps m0+1 .. m0+n+1
+// (each step also needs the next step's forcing); entries past the last
+// step are zero.
+template <int MC, bool EX, int NST>
+__device__ __forceinline__ void piped_run(const BlockTri<64, MC>& S, const OptionDev& o,
+                                          double (&V)[MC], double tau0, double dt, int steps,
+                                          double theta, bool homog, double* ftab) {
+    constexpr int T = 64, CH = kForceChunk - 1;
+    const double h = theta * dt, e = (1.0 - theta) * dt;
+    auto fill = [&](int m0, int n) {  // entries i = 0..n: step m0 + 1 + i
+        __syncthreads();
+        for (int i = threadIdx.x; i <= n; i += T) {
+            const int m = m0 + 1 + i;
+            double lo = 0.0, hi = 0.0;
+            if (m <= steps) {
+                double lo0, hi0, lo1, hi1;
+                dirichlet(o, exp(-o.r * (tau0 + (double)(m - 1) * dt)), lo0, hi0);
+                dirichlet(o, exp(-o.r * (tau0 + (double)m * dt)), lo1, hi1);
+                lo = fma(e, lo0, h * lo1);
+                hi = fma(e, hi0, h * hi1);
+            }
+            ftab[i] = lo;
+            ftab[kForceChunk + i] = hi;
+        }
+        __syncthreads();
+    };
+    typename BlockTri<64, MC>::Pipe P;
+    int n = min(CH, steps);
+    if (!homog) fill(0, n);
+    S.pipe_begin(V, homog ? 0.0 : ftab[0], homog ? 0.0 : ftab[kForceChunk], P);
+    for (int m0 = 0; m0 < steps;) {
+        double lo = homog ? 0.0 : ftab[0], hi = homog ? 0.0 : ftab[kForceChunk];
+        for (int i = 0; i < n; ++i) {
+            const double lo_n = homog ? 0.0 : ftab[i + 1];
+            const double hi_n = homog ? 0.0 : ftab[kForceChunk + i + 1];
+            S.template pipe_step<EX, NST>(P, lo, hi, lo_n, hi_n);
+            lo = lo_n;
+            hi = hi_n;
+        }
+        m0 += n;
+        if (m0 < steps) {
+            n = min(CH, steps - m0);
+            if (!homog) fill(m0, n);
+        }
+    }
+    S.pipe_end(P, V);
+}
+
 template <int T, int MC, bool EX, class Solver>
 __device__ __forceinline__ void theta_steps(const Solver& S, const OptionDev& o,
                                             double (&V)[MC], double tau0, double dt, int steps,
                                             double theta, bool homog, double* lds, double* ftab) {
+    if constexpr (IsWaveSolver<Solver>::value) {
+        (void)lds;
+        switch (S.nst) {
+            case 0: piped_run<MC, EX, 0>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+            case 1: piped_run<MC, EX, 1>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+            case 2: piped_run<MC, EX, 2>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+            case 3: piped_run<MC, EX, 3>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+            default: piped_run<MC, EX, -1>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+        }
+        return;
+    }
     const double h = theta * dt, e = (1.0 - theta) * dt;
     for (int m0 = 0; m0 < steps; m0 += kForceChunk) {
         const int nch = min(kForceChunk, steps - m0);

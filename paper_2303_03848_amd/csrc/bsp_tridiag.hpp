@@ -207,6 +207,7 @@ struct BlockTri {
     Forcing fc;
     double aq, cq, kap, mu;         // interface row: sub/super diagonal; step constants
     double k1[LOGT], k2[LOGT], invB;
+    double al[NI], be[NI];          // L~^{-1} v, L~^{-1} w (pipelined steps)
     int p, nst;
 
     __device__ __forceinline__ double up(double x, int s) const {
@@ -271,6 +272,126 @@ struct BlockTri {
         }
         invB = 1.0 / B;
         nst = wave_uniform(nst);
+        // forward-swept interface responses for the pipelined steps
+        al[0] = lu.v[0];
+        be[0] = lu.w[0];
+#pragma unroll
+        for (int q = 1; q < NI; ++q) {
+            al[q] = fma(-lu.l[q], al[q - 1], lu.v[q]);
+            be[q] = fma(-lu.l[q], be[q - 1], lu.w[q]);
+        }
+    }
+
+    // ---------------------------------------------------------------------
+    // Pipelined steps.  With L~ the unit lower factor of the interior block,
+    // the forward sweep of step m+1 is
+    //   y = L~^{-1} (V^m + f^{m+1}/kappa) = yP + z_{p-1} al + z_p be,
+    //   yP = L~^{-1} (P^m + f^{m+1}/kappa),  al = L~^{-1} v,  be = L~^{-1} w,
+    // where P^m is step m's interior value before its interface correction
+    // (V^m = P^m + z_{p-1} v + z_p w).  yP depends only on P^m, so its
+    // sweep runs while step m's interface reduction waits on lane exchanges;
+    // once z is known, y is two independent FMAs per node.  The interior
+    // state itself is never formed between steps: where -mu V^m is needed it
+    // is rebuilt from the forward sweep, V_q = y_q + l_q y_{q-1} - f_q/kappa.
+    struct Pipe {
+        double A[MC];     // yP of the coming step (interior entries)
+        double z, zl;     // interface values of the last step (own, left)
+        double Vi;        // the interface node's value
+    };
+
+    // Adds t * bhi to entry r_hi of the chunk holding row M-1 as an interior row.
+    __device__ __forceinline__ void add_hi(double (&B)[MC], double t) const {
+        if (fc.hi_in) {
+#pragma unroll
+            for (int q = 0; q < NI; ++q) B[q] += (q == fc.r_hi) ? t : 0.0;
+        }
+    }
+
+    // Starts a run from state V; flo, fhi: forcing of the first step.
+    __device__ __forceinline__ void pipe_begin(const double (&V)[MC], double flo, double fhi,
+                                               Pipe& P) const {
+        double B[MC];
+#pragma unroll
+        for (int q = 0; q < MC; ++q) B[q] = V[q];
+        add_hi(B, fc.bhi * fhi);
+        P.A[0] = fma(fc.blo, flo, B[0]);
+#pragma unroll
+        for (int q = 1; q < NI; ++q) P.A[q] = fma(-lu.l[q], P.A[q - 1], B[q]);
+        P.z = 0.0;
+        P.zl = 0.0;
+        P.Vi = V[MC - 1];
+    }
+
+    // One step: flo, fhi its forcing; flo_n, fhi_n the next step's (zero
+    // after the last step).  NST: reduction stages (>= 0 compile-time, no
+    // branches; -1: nst at run time).
+    template <bool EX, int NST>
+    __device__ __forceinline__ void pipe_step(Pipe& P, double flo, double fhi, double flo_n,
+                                              double fhi_n) const {
+        double y[MC], B[MC];
+#pragma unroll
+        for (int q = 0; q < NI; ++q) y[q] = fma(P.zl, al[q], fma(P.z, be[q], P.A[q]));
+        // backward sweep; B = x - mu V^{m-1} (V rebuilt from y before y is consumed)
+        double xn = lu.ku[NI - 1] * y[NI - 1];
+        const double xl = xn;
+#pragma unroll
+        for (int q = NI - 1; q >= 0; --q) {
+            const double x = (q == NI - 1) ? xn : fma(-lu.cu[q], xn, lu.ku[q] * y[q]);
+            if constexpr (EX) {
+                const double t = (q > 0) ? fma(lu.l[q], y[q - 1], y[q]) : y[0];
+                B[q] = fma(-mu, t, x);
+            } else {
+                B[q] = x;
+            }
+            xn = x;
+        }
+        const double yF = dpp_from_next(xn);  // x_0 of the next chunk
+        double D = fma(kap, P.Vi, fma(fc.bhiD, fhi, fma(-aq, xl, -cq * yF)));
+        if constexpr (EX) {
+            // the rebuilt V carried this step's forcing: give its -mu share back
+            B[0] = fma(mu * fc.blo, flo, B[0]);
+            add_hi(B, mu * fc.bhi * fhi);
+        }
+        // interface reduction
+        if constexpr (NST >= 0) {
+#pragma unroll
+            for (int k = 0; k < NST; ++k) {
+                const int s = 1 << k;
+                const double Dm = up(D, s);
+                const double Dp = down(D, s);
+                D = fma(-k1[k], Dm, fma(-k2[k], Dp, D));
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < LOGT; ++k) {
+                if (k < nst) {
+                    const int s = 1 << k;
+                    const double Dm = up(D, s);
+                    const double Dp = down(D, s);
+                    D = fma(-k1[k], Dm, fma(-k2[k], Dp, D));
+                }
+            }
+        }
+        // next step's forward sweep on B: independent of the reduction above
+        add_hi(B, fc.bhi * fhi_n);
+        P.A[0] = fma(fc.blo, flo_n, B[0]);
+#pragma unroll
+        for (int q = 1; q < NI; ++q) P.A[q] = fma(-lu.l[q], P.A[q - 1], B[q]);
+        const double z = D * invB;
+        P.zl = dpp_from_prev(z);
+        P.z = z;
+        P.Vi = EX ? fma(-mu, P.Vi, z) : z;
+    }
+
+    // Ends a run (the last pipe_step had zero next-step forcing): V = state.
+    __device__ __forceinline__ void pipe_end(const Pipe& P, double (&V)[MC]) const {
+        double y[MC];
+#pragma unroll
+        for (int q = 0; q < NI; ++q) y[q] = fma(P.zl, al[q], fma(P.z, be[q], P.A[q]));
+        V[0] = y[0];
+#pragma unroll
+        for (int q = 1; q < NI; ++q) V[q] = fma(lu.l[q], y[q - 1], y[q]);
+        V[MC - 1] = P.Vi;
     }
 
     // One step.  V: this chunk (in/out).  flo, fhi: boundary forcing

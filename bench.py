@@ -92,6 +92,9 @@ def main():
                     help="pin the F block shape (threads, nodes per thread) instead of tuning")
     ap.add_argument("--sweep-shape", type=int, nargs=2, metavar=("T", "MC"),
                     help="pin the sweep block shape instead of tuning")
+    ap.add_argument("--all-workloads", action="store_true",
+                    help="also measure the small call, a training step, the 512-option batch "
+                         "and the 16384-node put (reported under other_workloads)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain elementwise copy of MIB MiB (float64) so a "
                          "counter profile of this command has a copy kernel of known size")
@@ -256,6 +259,11 @@ def main():
         comp["speedup_bound_eq8"] = 1.0 / ((1 + K_it / N) * c_c / c_f + K_it / N)
         comp["speedup_vs_serial_fine"] = comp["serial_fine_gpu_ms"] / ms_per_step
         out["comparisons"] = comp
+
+    if args.all_workloads:
+        from paper_2303_03848_amd.workload_bench import measure_all
+        bsp.bs_tune_reset()  # the other workloads use the default block shapes
+        out["other_workloads"] = measure_all(log)
 
     if not args.no_cpu_baseline:
         import oracle

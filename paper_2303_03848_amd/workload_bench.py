@@ -1,0 +1,146 @@
+"""Measurements of the workloads besides the headline one (one GPU): the
+small call, one training step of the residual loss, the batch of 512
+options and the 16384-node put.  Used by ``bench.py --all-workloads``; every
+number comes from the library's kernels, timed with events on the current
+stream after a warm-up.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+import paper_2303_03848_amd as bsp
+from workloads import (LARGE_PUT, OPTION_BATCH, SMALL_CALL, TRAIN_STEP, collocation, option_batch,
+                       option_params, xavier_normal)
+
+FP32_VALU_PEAK = 157.3e12
+BF16_MFMA_PEAK = 2.5e15
+
+
+def _timed(fn, reps: int) -> float:
+    """Mean milliseconds of fn() over reps calls after one warm-up call."""
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / reps
+
+
+def parareal_cells(M: int, N: int, Sf: int, iters: int) -> float:
+    """Fine cell-updates of a Parareal solve of `iters` iterations (slices
+    n < k-1 are not propagated in iteration k)."""
+    return float(sum((N - min(k - 1, N - 1)) * Sf * M for k in range(1, iters + 1)))
+
+
+def small_call() -> dict:
+    cfg = SMALL_CALL
+    p, M, N, Sf = option_params(cfg), cfg["M"], cfg["N"], cfg["fine_steps"]
+    pr = bsp.Parareal(p, M, N, Sf, 1, bsp.COARSE_IE)
+    it = [0]
+
+    def solve():
+        it[0] = pr.solve(cfg["tol"])[0]
+
+    ms = _timed(solve, 20)
+    return {"workload": cfg["name"], "coarse": "implicit_euler", "time_to_solution_ms": ms,
+            "iters": it[0], "cell_updates_per_s": parareal_cells(M, N, Sf, it[0]) / (ms / 1e3)}
+
+
+def train_step() -> dict:
+    """One minibatch of the residual loss, forward and hand-written backward
+    (no optimiser update), FP32 and BF16-MFMA."""
+    cfg = TRAIN_STEP
+    p = option_params(cfg)
+    d, w = cfg["depth"], cfg["width"]
+    nf, ne, nb = cfg["batch_f"], cfg["batch_e"], cfg["batch_b"]
+    Xf, Xe, Xb = collocation(nf, ne, nb, p["T"], p["s_max"] / p["K"])
+    Xf, Xe, Xb = (torch.tensor(a, dtype=torch.float32, device="cuda") for a in (Xf, Xe, Xb))
+    theta = torch.tensor(xavier_normal(cfg["n_in"], d, w, 0), device="cuda")
+    # algorithmic flops: 4 derivative streams forward and 2x backward for the
+    # interior points, the value stream for terminal and boundary points,
+    # through the (d - 1) hidden w x w products
+    flops = 3 * 2 * w * w * (d - 1) * (4 * nf + ne + nb)
+    out = {"workload": cfg["name"], "network": f"{d}x{w} tanh",
+           "points": [nf, ne, nb], "flops_per_step": flops}
+    for name, prec, peak in (("fp32", bsp.PREC_FP32, FP32_VALU_PEAK),
+                             ("bf16", bsp.PREC_BF16, BF16_MFMA_PEAK)):
+        net = bsp.PinnNet(theta, cfg["n_in"], d, w, prec)
+        ws = torch.empty(bsp.pinn_residual_workspace_size(net, nf, ne, nb), dtype=torch.uint8,
+                         device="cuda")
+        loss3 = torch.empty(3, dtype=torch.float32, device="cuda")
+        grad = torch.empty_like(theta)
+        ms = _timed(lambda: bsp.pinn_residual_fwd_bwd(net, p, Xf, Xe, Xb, ws, loss3, grad), 50)
+        out[name] = {"ms_per_step": ms, "tflops": flops / (ms / 1e3) / 1e12,
+                     "frac_of_peak": flops / (ms / 1e3) / peak,
+                     "peak": "FP32 vector 157.3 TFLOP/s" if name == "fp32"
+                     else "BF16 dense MFMA 2.5 PFLOP/s"}
+    return out
+
+
+def batch_options(n_opt: int | None = None) -> dict:
+    """The batch of options, numerical coarse, one launch per phase and block
+    shape with hipGraph replay."""
+    cfg = OPTION_BATCH
+    opts = option_batch(cfg, n_opt=n_opt)
+    for o in opts:
+        o["fine_steps"] = cfg["fine_steps"]
+        o["coarse_steps"] = cfg["coarse_steps"]
+    res = {}
+
+    def solve():
+        _, _, iters, _, _ = bsp.parareal_solve_batch(opts, bsp.COARSE_IE, cfg["tol"])
+        res["iters"] = iters
+
+    ms = _timed(solve, 2)
+    iters = np.array(res["iters"])
+    cells = sum(parareal_cells(o["M"], o["N"], o["fine_steps"], int(k))
+                for o, k in zip(opts, iters))
+    serial = sum(float(o["N"] * o["fine_steps"] * o["M"]) for o in opts)
+    return {"workload": cfg["name"], "options": len(opts), "coarse": "implicit_euler",
+            "time_ms": ms, "iters_mean": float(iters.mean()), "iters_min": int(iters.min()),
+            "iters_max": int(iters.max()), "cell_updates_per_s": cells / (ms / 1e3),
+            "serial_fine_cells": serial}
+
+
+def large_put() -> dict:
+    cfg = LARGE_PUT
+    p, M, N, Sf = option_params(cfg), cfg["M"], cfg["N"], cfg["fine_steps"]
+    pr = bsp.Parareal(p, M, N, Sf, 1, bsp.COARSE_IE)
+    it = [0]
+
+    def solve():
+        it[0] = pr.solve(cfg["tol"])[0]
+
+    ms = _timed(solve, 1)
+    # the network on the whole (N+1) x M grid, BF16 MFMA, seeded weights
+    d, w = cfg["depth"], cfg["width"]
+    net = bsp.PinnNet(torch.tensor(xavier_normal(cfg["n_in"], d, w, 0), device="cuda"),
+                      cfg["n_in"], d, w, bsp.PREC_BF16)
+    from paper_2303_03848_amd.pinn import grid_values
+    grid_values(net, p, M, N)  # builds the inputs once (host side) and warms up
+    S = (np.arange(1, M + 1) * (p["s_max"] / (M + 1))) / p["K"]
+    taus = np.arange(N + 1) * (p["T"] / N)
+    T, X = np.meshgrid(taus, S, indexing="ij")
+    X = torch.tensor(np.stack([T.ravel(), X.ravel()], 1), dtype=torch.float32, device="cuda")
+    out32 = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
+    mlp_ms = _timed(lambda: bsp.pinn_forward(net, X, out32), 5)
+    mlp_flops = 2.0 * (cfg["n_in"] * w + (d - 1) * w * w + w) * X.shape[0]
+    return {"workload": cfg["name"], "coarse": "implicit_euler", "time_to_solution_ms": ms,
+            "iters": it[0], "cell_updates_per_s": parareal_cells(M, N, Sf, it[0]) / (ms / 1e3),
+            "network_grid_eval": {"network": f"{d}x{w} tanh bf16", "points": int(X.shape[0]),
+                                  "ms": mlp_ms, "tflops": mlp_flops / (mlp_ms / 1e3) / 1e12,
+                                  "mfma_frac": mlp_flops / (mlp_ms / 1e3) / BF16_MFMA_PEAK}}
+
+
+def measure_all(log=print) -> dict:
+    out = {}
+    for name, fn in (("small_call", small_call), ("train_step", train_step),
+                     ("option_batch", batch_options), ("large_put", large_put)):
+        t0 = time.time()
+        out[name] = fn()
+        log(f"[workloads] {name}: {time.time() - t0:.1f}s {out[name]}")
+    return out

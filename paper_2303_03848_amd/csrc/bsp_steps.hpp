@@ -105,7 +105,7 @@ struct IsWaveSolver<BlockTri<64, MC>> : std::true_type {};
 // straight-line block.  The forcing tables here hold steps m0+1 .. m0+n+1
 // (each step also needs the next step's forcing); entries past the last
 // step are zero.
-template <int MC, bool EX, int NST>
+template <int MC, bool EX, int NST, bool HI>
 __device__ __forceinline__ void piped_run(const BlockTri<64, MC>& S, const OptionDev& o,
                                           double (&V)[MC], double tau0, double dt, int steps,
                                           double theta, bool homog, double* ftab) {
@@ -137,7 +137,7 @@ __device__ __forceinline__ void piped_run(const BlockTri<64, MC>& S, const Optio
         for (int i = 0; i < n; ++i) {
             const double lo_n = homog ? 0.0 : ftab[i + 1];
             const double hi_n = homog ? 0.0 : ftab[kForceChunk + i + 1];
-            S.template pipe_step<EX, NST>(P, lo, hi, lo_n, hi_n);
+            S.template pipe_step<EX, NST, HI>(P, lo, hi, lo_n, hi_n);
             lo = lo_n;
             hi = hi_n;
         }
@@ -156,12 +156,25 @@ __device__ __forceinline__ void theta_steps(const Solver& S, const OptionDev& o,
                                             double theta, bool homog, double* lds, double* ftab) {
     if constexpr (IsWaveSolver<Solver>::value) {
         (void)lds;
-        switch (S.nst) {
-            case 0: piped_run<MC, EX, 0>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
-            case 1: piped_run<MC, EX, 1>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
-            case 2: piped_run<MC, EX, 2>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
-            case 3: piped_run<MC, EX, 3>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
-            default: piped_run<MC, EX, -1>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+        // HI: row M-1 lies inside a chunk (grid not a multiple of MC) and
+        // carries forcing; homogeneous runs have none.
+        const bool hi = !homog && S.fc.r_hi != MC - 1;
+        if (hi) {
+            switch (S.nst) {
+                case 0: piped_run<MC, EX, 0, true>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+                case 1: piped_run<MC, EX, 1, true>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+                case 2: piped_run<MC, EX, 2, true>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+                case 3: piped_run<MC, EX, 3, true>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+                default: piped_run<MC, EX, -1, true>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+            }
+        } else {
+            switch (S.nst) {
+                case 0: piped_run<MC, EX, 0, false>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+                case 1: piped_run<MC, EX, 1, false>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+                case 2: piped_run<MC, EX, 2, false>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+                case 3: piped_run<MC, EX, 3, false>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+                default: piped_run<MC, EX, -1, false>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+            }
         }
         return;
     }

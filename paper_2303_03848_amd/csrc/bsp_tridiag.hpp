@@ -299,11 +299,16 @@ struct BlockTri {
         double Vi;        // the interface node's value
     };
 
-    // Adds t * bhi to entry r_hi of the chunk holding row M-1 as an interior row.
+    // Adds t (already scaled by bhi) to entry r_hi of the chunk holding row
+    // M-1 as an interior row.  HI: such a chunk exists (M-1 is not the last
+    // node of a chunk); the add is then select-based on every lane, so the
+    // step body stays free of branches; without it there is no code at all.
+    template <bool HI>
     __device__ __forceinline__ void add_hi(double (&B)[MC], double t) const {
-        if (fc.hi_in) {
+        if constexpr (HI) {
+            const double tt = fc.hi_in ? t : 0.0;
 #pragma unroll
-            for (int q = 0; q < NI; ++q) B[q] += (q == fc.r_hi) ? t : 0.0;
+            for (int q = 0; q < NI; ++q) B[q] += (q == fc.r_hi) ? tt : 0.0;
         }
     }
 
@@ -313,7 +318,7 @@ struct BlockTri {
         double B[MC];
 #pragma unroll
         for (int q = 0; q < MC; ++q) B[q] = V[q];
-        add_hi(B, fc.bhi * fhi);
+        add_hi<true>(B, fc.bhi * fhi);
         P.A[0] = fma(fc.blo, flo, B[0]);
 #pragma unroll
         for (int q = 1; q < NI; ++q) P.A[q] = fma(-lu.l[q], P.A[q - 1], B[q]);
@@ -325,7 +330,7 @@ struct BlockTri {
     // One step: flo, fhi its forcing; flo_n, fhi_n the next step's (zero
     // after the last step).  NST: reduction stages (>= 0 compile-time, no
     // branches; -1: nst at run time).
-    template <bool EX, int NST>
+    template <bool EX, int NST, bool HI>
     __device__ __forceinline__ void pipe_step(Pipe& P, double flo, double fhi, double flo_n,
                                               double fhi_n) const {
         double y[MC], B[MC];
@@ -347,11 +352,10 @@ struct BlockTri {
         }
         const double yF = dpp_from_next(xn);  // x_0 of the next chunk
         double D = fma(kap, P.Vi, fma(fc.bhiD, fhi, fma(-aq, xl, -cq * yF)));
-        if constexpr (EX) {
-            // the rebuilt V carried this step's forcing: give its -mu share back
-            B[0] = fma(mu * fc.blo, flo, B[0]);
-            add_hi(B, mu * fc.bhi * fhi);
-        }
+        // Forcing on B: the rebuilt V carried this step's forcing (give its
+        // -mu share back), and the next step's enters its forward sweep.
+        if constexpr (EX) B[0] = fma(mu * fc.blo, flo, B[0]);
+        add_hi<HI>(B, EX ? fc.bhi * fma(mu, fhi, fhi_n) : fc.bhi * fhi_n);
         // interface reduction
         if constexpr (NST >= 0) {
 #pragma unroll
@@ -373,7 +377,6 @@ struct BlockTri {
             }
         }
         // next step's forward sweep on B: independent of the reduction above
-        add_hi(B, fc.bhi * fhi_n);
         P.A[0] = fma(fc.blo, flo_n, B[0]);
 #pragma unroll
         for (int q = 1; q < NI; ++q) P.A[q] = fma(-lu.l[q], P.A[q - 1], B[q]);

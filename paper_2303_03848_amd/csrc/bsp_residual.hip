@@ -75,6 +75,7 @@ struct ResWs {
 };
 
 constexpr int kResPartBlocks = 64;
+constexpr int kPartRows = 256;  // partial rows in the workspace: max over the split kernels
 
 static size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -94,7 +95,7 @@ static ResWs res_layout(const pinn_net& n, long npts, void* base) {
     w.abar = (float*)take(plane);
     w.g = (float*)take(sizeof(float) * 4 * w.n_pad);
     w.lossc = (float*)take(sizeof(float) * w.n_pad);
-    w.part = (float*)take(sizeof(float) * (size_t)kResPartBlocks * net_layout(n).total);
+    w.part = (float*)take(sizeof(float) * (size_t)kPartRows * net_layout(n).total);
     w.bytes = off;
     return w;
 }
@@ -328,32 +329,93 @@ __device__ __forceinline__ void chunk_range(long n, long& lo, long& hi) {
     hi = lo + chunk < n ? lo + chunk : n;
 }
 
-// Hidden-layer weight gradient (FP32): outputs dW[j][k] (W*W) then db[j] (W).
-__global__ void k_res_gradw_f32(const float* __restrict__ zbar, const float* __restrict__ cprev,
-                                long n, long n_pad, int W, float* __restrict__ part) {
+// Hidden-layer weight gradient, tiled (FP32):
+//   dW[j][k] = sum_i sum_s zbar_s[i][j] a_s[i][k],  db[j] = sum_i zbar_0[i][j],
+// s over the four derivative streams.  Split over points: each of the
+// kGradwBlocks blocks sums a contiguous range of points into its own partial
+// (reduced afterwards in a fixed order, so the result is deterministic).
+// Points go through LDS in chunks of CH: the four adjoint streams and the
+// four activation streams (rebuilt from the cache) of the chunk; thread
+// (tj, tk) of a 16 x 16 grid accumulates rows j = tj + 16 a (a < JB) and
+// columns k = tk + 16 b (b < W/16) in registers, JB rows per pass.
+constexpr int kGradwBlocks = 256;
+
+template <int W>
+__global__ __launch_bounds__(256) void k_res_gradw_tiled(const float* __restrict__ zbar,
+                                                         const float* __restrict__ cprev, long n,
+                                                         long n_pad, float* __restrict__ part) {
+    constexpr int CH = W >= 256 ? 8 : 16;
+    constexpr int KB = W / 16 > 0 ? W / 16 : 1;  // columns per thread
+    constexpr int JB = KB > 8 ? 8 : KB;          // rows per thread per pass
+    constexpr int PASSES = KB / JB;
+    __shared__ float zs[4][CH][W];
+    __shared__ float as[4][CH][W];
+    const int tid = threadIdx.x, tj = tid >> 4, tk = tid & 15;
     long lo, hi;
     chunk_range(n, lo, hi);
     const long plane = n_pad * W;
     const int count = W * W + W;
-    for (int x = threadIdx.x; x < count; x += blockDim.x) {
-        float acc = 0.f;
-        if (x < W * W) {
-            const int j = x / W, k = x - j * W;
-            for (long i = lo; i < hi; ++i) {
-                float a, at, ax, axx;
-                streams_from_cache(cprev, plane, i * W + k, a, at, ax, axx);
-                const long idx = i * W + j;
-                acc = fmaf(zbar[idx], a, acc);
-                acc = fmaf(zbar[plane + idx], at, acc);
-                acc = fmaf(zbar[2 * plane + idx], ax, acc);
-                acc = fmaf(zbar[3 * plane + idx], axx, acc);
+    float* out = part + (long)blockIdx.x * count;
+    float dbacc = 0.f;  // thread t < W: db[t]
+    for (int pass = 0; pass < PASSES; ++pass) {
+        float acc[JB][KB];
+#pragma unroll
+        for (int a = 0; a < JB; ++a)
+#pragma unroll
+            for (int b = 0; b < KB; ++b) acc[a][b] = 0.f;
+        for (long i0 = lo; i0 < hi; i0 += CH) {
+            const int cnt = (int)(hi - i0 < CH ? hi - i0 : CH);
+            __syncthreads();
+            for (int e = tid; e < CH * W; e += 256) {
+                const int c = e / W, k = e - c * W;
+                float z0 = 0.f, z1 = 0.f, z2 = 0.f, z3 = 0.f, a = 0.f, at = 0.f, ax = 0.f, axx = 0.f;
+                if (c < cnt) {
+                    const long idx = (i0 + c) * W + k;
+                    z0 = zbar[idx];
+                    z1 = zbar[plane + idx];
+                    z2 = zbar[2 * plane + idx];
+                    z3 = zbar[3 * plane + idx];
+                    streams_from_cache(cprev, plane, idx, a, at, ax, axx);
+                }
+                zs[0][c][k] = z0;
+                zs[1][c][k] = z1;
+                zs[2][c][k] = z2;
+                zs[3][c][k] = z3;
+                as[0][c][k] = a;
+                as[1][c][k] = at;
+                as[2][c][k] = ax;
+                as[3][c][k] = axx;
             }
-        } else {
-            const int j = x - W * W;
-            for (long i = lo; i < hi; ++i) acc += zbar[i * W + j];
+            __syncthreads();
+            if (pass == 0 && tid < W)
+                for (int c = 0; c < cnt; ++c) dbacc += zs[0][c][tid];
+            for (int c = 0; c < cnt; ++c) {
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    float zj[JB], ak[KB];
+#pragma unroll
+                    for (int a = 0; a < JB; ++a) zj[a] = zs[st][c][(pass * JB + a) * 16 + tj];
+#pragma unroll
+                    for (int b = 0; b < KB; ++b) ak[b] = as[st][c][b * 16 + tk];
+#pragma unroll
+                    for (int a = 0; a < JB; ++a)
+#pragma unroll
+                        for (int b = 0; b < KB; ++b) acc[a][b] = fmaf(zj[a], ak[b], acc[a][b]);
+                }
+            }
         }
-        part[(long)blockIdx.x * count + x] = acc;
+#pragma unroll
+        for (int a = 0; a < JB; ++a) {
+            const int j = (pass * JB + a) * 16 + tj;
+            if (j < W && tk < W)
+#pragma unroll
+                for (int b = 0; b < KB; ++b) {
+                    const int k = b * 16 + tk;
+                    if (k < W) out[(long)j * W + k] = acc[a][b];
+                }
+        }
     }
+    if (tid < W) out[W * W + tid] = dbacc;
 }
 
 // First-layer gradient: dW1[j][c] = sum_i zb_ij x_ic (+ sum zb_t for c = 0,
@@ -502,10 +564,20 @@ extern "C" int pinn_residual_fwd_bwd(const pinn_net* net, const bs_params* prm, 
             hipLaunchKernelGGL(k_res_bwd_data_f32, grid_for(work, 256), dim3(256), 0, st,
                                P0 + L.offW[l], w.zbar, w.abar, np, W);
             BSP_LAUNCHED();
-            hipLaunchKernelGGL(k_res_gradw_f32, dim3(kResPartBlocks), dim3(256), 0, st, w.zbar,
-                               cache(l - 1), n, np, W, w.part);
+            switch (W) {
+#define BSP_W(W_)                                                                             \
+    case W_:                                                                                  \
+        hipLaunchKernelGGL(k_res_gradw_tiled<W_>, dim3(kGradwBlocks), dim3(256), 0, st, w.zbar, \
+                           cache(l - 1), n, np, w.part);                                      \
+        break;
+                BSP_W(16) BSP_W(32) BSP_W(64) BSP_W(128) BSP_W(256)
+#undef BSP_W
+                default:
+                    set_error("unsupported width %d", W);
+                    return BS_ERR_ARG;
+            }
             BSP_LAUNCHED();
-            if ((rc = launch_res_reduce(w.part, kResPartBlocks, W * W + W, grad + L.offW[l], st)))
+            if ((rc = launch_res_reduce(w.part, kGradwBlocks, W * W + W, grad + L.offW[l], st)))
                 return rc;
         }
     }

@@ -163,27 +163,113 @@ __device__ __forceinline__ void tanh_epilogue(float z, float zt, float zx, float
     c[3 * plane + idx] = zxx;
 }
 
-// Hidden layer, FP32: one thread per (point, unit), four streams.
-__global__ void k_res_fwd_f32(const float* __restrict__ Wl, const float* __restrict__ bl,
-                              const float* __restrict__ cprev, float* __restrict__ cnext,
-                              long n_pad, int W) {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_pad * W) return;
-    const long i = t / W;
-    const int j = (int)(t - i * W);
+// Hidden-layer products of the FP32 residual pass, tiled: 32 points per
+// block; the layer's weights and the points' four input streams go through
+// LDS in K-chunks of up to 32; thread (tp, tu) of a 16 x 16 grid holds points
+// tp, tp + 16 and units tu + 16 b (b < W/16) for the four streams.  Sums run
+// over K in ascending order (bias first), as a plain per-output loop would.
+//   MODE 0 (forward): z_s[i][j] = b_j [s = 0] + sum_k W[j][k] a_s[i][k], with
+//                     a_s rebuilt from the cache of the layer below, then the
+//                     tanh derivative streams into the next cache.
+//   MODE 1 (adjoint): abar_s[i][k] = sum_j W[j][k] zbar_s[i][j].
+template <int W, int MODE>
+__global__ __launch_bounds__(256) void k_res_gemm_f32(const float* __restrict__ Wl,
+                                                      const float* __restrict__ bl,
+                                                      const float* __restrict__ in,
+                                                      float* __restrict__ out, long n_pad) {
+    constexpr int KC = W < 32 ? W : 32;
+    constexpr int UB = W / 16;  // units per thread
+    __shared__ float bs[KC][W + 1];     // B[k][u]: MODE 0 W[u][k], MODE 1 W[k][u]
+    __shared__ float xs[4][32][KC + 1];  // inputs [stream][point][k]
+    const int tid = threadIdx.x, tp = tid >> 4, tu = tid & 15;
+    const long i0 = (long)blockIdx.x * 32;
     const long plane = n_pad * W;
-    float z = bl[j], zt = 0.f, zx = 0.f, zxx = 0.f;
-    const float* w = Wl + (long)j * W;
-    for (int k = 0; k < W; ++k) {
-        float a, at, ax, axx;
-        streams_from_cache(cprev, plane, i * W + k, a, at, ax, axx);
-        const float wk = w[k];
-        z = fmaf(wk, a, z);
-        zt = fmaf(wk, at, zt);
-        zx = fmaf(wk, ax, zx);
-        zxx = fmaf(wk, axx, zxx);
+    float acc[4][2][UB];
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < UB; ++b)
+                acc[st][a][b] = (MODE == 0 && st == 0) ? bl[tu + 16 * b] : 0.f;
+    for (int k0 = 0; k0 < W; k0 += KC) {
+        __syncthreads();
+        for (int e = tid; e < KC * W; e += 256) {
+            if (MODE == 0) {  // row u of W, columns k0 .. k0 + KC
+                const int u = e / KC, kk = e - u * KC;
+                bs[kk][u] = Wl[(long)u * W + k0 + kk];
+            } else {  // rows k0 .. k0 + KC of W
+                const int kk = e / W, u = e - kk * W;
+                bs[kk][u] = Wl[(long)(k0 + kk) * W + u];
+            }
+        }
+        for (int e = tid; e < 32 * KC; e += 256) {
+            const int c = e / KC, kk = e - c * KC;
+            const long idx = (i0 + c) * W + k0 + kk;
+            if (MODE == 0) {
+                float a, at, ax, axx;
+                streams_from_cache(in, plane, idx, a, at, ax, axx);
+                xs[0][c][kk] = a;
+                xs[1][c][kk] = at;
+                xs[2][c][kk] = ax;
+                xs[3][c][kk] = axx;
+            } else {
+#pragma unroll
+                for (int st = 0; st < 4; ++st) xs[st][c][kk] = in[st * plane + idx];
+            }
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < KC; ++kk) {
+            float x[4][2], wv[UB];
+#pragma unroll
+            for (int st = 0; st < 4; ++st)
+#pragma unroll
+                for (int a = 0; a < 2; ++a) x[st][a] = xs[st][tp + 16 * a][kk];
+#pragma unroll
+            for (int b = 0; b < UB; ++b) wv[b] = bs[kk][tu + 16 * b];
+#pragma unroll
+            for (int st = 0; st < 4; ++st)
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < UB; ++b)
+                        acc[st][a][b] = fmaf(wv[b], x[st][a], acc[st][a][b]);
+        }
     }
-    tanh_epilogue(z, zt, zx, zxx, cnext, plane, t);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < UB; ++b) {
+            const long idx = (i0 + tp + 16 * a) * W + tu + 16 * b;
+            if (MODE == 0) {
+                tanh_epilogue(acc[0][a][b], acc[1][a][b], acc[2][a][b], acc[3][a][b], out, plane,
+                              idx);
+            } else {
+#pragma unroll
+                for (int st = 0; st < 4; ++st) out[st * plane + idx] = acc[st][a][b];
+            }
+        }
+}
+
+template <int MODE>
+static int launch_res_gemm_f32(const float* Wl, const float* bl, const float* in, float* out,
+                               long n_pad, int W, hipStream_t st) {
+    const dim3 grid((unsigned)(n_pad / 32));
+    switch (W) {
+#define BSP_W(W_)                                                                              \
+    case W_:                                                                                   \
+        hipLaunchKernelGGL((k_res_gemm_f32<W_, MODE>), grid, dim3(256), 0, st, Wl, bl, in, out, \
+                           n_pad);                                                             \
+        break;
+        BSP_W(16) BSP_W(32) BSP_W(64) BSP_W(128) BSP_W(256)
+#undef BSP_W
+        default:
+            set_error("unsupported width %d", W);
+            return BS_ERR_ARG;
+    }
+    BSP_LAUNCHED();
+    return BS_OK;
 }
 
 // Output layer, loss terms and output adjoints (one thread per point).
@@ -296,28 +382,6 @@ __global__ void k_res_zbar(const float* __restrict__ c, const float* __restrict_
                    2.0f * zx * zx * (1.0f - 3.0f * a * a) * Axx);
 }
 
-// abar_prev[s][i][k] = sum_j zbar[s][i][j] W[j][k]  (FP32, one thread per (i, k)).
-__global__ void k_res_bwd_data_f32(const float* __restrict__ Wl, const float* __restrict__ zbar,
-                                   float* __restrict__ abar, long n_pad, int W) {
-    const long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_pad * W) return;
-    const long i = t / W;
-    const int k = (int)(t - i * W);
-    const long plane = n_pad * W;
-    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-    for (int j = 0; j < W; ++j) {
-        const float w = Wl[(long)j * W + k];
-        const long idx = i * W + j;
-        s0 = fmaf(zbar[idx], w, s0);
-        s1 = fmaf(zbar[plane + idx], w, s1);
-        s2 = fmaf(zbar[2 * plane + idx], w, s2);
-        s3 = fmaf(zbar[3 * plane + idx], w, s3);
-    }
-    abar[t] = s0;
-    abar[plane + t] = s1;
-    abar[2 * plane + t] = s2;
-    abar[3 * plane + t] = s3;
-}
 
 // The gradient kernels below sum over points in chunks: block c of gridDim.x
 // takes the points [c*chunk, (c+1)*chunk) and writes one partial per output
@@ -526,9 +590,9 @@ extern "C" int pinn_residual_fwd_bwd(const pinn_net* net, const bs_params* prm, 
                                            nullptr, st)))
                 return rc;
         } else {
-            hipLaunchKernelGGL(k_res_fwd_f32, grid_for(work, 256), dim3(256), 0, st,
-                               P0 + L.offW[l], P0 + L.offb[l], cache(l - 1), cache(l), np, W);
-            BSP_LAUNCHED();
+            if ((rc = launch_res_gemm_f32<0>(P0 + L.offW[l], P0 + L.offb[l], cache(l - 1),
+                                             cache(l), np, W, st)))
+                return rc;
         }
     }
     hipLaunchKernelGGL(k_res_head, grid_for(np, 256), dim3(256), 0, st, P0, L.off_wo, L.off_bo,
@@ -561,9 +625,9 @@ extern "C" int pinn_residual_fwd_bwd(const pinn_net* net, const bs_params* prm, 
                                            w.part, st)))
                 return rc;
         } else {
-            hipLaunchKernelGGL(k_res_bwd_data_f32, grid_for(work, 256), dim3(256), 0, st,
-                               P0 + L.offW[l], w.zbar, w.abar, np, W);
-            BSP_LAUNCHED();
+            if ((rc = launch_res_gemm_f32<1>(P0 + L.offW[l], nullptr, w.zbar, w.abar, np, W,
+                                             st)))
+                return rc;
             switch (W) {
 #define BSP_W(W_)                                                                             \
     case W_:                                                                                  \

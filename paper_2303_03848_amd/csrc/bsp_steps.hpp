@@ -154,8 +154,9 @@ template <int T, int MC, bool EX, class Solver>
 __device__ __forceinline__ void theta_steps(const Solver& S, const OptionDev& o,
                                             double (&V)[MC], double tau0, double dt, int steps,
                                             double theta, bool homog, double* lds, double* ftab) {
-    if constexpr (IsWaveSolver<Solver>::value) {
-        (void)lds;
+    // The pipelined one-wavefront steps cover mu = 1 (Crank-Nicolson) and
+    // mu = 0 (implicit Euler); any other theta takes the plain step loop.
+    if constexpr (IsWaveSolver<Solver>::value) if (!EX || S.mu == 1.0) {
         // HI: row M-1 lies inside a chunk (grid not a multiple of MC) and
         // carries forcing; homogeneous runs have none.
         const bool hi = !homog && S.fc.r_hi != MC - 1;

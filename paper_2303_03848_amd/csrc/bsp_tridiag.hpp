@@ -207,7 +207,11 @@ struct BlockTri {
     Forcing fc;
     double aq, cq, kap, mu;         // interface row: sub/super diagonal; step constants
     double k1[LOGT], k2[LOGT], invB;
-    double al[NI], be[NI];          // L~^{-1} v, L~^{-1} w (pipelined steps)
+    // pipelined steps: L~^{-1} v, L~^{-1} w; the sweep multipliers in the
+    // scaled variables xi_q = x_q / ku_q; ku-scaled interface couplings and
+    // forcing coefficients
+    double al[NI], be[NI], lh[NI], ch[NI];
+    double aqk, cqk, blok, bhik;
     int p, nst;
 
     __device__ __forceinline__ double up(double x, int s) const {
@@ -280,37 +284,49 @@ struct BlockTri {
             al[q] = fma(-lu.l[q], al[q - 1], lu.v[q]);
             be[q] = fma(-lu.l[q], be[q - 1], lu.w[q]);
         }
+        // x_q = ku_q xi_q turns the backward sweep x_q = ku_q y_q - cu_q x_{q+1}
+        // into xi_q = y_q - ch_q xi_{q+1} and the forward sweep of x,
+        // F_q = x_q - l_q F_{q-1} with F_q = ku_q phi_q, into
+        // phi_q = xi_q - lh_q phi_{q-1}: one FMA per node each.
+#pragma unroll
+        for (int q = 0; q < NI; ++q) {
+            lh[q] = (q > 0) ? lu.l[q] * lu.ku[q - 1] / lu.ku[q] : 0.0;
+            ch[q] = (q < NI - 1) ? lu.cu[q] * lu.ku[q + 1] / lu.ku[q] : 0.0;
+        }
+        aqk = aq * lu.ku[NI - 1];
+        cqk = cq * dpp_from_next(lu.ku[0]);  // cq = 0 on the last lane
+        blok = fc.blo / lu.ku[0];
+        double kr = 1.0;
+#pragma unroll
+        for (int q = 0; q < NI; ++q)
+            if (q == fc.r_hi) kr = lu.ku[q];
+        bhik = fc.bhi / kr;
     }
 
     // ---------------------------------------------------------------------
-    // Pipelined steps.  With L~ the unit lower factor of the interior block,
-    // the forward sweep of step m+1 is
+    // Pipelined steps (Crank-Nicolson, mu = 1, and implicit Euler, mu = 0).
+    // With L~ the unit lower factor of the interior block, the forward sweep
+    // of step m+1 is
     //   y = L~^{-1} (V^m + f^{m+1}/kappa) = yP + z_{p-1} al + z_p be,
     //   yP = L~^{-1} (P^m + f^{m+1}/kappa),  al = L~^{-1} v,  be = L~^{-1} w,
     // where P^m is step m's interior value before its interface correction
     // (V^m = P^m + z_{p-1} v + z_p w).  yP depends only on P^m, so its
     // sweep runs while step m's interface reduction waits on lane exchanges;
     // once z is known, y is two independent FMAs per node.  The interior
-    // state itself is never formed between steps: where -mu V^m is needed it
-    // is rebuilt from the forward sweep, V_q = y_q + l_q y_{q-1} - f_q/kappa.
+    // state itself is never formed between steps.  With x = kappa-scaled
+    // solve of step m+1 (before its interface correction),
+    //   P^{m+1} = x - mu V^m   and   V^m = L~ y - f^{m+1}/kappa,
+    // so the next step's sweep is
+    //   yP' = L~^{-1} (x + (mu f^{m+1} + f^{m+2})/kappa) - mu y,
+    // whose forcing enters only the rows that carry it (row 0, row M-1) at the
+    // start of the recursion.  In the scaled variables xi, phi the step costs
+    // five operations per interior node: two for y, one backward, one forward,
+    // one for yP'.
     struct Pipe {
         double A[MC];     // yP of the coming step (interior entries)
         double z, zl;     // interface values of the last step (own, left)
         double Vi;        // the interface node's value
     };
-
-    // Adds t (already scaled by bhi) to entry r_hi of the chunk holding row
-    // M-1 as an interior row.  HI: such a chunk exists (M-1 is not the last
-    // node of a chunk); the add is then select-based on every lane, so the
-    // step body stays free of branches; without it there is no code at all.
-    template <bool HI>
-    __device__ __forceinline__ void add_hi(double (&B)[MC], double t) const {
-        if constexpr (HI) {
-            const double tt = fc.hi_in ? t : 0.0;
-#pragma unroll
-            for (int q = 0; q < NI; ++q) B[q] += (q == fc.r_hi) ? tt : 0.0;
-        }
-    }
 
     // Starts a run from state V; flo, fhi: forcing of the first step.
     __device__ __forceinline__ void pipe_begin(const double (&V)[MC], double flo, double fhi,
@@ -318,7 +334,9 @@ struct BlockTri {
         double B[MC];
 #pragma unroll
         for (int q = 0; q < MC; ++q) B[q] = V[q];
-        add_hi<true>(B, fc.bhi * fhi);
+        const double tt = fc.hi_in ? fc.bhi * fhi : 0.0;
+#pragma unroll
+        for (int q = 0; q < NI; ++q) B[q] += (q == fc.r_hi) ? tt : 0.0;
         P.A[0] = fma(fc.blo, flo, B[0]);
 #pragma unroll
         for (int q = 1; q < NI; ++q) P.A[q] = fma(-lu.l[q], P.A[q - 1], B[q]);
@@ -328,34 +346,22 @@ struct BlockTri {
     }
 
     // One step: flo, fhi its forcing; flo_n, fhi_n the next step's (zero
-    // after the last step).  NST: reduction stages (>= 0 compile-time, no
-    // branches; -1: nst at run time).
+    // after the last step).  EX: mu = 1 (Crank-Nicolson), else mu = 0.
+    // NST: reduction stages (>= 0 compile-time, no branches; -1: nst at run
+    // time).  HI: row M-1 is an interior row of some chunk (a grid that is
+    // not a multiple of MC); its forcing is then added by selects on every
+    // lane, so the step body stays free of branches.
     template <bool EX, int NST, bool HI>
     __device__ __forceinline__ void pipe_step(Pipe& P, double flo, double fhi, double flo_n,
                                               double fhi_n) const {
-        double y[MC], B[MC];
+        double y[NI], xi[NI];
 #pragma unroll
         for (int q = 0; q < NI; ++q) y[q] = fma(P.zl, al[q], fma(P.z, be[q], P.A[q]));
-        // backward sweep; B = x - mu V^{m-1} (V rebuilt from y before y is consumed)
-        double xn = lu.ku[NI - 1] * y[NI - 1];
-        const double xl = xn;
+        xi[NI - 1] = y[NI - 1];
 #pragma unroll
-        for (int q = NI - 1; q >= 0; --q) {
-            const double x = (q == NI - 1) ? xn : fma(-lu.cu[q], xn, lu.ku[q] * y[q]);
-            if constexpr (EX) {
-                const double t = (q > 0) ? fma(lu.l[q], y[q - 1], y[q]) : y[0];
-                B[q] = fma(-mu, t, x);
-            } else {
-                B[q] = x;
-            }
-            xn = x;
-        }
-        const double yF = dpp_from_next(xn);  // x_0 of the next chunk
-        double D = fma(kap, P.Vi, fma(fc.bhiD, fhi, fma(-aq, xl, -cq * yF)));
-        // Forcing on B: the rebuilt V carried this step's forcing (give its
-        // -mu share back), and the next step's enters its forward sweep.
-        if constexpr (EX) B[0] = fma(mu * fc.blo, flo, B[0]);
-        add_hi<HI>(B, EX ? fc.bhi * fma(mu, fhi, fhi_n) : fc.bhi * fhi_n);
+        for (int q = NI - 2; q >= 0; --q) xi[q] = fma(-ch[q], xi[q + 1], y[q]);
+        const double xF = dpp_from_next(xi[0]);  // xi_0 of the next chunk
+        double D = fma(kap, P.Vi, fma(fc.bhiD, fhi, fma(-aqk, xi[NI - 1], -cqk * xF)));
         // interface reduction
         if constexpr (NST >= 0) {
 #pragma unroll
@@ -376,14 +382,23 @@ struct BlockTri {
                 }
             }
         }
-        // next step's forward sweep on B: independent of the reduction above
-        P.A[0] = fma(fc.blo, flo_n, B[0]);
+        // next step's forward sweep: independent of the reduction above
+        double tt = 0.0;
+        if constexpr (HI) tt = fc.hi_in ? bhik * (EX ? fhi + fhi_n : fhi_n) : 0.0;
+        double ph = fma(blok, EX ? flo + flo_n : flo_n, xi[0]);
+        if constexpr (HI) ph += (fc.r_hi == 0) ? tt : 0.0;
+        P.A[0] = EX ? fma(lu.ku[0], ph, -y[0]) : lu.ku[0] * ph;
 #pragma unroll
-        for (int q = 1; q < NI; ++q) P.A[q] = fma(-lu.l[q], P.A[q - 1], B[q]);
+        for (int q = 1; q < NI; ++q) {
+            double xq = xi[q];
+            if constexpr (HI) xq += (q == fc.r_hi) ? tt : 0.0;
+            ph = fma(-lh[q], ph, xq);
+            P.A[q] = EX ? fma(lu.ku[q], ph, -y[q]) : lu.ku[q] * ph;
+        }
         const double z = D * invB;
         P.zl = dpp_from_prev(z);
         P.z = z;
-        P.Vi = EX ? fma(-mu, P.Vi, z) : z;
+        P.Vi = EX ? z - P.Vi : z;
     }
 
     // Ends a run (the last pipe_step had zero next-step forcing): V = state.

@@ -150,7 +150,8 @@ int pinn_residual_fwd_bwd(const pinn_net* net, const bs_params* prm, int n_f, co
                           int n_e, const float* X_e, int n_b, const float* X_b, float* loss3,
                           float* grad, void* ws, size_t ws_bytes, void* stream);
 
-/* Bytes of device workspace one Parareal solve needs. */
+/* Bytes of device workspace one Parareal solve needs (F and coarse values,
+ * progress counters, and the network grid for the network kinds). */
 size_t parareal_workspace_size(const bs_grid* grid, const bs_slices* sl, int coarse_kind);
 
 /* Start a Parareal solve: U[0] = expiry payoff; for the network kinds the
@@ -178,7 +179,15 @@ int parareal_iterate(const bs_params* prm, const bs_grid* grid, const bs_slices*
  * SYNCHRONOUS.  iters (host, out): iterations done; defect_hist (host,
  * [max_iter] or NULL): defect of each iteration.  net may be NULL for
  * BS_COARSE_IE.  Returns BS_OK, BS_NOT_CONVERGED (max_iter hit first) or an
- * error. */
+ * error.
+ * For grids of up to 4096 nodes the iterations overlap (same iterates as
+ * parareal_iterate called for k = 1, 2, ...): F of iteration k runs on one
+ * of two library-owned side streams of the calling thread and starts each
+ * slice once the sweep of iteration k-1 has produced its initial value; the
+ * sweep of iteration k, on `stream`, takes each slice's F as soon as it is
+ * written.  The launches synchronise through progress counters in ws; every
+ * wait also ends on the stop flag, and after about 2 s the solve fails with
+ * BS_ERR_HIP.  `stream` is joined with the side streams before returning. */
 int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,
                    int coarse_kind, double tol, const pinn_net* net, int max_iter, void* ws,
                    size_t ws_bytes, double* U, int* iters, double* defect_hist, void* stream);

@@ -48,13 +48,18 @@ static int check_slices(const bs_slices* s) {
     return BS_OK;
 }
 
-// Parareal workspace: [result 2 doubles | Fv N*M | Gold N*M | Vt (N+1)*M (network kinds)]
+// Parareal workspace: [result 256 B | Fv N*M | Gold N*M | progress counters
+// 3(N+1)+1 ints | Vt (N+1)*M (network kinds)].  result: [0] defect, [1]
+// non-finite flag, int at [4]: stop flag of the asynchronous solve.
 struct Workspace {
     double* result;
     double* Fv;
     double* Gold;
+    int* flags;  // ready[N+1], taken[N+1], fdone[N+1], err
     double* Vt;
 };
+
+static int flag_count(int N) { return 3 * (N + 1) + 1; }
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -62,6 +67,7 @@ static size_t ws_bytes(int M, int N, int kind) {
     size_t b = 256;
     b += align256(sizeof(double) * (size_t)N * M);
     b += align256(sizeof(double) * (size_t)N * M);
+    b += align256(sizeof(int) * (size_t)flag_count(N));
     if (kind != BS_COARSE_IE) b += align256(sizeof(double) * (size_t)(N + 1) * M);
     return b;
 }
@@ -75,6 +81,8 @@ static Workspace ws_layout(void* ws, int M, int N, int kind) {
     p += align256(sizeof(double) * (size_t)N * M);
     w.Gold = (double*)p;
     p += align256(sizeof(double) * (size_t)N * M);
+    w.flags = (int*)p;
+    p += align256(sizeof(int) * (size_t)flag_count(N));
     w.Vt = (kind != BS_COARSE_IE) ? (double*)p : nullptr;
     return w;
 }
@@ -119,8 +127,8 @@ static int propagate_checked(const bs_params* prm, const bs_grid* grid, int nsys
 
 // ----------------------------------------------------------- profiling
 // F and sweep launches of parareal_iterate / parareal_solve are bracketed by
-// events on the solve's stream (three per enqueued iteration), read back once
-// the call has synchronised.
+// events on the streams they run on (four per enqueued iteration), read back
+// once the call has synchronised.
 struct Profile {
     bool on = false;
     std::vector<hipEvent_t> ev;
@@ -129,7 +137,7 @@ struct Profile {
 static Profile g_prof;
 
 static int prof_reserve(int slots) {
-    while ((int)g_prof.ev.size() < 3 * slots) {
+    while ((int)g_prof.ev.size() < 4 * slots) {
         hipEvent_t e;
         BSP_HIP(hipEventCreate(&e));
         g_prof.ev.push_back(e);
@@ -140,14 +148,36 @@ static int prof_reserve(int slots) {
 // Adds iteration slot `slot` to the profile; cells: fine cell updates it did.
 static int prof_collect(int slot, double cells) {
     float f_ms = 0.f, s_ms = 0.f;
-    BSP_HIP(hipEventElapsedTime(&f_ms, g_prof.ev[3 * slot], g_prof.ev[3 * slot + 1]));
-    BSP_HIP(hipEventElapsedTime(&s_ms, g_prof.ev[3 * slot + 1], g_prof.ev[3 * slot + 2]));
+    BSP_HIP(hipEventElapsedTime(&f_ms, g_prof.ev[4 * slot], g_prof.ev[4 * slot + 1]));
+    BSP_HIP(hipEventElapsedTime(&s_ms, g_prof.ev[4 * slot + 2], g_prof.ev[4 * slot + 3]));
     g_prof.fine_ms += f_ms;
     g_prof.fine_launches += 1;
     g_prof.fine_cells += cells;
     g_prof.sweep_ms += s_ms;
     g_prof.sweep_launches += 1;
     return BS_OK;
+}
+
+// Initial state, network grid (network kinds) and the prediction sweep.
+// ps: progress counters of the overlapped solve (the sweep publishes U[n]).
+static int start_impl(const bs_params* prm, const bs_grid* grid, const bs_slices* sl, int kind,
+                      const pinn_net* net, void* ws, double* U, const PipeSync* ps,
+                      hipStream_t st) {
+    int rc;
+    const int M = grid->M, N = sl->N;
+    const OptionDev o = make_option(*prm, M);
+    const double dT = prm->T / N;
+    Workspace w = ws_layout(ws, M, N, kind);
+    if ((rc = launch_initial(o, M, grid->payoff_mode, U, st))) return rc;
+    if (kind != BS_COARSE_IE) {
+        if ((rc = launch_pinn_grid(*net, o, M, N, dT, w.Vt, st))) return rc;
+    }
+    SweepArgs a{o, M, N, 0, sl->coarse_steps, kind, 1, dT, U, w.Fv, w.Gold, w.Vt, w.result};
+    if (ps) {
+        a.ps = *ps;
+        a.ps.k = 0;
+    }
+    return launch_sweep(a, st);
 }
 
 }  // namespace bsp
@@ -225,41 +255,42 @@ int parareal_start(const bs_params* prm, const bs_grid* grid, const bs_slices* s
     clear_error();
     int rc = check_parareal(prm, grid, sl, kind, net, ws, ws_size, U);
     if (rc) return rc;
-    const int M = grid->M, N = sl->N;
-    hipStream_t st = (hipStream_t)stream;
-    const OptionDev o = make_option(*prm, M);
-    const double dT = prm->T / N;
-    Workspace w = ws_layout(ws, M, N, kind);
-    if ((rc = launch_initial(o, M, grid->payoff_mode, U, st))) return rc;
-    if (kind != BS_COARSE_IE) {
-        if ((rc = launch_pinn_grid(*net, o, M, N, dT, w.Vt, st))) return rc;
-    }
-    SweepArgs a{o, M, N, 0, sl->coarse_steps, kind, 1, dT, U, w.Fv, w.Gold, w.Vt, w.result};
-    return launch_sweep(a, st);
+    return start_impl(prm, grid, sl, kind, net, ws, U, nullptr, (hipStream_t)stream);
 }
 
-// Enqueues iteration k (F over the slices that still change, then the
-// sweep) on st.  stop/hist/tol: device-side stopping of the asynchronous
-// solve (null for a single synchronous iteration).  slot: profiling slot.
+}  // extern "C"
+
+// Enqueues iteration k: F over the slices that still change on fst, then
+// the sweep on st.  stop/hist/tol: device-side stopping of the asynchronous
+// solve (null for a single synchronous iteration).  ps: progress counters of
+// the overlapped solve (null: fst == st and the launches follow each other).
+// slot: profiling slot.
 static int enqueue_iteration(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,
                              int kind, void* ws, double* U, int k, int* stop, double* hist,
-                             double tol, int slot, hipStream_t st) {
+                             double tol, int slot, const PipeSync* ps, hipStream_t fst,
+                             hipStream_t st) {
     const int M = grid->M, N = sl->N;
     const OptionDev o = make_option(*prm, M);
     const double dT = prm->T / N;
     Workspace w = ws_layout(ws, M, N, kind);
     const int first = k - 1 < N - 1 ? k - 1 : N - 1;
     const bool prof = g_prof.on;
-    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[3 * slot], st));
+    PipeSync pk{};
+    if (ps) {
+        pk = *ps;
+        pk.k = k;
+    }
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[4 * slot], fst));
     int rc = launch_theta_batch(o, M, N - first, nullptr, 0.0, dT, first, dT / sl->fine_steps,
                                 sl->fine_steps, 0.5, 0, U + (long)first * M, M,
-                                w.Fv + (long)first * M, M, st, stop);
+                                w.Fv + (long)first * M, M, fst, stop, ps ? &pk : nullptr);
     if (rc) return rc;
-    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[3 * slot + 1], st));
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[4 * slot + 1], fst));
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[4 * slot + 2], st));
     SweepArgs a{o,      M,      N,      first,    sl->coarse_steps, kind, 0, dT, U, w.Fv,
-                w.Gold, w.Vt,   w.result, stop,   hist,             tol,  k};
+                w.Gold, w.Vt,   w.result, stop,   hist,             tol,  k,  pk};
     if ((rc = launch_sweep(a, st))) return rc;
-    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[3 * slot + 2], st));
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[4 * slot + 3], st));
     return BS_OK;
 }
 
@@ -273,7 +304,8 @@ static int iterate_impl(const bs_params* prm, const bs_grid* grid, const bs_slic
                         void* ws, double* U, int k, double* defect, int* nonfinite,
                         hipStream_t st) {
     Workspace w = ws_layout(ws, grid->M, sl->N, kind);
-    int rc = enqueue_iteration(prm, grid, sl, kind, ws, U, k, nullptr, nullptr, 0.0, 0, st);
+    int rc = enqueue_iteration(prm, grid, sl, kind, ws, U, k, nullptr, nullptr, 0.0, 0, nullptr,
+                               st, st);
     if (rc) return rc;
     double res[2];
     BSP_HIP(hipMemcpyAsync(res, w.result, sizeof(res), hipMemcpyDeviceToHost, st));
@@ -290,12 +322,17 @@ static int iterate_impl(const bs_params* prm, const bs_grid* grid, const bs_slic
 
 // Host-side state of the asynchronous solve, one per host thread (a solve
 // is synchronous, so a thread runs one at a time): the per-iteration record
-// in mapped pinned host memory that the sweep writes, and completion events.
+// in mapped pinned host memory that the sweep writes, completion events, and
+// the two side streams (default priority, not synchronising with the null
+// stream) on which the fine launches of the overlapped solve alternate.
 struct SolveState {
     double* hist = nullptr;  // host view
     double* hist_dev = nullptr;
     size_t cap = 0;
     std::vector<hipEvent_t> done;
+    int dev = -1;
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t go = nullptr, side_done[2] = {nullptr, nullptr};
 };
 static thread_local SolveState t_solve;
 
@@ -318,6 +355,24 @@ static int solve_reserve(int kmax) {
     }
     return BS_OK;
 }
+
+// Side streams and their events on the current device (those made for
+// another device are kept until the process ends).
+static int solve_streams() {
+    SolveState& S = t_solve;
+    int dev = 0;
+    BSP_HIP(hipGetDevice(&dev));
+    if (S.dev == dev) return BS_OK;
+    for (int i = 0; i < 2; ++i) {
+        BSP_HIP(hipStreamCreateWithFlags(&S.side[i], hipStreamNonBlocking));
+        BSP_HIP(hipEventCreateWithFlags(&S.side_done[i], hipEventDisableTiming));
+    }
+    BSP_HIP(hipEventCreateWithFlags(&S.go, hipEventDisableTiming));
+    S.dev = dev;
+    return BS_OK;
+}
+
+extern "C" {
 
 int parareal_iterate(const bs_params* prm, const bs_grid* grid, const bs_slices* sl, int kind,
                      const pinn_net* net, void* ws, size_t ws_size, double* U, int k,
@@ -349,8 +404,30 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
     for (size_t i = 0; i < 2 * (size_t)(kmax + 1); ++i) S.hist[i] = 0.0;
     Workspace w = ws_layout(ws, grid->M, N, kind);
     int* stop = reinterpret_cast<int*>(w.result + 4);
-    if ((rc = parareal_start(prm, grid, sl, kind, net, ws, ws_size, U, stream))) return rc;
     if ((rc = launch_set_int(stop, 0, st))) return rc;
+
+    // Overlapped iterations (grids the one-block sweep and the per-system
+    // fine kernel cover): the fine launch of iteration k runs on a side
+    // stream and starts each slice as soon as the sweep of iteration k-1 has
+    // produced its initial value, so the sweep of iteration k-1 and the fine
+    // work of iteration k run at the same time; the sweep of iteration k
+    // follows slice by slice.  The iterates are the same as one launch after
+    // the other.  Consecutive fine launches alternate between two side
+    // streams so that one may start while the previous one's last slices
+    // still run.
+    const bool pipe = pipe_capable(grid->M);
+    PipeSync ps{};
+    if (pipe) {
+        if ((rc = solve_streams())) return rc;
+        ps.ready = w.flags;
+        ps.taken = w.flags + (N + 1);
+        ps.fdone = w.flags + 2 * (N + 1);
+        ps.err = w.flags + 3 * (N + 1);
+        if ((rc = launch_fill_int(w.flags, flag_count(N), 0, st))) return rc;
+        BSP_HIP(hipEventRecord(S.go, st));
+        for (int i = 0; i < 2; ++i) BSP_HIP(hipStreamWaitEvent(S.side[i], S.go, 0));
+    }
+    if ((rc = start_impl(prm, grid, sl, kind, net, ws, U, pipe ? &ps : nullptr, st))) return rc;
 
     // Iteration k+1 is queued before the host looks at iteration k, so the
     // stream never waits for the host; the sweep that meets the stopping
@@ -375,7 +452,7 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
     bool decided = false;
     for (int k = 1; k <= kmax && !decided; ++k) {
         if ((rc = enqueue_iteration(prm, grid, sl, kind, ws, U, k, stop, S.hist_dev, tol, k - 1,
-                                    st)))
+                                    pipe ? &ps : nullptr, pipe ? S.side[k & 1] : st, st)))
             return rc;
         BSP_HIP(hipEventRecord(S.done[k], st));
         enq = k;
@@ -388,8 +465,20 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
         BSP_HIP(hipEventSynchronize(S.done[enq]));
         decide(enq);
     }
+    int err = 0;
+    if (pipe) {  // the caller's stream ends after the side streams' work
+        for (int i = 0; i < 2; ++i) {
+            BSP_HIP(hipEventRecord(S.side_done[i], S.side[i]));
+            BSP_HIP(hipStreamWaitEvent(st, S.side_done[i], 0));
+        }
+        BSP_HIP(hipMemcpyAsync(&err, ps.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    }
     BSP_HIP(hipStreamSynchronize(st));
     *iters = last;
+    if (err) {
+        set_error("overlapped Parareal solve: a launch waited longer than its time limit");
+        return BS_ERR_HIP;
+    }
     if (g_prof.on) {
         for (int k = 1; k <= enq; ++k)
             if ((rc = prof_collect(k - 1, k <= last ? iteration_cells(grid, sl, k) : 0.0)))

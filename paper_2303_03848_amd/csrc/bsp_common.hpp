@@ -100,6 +100,68 @@ TriShape shape_for(int kernel, int M);  // kernel 0: F/G batch, 1: sweep
 int set_shape_override(int kernel, int M_lo, int M_hi, int T, int MC);
 void reset_shape_overrides();
 
+// ------------------------------------------- overlapped Parareal iterations
+// Per-slice progress counters of a solve whose fine launch of iteration k+1
+// runs alongside the sweep of iteration k (all zero at the start of a solve,
+// in the caller's workspace):
+//   ready[n] = j + 1 once U[n] holds iterate j (n = 0..N),
+//   taken[n] = k once the fine launch of iteration k has read U[n],
+//   fdone[n] = k once it has written Fv[n].
+// Every wait names a counter that only earlier-queued work advances, so any
+// serialisation of the launches completes.  A wait also ends when *stop is
+// set (the solve has converged) or when *err is set; after kPipeSpinTicks of
+// the constant-rate clock it sets *err itself.
+struct PipeSync {
+    int* ready;
+    int* taken;
+    int* fdone;
+    int* err;
+    int k;  // iteration of the launch (0: the prediction sweep)
+};
+constexpr long long kPipeSpinTicks = 200000000LL;  // 2 s at 100 MHz
+
+__device__ __forceinline__ int pipe_load(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block-wide wait for *f >= v: thread 0 polls, the outcome is shared through
+// *slot (LDS), and every thread then orders its later loads after the
+// producer's stores.  Returns false if the block must stop (stop or error).
+__device__ inline bool pipe_wait(const PipeSync& ps, const int* f, int v, const int* stop,
+                                 int* slot) {
+    __syncthreads();  // slot may still be read from the previous wait
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        if (pipe_load(f) < v) {
+            const long long t0 = wall_clock64();
+            while (pipe_load(f) < v) {
+                if ((stop && pipe_load(stop)) || pipe_load(ps.err)) {
+                    ok = 0;
+                    break;
+                }
+                if (wall_clock64() - t0 > kPipeSpinTicks) {
+                    __hip_atomic_store(ps.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        *slot = ok;
+    }
+    __syncthreads();
+    const bool ok = *slot != 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok;
+}
+
+// Publishes *f = v after every thread's stores of the block.
+__device__ inline void pipe_signal(int* f, int v) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // --------------------------------------------------- internal launchers
 
 // theta-method on nsys independent systems: tau of system s = tau0[s] if
@@ -108,8 +170,8 @@ void reset_shape_overrides();
 int launch_theta_batch(const OptionDev& o, int M, int nsys, const double* tau0, double tau_start,
                        double tau_stride, int sys_offset, double dt, int steps, double theta,
                        int homog, const double* u_in, long ld_in, double* u_out, long ld_out,
-                       hipStream_t stream,
-                       const int* stop = nullptr);
+                       hipStream_t stream, const int* stop = nullptr,
+                       const PipeSync* ps = nullptr);
 
 struct SweepArgs {
     OptionDev o;
@@ -129,9 +191,12 @@ struct SweepArgs {
     double* hist;
     double tol;
     int k;
+    PipeSync ps;  // overlapped solve (ps.ready null: not overlapped)
 };
 int launch_sweep(const SweepArgs& a, hipStream_t stream);
 int launch_set_int(int* p, int v, hipStream_t stream);  // *p = v in stream order
+int launch_fill_int(int* p, int n, int v, hipStream_t stream);  // p[0..n) = v
+bool pipe_capable(int M);  // the overlapped solve covers grids of this size
 
 int launch_initial(const OptionDev& o, int M, int payoff_mode, double* u0, hipStream_t stream);
 

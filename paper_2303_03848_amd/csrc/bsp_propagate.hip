@@ -48,6 +48,7 @@ struct ThetaArgs {
     double* u_out;
     long ld_out;
     const int* stop;  // when non-null and set, the launch does nothing
+    PipeSync ps;      // overlapped solve (k_theta_pipe only)
 };
 
 __device__ __forceinline__ bool stopped(const int* stop) {
@@ -55,6 +56,18 @@ __device__ __forceinline__ bool stopped(const int* stop) {
 }
 
 __global__ void k_set_int(int* p, int v) { *p = v; }
+
+__global__ void k_fill_int(int* p, int n, int v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+int launch_fill_int(int* p, int n, int v, hipStream_t stream) {
+    if (n <= 0) return BS_OK;
+    hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, stream, p, n, v);
+    BSP_LAUNCHED();
+    return BS_OK;
+}
 
 int launch_set_int(int* p, int v, hipStream_t stream) {
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, stream, p, v);
@@ -74,24 +87,51 @@ __device__ __forceinline__ void sweep_record(const SweepArgs& a, double dmax, in
     if (a.stop && (bad || dmax <= a.tol)) *a.stop = 1;
 }
 
-template <int T, int MC>
-__global__ __launch_bounds__(T) void k_theta_batch(ThetaArgs a) {
-    __shared__ double smem[smem_doubles<T>()];
+// One block per system.  PIPE (overlapped Parareal solve): system sys is
+// slice n = sys + sys_offset of iteration ps.k; it waits until U[n] holds
+// iterate k-1, reports having read it, polls the stop flag while stepping,
+// and writes Fv[n] only after the sweep of iteration k-1 has consumed the
+// previous one (U[n+1] holds iterate k-1).
+template <int T, int MC, bool PIPE>
+__device__ __forceinline__ void theta_body(const ThetaArgs& a, double* smem, int* pslot) {
     double* lds = smem;
     double* ftab = smem + 4 * T;
     if (stopped(a.stop)) return;
     const int sys = blockIdx.x;
+    const int n = sys + a.sys_offset;
+    if constexpr (PIPE)
+        if (!pipe_wait(a.ps, a.ps.ready + n, a.ps.k, a.stop, pslot)) return;
     double V[MC];
     load_system<T, MC>(a.u_in + (long)sys * a.ld_in, a.M, V, smem);
-    Solver<T, MC> S;
+    if constexpr (PIPE) pipe_signal(a.ps.taken + n, a.ps.k);
+    using S_t = Solver<T, MC>;
+    S_t S;
     S.setup(a.o.s2, a.o.r, a.theta * a.dt, (1.0 - a.theta) * a.dt, a.M, lds);
-    const double tau0 =
-        a.tau0 ? a.tau0[sys] : a.tau_start + (double)(sys + a.sys_offset) * a.tau_stride;
-    if (a.theta == 1.0)
-        theta_steps<T, MC, false>(S, a.o, V, tau0, a.dt, a.steps, 1.0, a.homog != 0, lds, ftab);
-    else
-        theta_steps<T, MC, true>(S, a.o, V, tau0, a.dt, a.steps, a.theta, a.homog != 0, lds, ftab);
+    const double tau0 = a.tau0 ? a.tau0[sys] : a.tau_start + (double)n * a.tau_stride;
+    const bool ok =
+        (a.theta == 1.0)
+            ? theta_steps<T, MC, false, S_t, PIPE>(S, a.o, V, tau0, a.dt, a.steps, 1.0,
+                                                   a.homog != 0, lds, ftab, a.stop)
+            : theta_steps<T, MC, true, S_t, PIPE>(S, a.o, V, tau0, a.dt, a.steps, a.theta,
+                                                  a.homog != 0, lds, ftab, a.stop);
+    if (!ok) return;
+    if constexpr (PIPE)
+        if (!pipe_wait(a.ps, a.ps.ready + n + 1, a.ps.k, a.stop, pslot)) return;
     store_system<T, MC>(a.u_out + (long)sys * a.ld_out, a.M, V, smem);
+    if constexpr (PIPE) pipe_signal(a.ps.fdone + n, a.ps.k);
+}
+
+template <int T, int MC>
+__global__ __launch_bounds__(T) void k_theta_batch(ThetaArgs a) {
+    __shared__ double smem[smem_doubles<T>()];
+    theta_body<T, MC, false>(a, smem, nullptr);
+}
+
+template <int T, int MC>
+__global__ __launch_bounds__(T) void k_theta_pipe(ThetaArgs a) {
+    __shared__ double smem[smem_doubles<T>()];
+    __shared__ int pslot;
+    theta_body<T, MC, true>(a, smem, &pslot);
 }
 
 // ---------------------------------------------------- Parareal sweep
@@ -100,13 +140,16 @@ template <int T, int MC>
 __global__ __launch_bounds__(T) void k_sweep(SweepArgs a) {
     __shared__ double lds[4 * T];
     __shared__ double ftab[2 * kForceChunk];
+    __shared__ int pslot;
     if (stopped(a.stop)) return;
     Solver<T, MC> S;
     S.setup(a.o.s2, a.o.r, a.dT / (double)a.coarse_steps, 0.0, a.M, lds);
     double dmax = 0.0;
     int bad = 0;
-    sweep_slices<T, MC>(S, a.o, a.M, a.N, a.n0, a.coarse_steps, a.kind, a.predict != 0, a.dT, a.U,
-                        a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad);
+    if (!sweep_slices<T, MC>(S, a.o, a.M, a.N, a.n0, a.coarse_steps, a.kind, a.predict != 0, a.dT,
+                             a.U, a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad,
+                             a.ps.ready ? &a.ps : nullptr, a.stop, &pslot))
+        return;
     if (!a.predict) {
         block_defect<T>(dmax, bad, lds);
         if (threadIdx.x == 0) sweep_record(a, dmax, bad);
@@ -256,14 +299,33 @@ int set_shape_override(int kernel, int M_lo, int M_hi, int T, int MC) {
 
 void reset_shape_overrides() { g_nover[0] = g_nover[1] = 0; }
 
+bool pipe_capable(int M) { return !is_large(shape_for(0, M)) && !is_large(shape_for(1, M)); }
+
 int launch_theta_batch(const OptionDev& o, int M, int nsys, const double* tau0, double tau_start,
                        double tau_stride, int sys_offset, double dt, int steps, double theta,
                        int homog, const double* u_in, long ld_in, double* u_out, long ld_out,
-                       hipStream_t stream, const int* stop) {
+                       hipStream_t stream, const int* stop, const PipeSync* ps) {
     if (nsys == 0) return BS_OK;
     const TriShape sh = shape_for(0, M);
     ThetaArgs a{o,     M,           steps, homog, sys_offset, tau0, tau_start,
                 tau_stride, dt, theta, u_in,  ld_in, u_out,     ld_out, stop};
+    if (ps) {
+        if (is_large(sh) || !stop) {
+            set_error("overlapped fine launch needs a stop flag and a grid of at most 4096 nodes");
+            return BS_ERR_ARG;
+        }
+        a.ps = *ps;
+#define BSP_CASE(T_, MC_)                                                                  \
+    if (sh.T == T_ && sh.MC == MC_) {                                                      \
+        hipLaunchKernelGGL((k_theta_pipe<T_, MC_>), dim3(nsys), dim3(T_), 0, stream, a);   \
+        BSP_LAUNCHED();                                                                    \
+        return BS_OK;                                                                      \
+    }
+        BSP_TRI_SHAPES(BSP_CASE)
+#undef BSP_CASE
+        set_error("M = %d is beyond the supported range of the tridiagonal kernels", M);
+        return BS_ERR_ARG;
+    }
     if (is_large(sh)) {
         double *tab, *ptab;
         int rc = large_tables(0, &tab, &ptab);

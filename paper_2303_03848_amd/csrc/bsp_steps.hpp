@@ -105,10 +105,16 @@ struct IsWaveSolver<BlockTri<64, MC>> : std::true_type {};
 // straight-line block.  The forcing tables here hold steps m0+1 .. m0+n+1
 // (each step also needs the next step's forcing); entries past the last
 // step are zero.
-template <int MC, bool EX, int NST, bool HI>
-__device__ __forceinline__ void piped_run(const BlockTri<64, MC>& S, const OptionDev& o,
+// POLL: the run checks *stop every kPollSteps steps (the flag is loaded one
+// period before it is tested, so the load is never waited for) and returns
+// false when it is set; the state is then left half-propagated.
+constexpr int kPollSteps = 64;
+
+template <int MC, bool EX, int NST, bool HI, bool POLL>
+__device__ __forceinline__ bool piped_run(const BlockTri<64, MC>& S, const OptionDev& o,
                                           double (&V)[MC], double tau0, double dt, int steps,
-                                          double theta, bool homog, double* ftab) {
+                                          double theta, bool homog, double* ftab,
+                                          const int* stop) {
     constexpr int T = 64, CH = kForceChunk - 1;
     const double h = theta * dt, e = (1.0 - theta) * dt;
     auto fill = [&](int m0, int n) {  // entries i = 0..n: step m0 + 1 + i
@@ -132,14 +138,26 @@ __device__ __forceinline__ void piped_run(const BlockTri<64, MC>& S, const Optio
     int n = min(CH, steps);
     if (!homog) fill(0, n);
     S.pipe_begin(V, homog ? 0.0 : ftab[0], homog ? 0.0 : ftab[kForceChunk], P);
+    int sv = 0;
     for (int m0 = 0; m0 < steps;) {
         double lo = homog ? 0.0 : ftab[0], hi = homog ? 0.0 : ftab[kForceChunk];
-        for (int i = 0; i < n; ++i) {
-            const double lo_n = homog ? 0.0 : ftab[i + 1];
-            const double hi_n = homog ? 0.0 : ftab[kForceChunk + i + 1];
-            S.template pipe_step<EX, NST, HI>(P, lo, hi, lo_n, hi_n);
-            lo = lo_n;
-            hi = hi_n;
+        auto run = [&](int i0, int i1) {
+            for (int i = i0; i < i1; ++i) {
+                const double lo_n = homog ? 0.0 : ftab[i + 1];
+                const double hi_n = homog ? 0.0 : ftab[kForceChunk + i + 1];
+                S.template pipe_step<EX, NST, HI>(P, lo, hi, lo_n, hi_n);
+                lo = lo_n;
+                hi = hi_n;
+            }
+        };
+        if constexpr (POLL) {
+            for (int i0 = 0; i0 < n; i0 += kPollSteps) {
+                if (sv) return false;
+                sv = pipe_load(stop);
+                run(i0, min(n, i0 + kPollSteps));
+            }
+        } else {
+            run(0, n);
         }
         m0 += n;
         if (m0 < steps) {
@@ -148,36 +166,42 @@ __device__ __forceinline__ void piped_run(const BlockTri<64, MC>& S, const Optio
         }
     }
     S.pipe_end(P, V);
+    return true;
 }
 
-template <int T, int MC, bool EX, class Solver>
-__device__ __forceinline__ void theta_steps(const Solver& S, const OptionDev& o,
+// Runs `steps` theta-steps on V.  POLL (one-wavefront solver only): stop early
+// when *stop is set, returning false.
+template <int T, int MC, bool EX, class Solver, bool POLL = false>
+__device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
                                             double (&V)[MC], double tau0, double dt, int steps,
-                                            double theta, bool homog, double* lds, double* ftab) {
+                                            double theta, bool homog, double* lds, double* ftab,
+                                            const int* stop = nullptr) {
     // The pipelined one-wavefront steps cover mu = 1 (Crank-Nicolson) and
     // mu = 0 (implicit Euler); any other theta takes the plain step loop.
     if constexpr (IsWaveSolver<Solver>::value) if (!EX || S.mu == 1.0) {
         // HI: row M-1 lies inside a chunk (grid not a multiple of MC) and
         // carries forcing; homogeneous runs have none.
         const bool hi = !homog && S.fc.r_hi != MC - 1;
+#define BSP_RUN(NST_, HI_) \
+    return piped_run<MC, EX, NST_, HI_, POLL>(S, o, V, tau0, dt, steps, theta, homog, ftab, stop)
         if (hi) {
             switch (S.nst) {
-                case 0: piped_run<MC, EX, 0, true>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
-                case 1: piped_run<MC, EX, 1, true>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
-                case 2: piped_run<MC, EX, 2, true>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
-                case 3: piped_run<MC, EX, 3, true>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
-                default: piped_run<MC, EX, -1, true>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+                case 0: BSP_RUN(0, true);
+                case 1: BSP_RUN(1, true);
+                case 2: BSP_RUN(2, true);
+                case 3: BSP_RUN(3, true);
+                default: BSP_RUN(-1, true);
             }
         } else {
             switch (S.nst) {
-                case 0: piped_run<MC, EX, 0, false>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
-                case 1: piped_run<MC, EX, 1, false>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
-                case 2: piped_run<MC, EX, 2, false>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
-                case 3: piped_run<MC, EX, 3, false>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
-                default: piped_run<MC, EX, -1, false>(S, o, V, tau0, dt, steps, theta, homog, ftab); break;
+                case 0: BSP_RUN(0, false);
+                case 1: BSP_RUN(1, false);
+                case 2: BSP_RUN(2, false);
+                case 3: BSP_RUN(3, false);
+                default: BSP_RUN(-1, false);
             }
         }
-        return;
+#undef BSP_RUN
     }
     const double h = theta * dt, e = (1.0 - theta) * dt;
     for (int m0 = 0; m0 < steps; m0 += kForceChunk) {
@@ -205,6 +229,7 @@ __device__ __forceinline__ void theta_steps(const Solver& S, const OptionDev& o,
             S.template step<EX>(V, flo, fhi, lds);
         }
     }
+    return true;
 }
 
 // One option's serial Parareal sweep over slices n = n0..N-1 in one block:
@@ -214,17 +239,24 @@ __device__ __forceinline__ void theta_steps(const Solver& S, const OptionDev& o,
 //            dmax = max |U_new[n+1] - U_old[n+1]|, bad |= non-finite.
 // S (BlockTri, BlockTriH or BlockTriG) must be set up for implicit Euler with
 // dt = dT / coarse_steps.
+// ps (overlapped solve, else null): the slice's fine result is waited for
+// after the coarse solve, U[n+1] is overwritten only once the fine launch
+// of this iteration has read it, and each finished slice is published.
+// Returns false if the block must stop (see PipeSync).
 template <int T, int MC, class Solver>
-__device__ __forceinline__ void sweep_slices(const Solver& S, const OptionDev& o, int M,
+__device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o, int M,
                                              int N, int n0, int coarse_steps, int kind, bool predict,
                                              double dT, double* __restrict__ U,
                                              const double* __restrict__ Fv,
                                              double* __restrict__ Gold,
                                              const double* __restrict__ Vt, double* lds,
-                                             double* ftab, double& dmax, int& bad) {
+                                             double* ftab, double& dmax, int& bad,
+                                             const PipeSync* ps = nullptr,
+                                             const int* stop = nullptr, int* pslot = nullptr) {
     const double dtc = dT / (double)coarse_steps;
     const int i0 = threadIdx.x * MC;
     const bool net = kind != BS_COARSE_IE;
+    if (ps && predict && n0 == 0) pipe_signal(ps->ready, 1);  // U[0], written before the launch
     double V[MC];
     load_chunk<T, MC>(U + (long)n0 * M, M, V);
     for (int n = n0; n < N; ++n) {
@@ -236,7 +268,7 @@ __device__ __forceinline__ void sweep_slices(const Solver& S, const OptionDev& o
         double fv[MC], gold[MC], uold[MC], vt0[MC], vt1[MC];
         if constexpr (kPrefetch) {
             if (!predict) {
-                load_chunk<T, MC>(Fv + (long)n * M, M, fv);
+                if (!ps) load_chunk<T, MC>(Fv + (long)n * M, M, fv);
                 load_chunk<T, MC>(go, M, gold);
                 load_chunk<T, MC>(un1, M, uold);
             }
@@ -268,6 +300,12 @@ __device__ __forceinline__ void sweep_slices(const Solver& S, const OptionDev& o
             for (int q = 0; q < MC; ++q)
                 g[q] = (kPrefetch ? vt1[q] : ((i0 + q < M) ? vn1[i0 + q] : 0.0)) + g[q];
         }
+        if (ps && !predict) {
+            // this iteration's fine result of slice n, then U[n+1] free to overwrite
+            if (!pipe_wait(*ps, ps->fdone + n, ps->k, stop, pslot)) return false;
+            if constexpr (kPrefetch) load_chunk<T, MC>(Fv + (long)n * M, M, fv);
+            if (n + 1 < N && !pipe_wait(*ps, ps->taken + n + 1, ps->k, stop, pslot)) return false;
+        }
         if (predict) {
             store_chunk<T, MC>(un1, M, g);
             store_chunk<T, MC>(go, M, g);
@@ -292,7 +330,9 @@ __device__ __forceinline__ void sweep_slices(const Solver& S, const OptionDev& o
                 }
             }
         }
+        if (ps) pipe_signal(ps->ready + n + 1, predict ? 1 : ps->k + 1);
     }
+    return true;
 }
 
 // Block max of dmax and OR of bad; the result is valid in thread 0.

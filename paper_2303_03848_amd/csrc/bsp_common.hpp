@@ -124,9 +124,13 @@ __device__ __forceinline__ int pipe_load(const int* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Block-wide wait for *f >= v: thread 0 polls, the outcome is shared through
-// *slot (LDS), and every thread then orders its later loads after the
-// producer's stores.  Returns false if the block must stop (stop or error).
+// Block-wide wait for *f >= v: thread 0 polls and the outcome is shared
+// through *slot (LDS).  ACQ: every thread then orders its later loads after
+// the producer's stores (needed when the block reads what the producer
+// wrote; a wait that only orders this block's later stores after the
+// producer's loads needs no fence).  Returns false if the block must stop
+// (stop or error).
+template <bool ACQ = true>
 __device__ inline bool pipe_wait(const PipeSync& ps, const int* f, int v, const int* stop,
                                  int* slot) {
     __syncthreads();  // slot may still be read from the previous wait
@@ -151,8 +155,14 @@ __device__ inline bool pipe_wait(const PipeSync& ps, const int* f, int v, const 
     }
     __syncthreads();
     const bool ok = *slot != 0;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if constexpr (ACQ) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return ok;
+}
+
+// Publishes *f = v once the block's loads have completed (it wrote nothing
+// the reader needs): after a barrier that follows their use.
+__device__ inline void pipe_mark(int* f, int v) {
+    if (threadIdx.x == 0) __hip_atomic_store(f, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Publishes *f = v after every thread's stores of the block.

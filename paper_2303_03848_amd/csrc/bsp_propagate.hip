@@ -88,36 +88,51 @@ __device__ __forceinline__ void sweep_record(const SweepArgs& a, double dmax, in
 }
 
 // One block per system.  PIPE (overlapped Parareal solve): system sys is
-// slice n = sys + sys_offset of iteration ps.k; it waits until U[n] holds
-// iterate k-1, reports having read it, polls the stop flag while stepping,
-// and writes Fv[n] only after the sweep of iteration k-1 has consumed the
-// previous one (U[n+1] holds iterate k-1).
+// slice n = sys + sys_offset of iteration ps.k.  Everything that does not
+// depend on the state (factors, the first forcing table) is built first;
+// then it waits until U[n] holds iterate k-1, reports having read it, polls
+// the stop flag while stepping, and writes Fv[n] only after the sweep of
+// iteration k-1 has consumed the previous one (U[n+1] holds iterate k-1).
+// smem: the solver's LDS, the forcing tables, and (PIPE) the staging area
+// of the state, kept apart from the tables built before the load.
 template <int T, int MC, bool PIPE>
 __device__ __forceinline__ void theta_body(const ThetaArgs& a, double* smem, int* pslot) {
     double* lds = smem;
     double* ftab = smem + 4 * T;
+    double* stage = PIPE ? smem + smem_doubles<T>() : smem;
     if (stopped(a.stop)) return;
     const int sys = blockIdx.x;
     const int n = sys + a.sys_offset;
-    if constexpr (PIPE)
-        if (!pipe_wait(a.ps, a.ps.ready + n, a.ps.k, a.stop, pslot)) return;
-    double V[MC];
-    load_system<T, MC>(a.u_in + (long)sys * a.ld_in, a.M, V, smem);
-    if constexpr (PIPE) pipe_signal(a.ps.taken + n, a.ps.k);
+    const double tau0 = a.tau0 ? a.tau0[sys] : a.tau_start + (double)n * a.tau_stride;
     using S_t = Solver<T, MC>;
     S_t S;
-    S.setup(a.o.s2, a.o.r, a.theta * a.dt, (1.0 - a.theta) * a.dt, a.M, lds);
-    const double tau0 = a.tau0 ? a.tau0[sys] : a.tau_start + (double)n * a.tau_stride;
+    double V[MC];
+    bool prefilled = false;
+    if constexpr (PIPE) {
+        S.setup(a.o.s2, a.o.r, a.theta * a.dt, (1.0 - a.theta) * a.dt, a.M, lds);
+        const bool ex = a.theta != 1.0;
+        if (!a.homog && (ex ? piped_path<true>(S) : piped_path<false>(S))) {
+            fill_piped_table<T>(a.o, tau0, a.dt, a.steps, a.theta, 0,
+                                min(kForceChunk - 1, a.steps), ftab);
+            prefilled = true;
+        }
+        if (!pipe_wait(a.ps, a.ps.ready + n, a.ps.k, a.stop, pslot)) return;
+        load_system<T, MC>(a.u_in + (long)sys * a.ld_in, a.M, V, stage);
+        pipe_mark(a.ps.taken + n, a.ps.k);
+    } else {
+        load_system<T, MC>(a.u_in + (long)sys * a.ld_in, a.M, V, stage);
+        S.setup(a.o.s2, a.o.r, a.theta * a.dt, (1.0 - a.theta) * a.dt, a.M, lds);
+    }
     const bool ok =
         (a.theta == 1.0)
             ? theta_steps<T, MC, false, S_t, PIPE>(S, a.o, V, tau0, a.dt, a.steps, 1.0,
-                                                   a.homog != 0, lds, ftab, a.stop)
+                                                   a.homog != 0, lds, ftab, a.stop, prefilled)
             : theta_steps<T, MC, true, S_t, PIPE>(S, a.o, V, tau0, a.dt, a.steps, a.theta,
-                                                  a.homog != 0, lds, ftab, a.stop);
+                                                  a.homog != 0, lds, ftab, a.stop, prefilled);
     if (!ok) return;
     if constexpr (PIPE)
-        if (!pipe_wait(a.ps, a.ps.ready + n + 1, a.ps.k, a.stop, pslot)) return;
-    store_system<T, MC>(a.u_out + (long)sys * a.ld_out, a.M, V, smem);
+        if (!pipe_wait<false>(a.ps, a.ps.ready + n + 1, a.ps.k, a.stop, pslot)) return;
+    store_system<T, MC>(a.u_out + (long)sys * a.ld_out, a.M, V, stage);
     if constexpr (PIPE) pipe_signal(a.ps.fdone + n, a.ps.k);
 }
 
@@ -129,7 +144,7 @@ __global__ __launch_bounds__(T) void k_theta_batch(ThetaArgs a) {
 
 template <int T, int MC>
 __global__ __launch_bounds__(T) void k_theta_pipe(ThetaArgs a) {
-    __shared__ double smem[smem_doubles<T>()];
+    __shared__ double smem[smem_doubles<T>() + T * MC];
     __shared__ int pslot;
     theta_body<T, MC, true>(a, smem, &pslot);
 }

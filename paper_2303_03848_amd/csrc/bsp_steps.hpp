@@ -110,33 +110,43 @@ struct IsWaveSolver<BlockTri<64, MC>> : std::true_type {};
 // false when it is set; the state is then left half-propagated.
 constexpr int kPollSteps = 64;
 
+// Forcing table of the pipelined steps for steps m0+1 .. m0+n+1 (entries
+// past the last step are zero), built by the block's T threads.
+template <int T>
+__device__ __forceinline__ void fill_piped_table(const OptionDev& o, double tau0, double dt,
+                                                 int steps, double theta, int m0, int n,
+                                                 double* ftab) {
+    const double h = theta * dt, e = (1.0 - theta) * dt;
+    __syncthreads();
+    for (int i = threadIdx.x; i <= n; i += T) {
+        const int m = m0 + 1 + i;
+        double lo = 0.0, hi = 0.0;
+        if (m <= steps) {
+            double lo0, hi0, lo1, hi1;
+            dirichlet(o, exp(-o.r * (tau0 + (double)(m - 1) * dt)), lo0, hi0);
+            dirichlet(o, exp(-o.r * (tau0 + (double)m * dt)), lo1, hi1);
+            lo = fma(e, lo0, h * lo1);
+            hi = fma(e, hi0, h * hi1);
+        }
+        ftab[i] = lo;
+        ftab[kForceChunk + i] = hi;
+    }
+    __syncthreads();
+}
+
+// prefilled: the first table (m0 = 0) is already in ftab.
 template <int MC, bool EX, int NST, bool HI, bool POLL>
 __device__ __forceinline__ bool piped_run(const BlockTri<64, MC>& S, const OptionDev& o,
                                           double (&V)[MC], double tau0, double dt, int steps,
                                           double theta, bool homog, double* ftab,
-                                          const int* stop) {
+                                          const int* stop, bool prefilled) {
     constexpr int T = 64, CH = kForceChunk - 1;
-    const double h = theta * dt, e = (1.0 - theta) * dt;
     auto fill = [&](int m0, int n) {  // entries i = 0..n: step m0 + 1 + i
-        __syncthreads();
-        for (int i = threadIdx.x; i <= n; i += T) {
-            const int m = m0 + 1 + i;
-            double lo = 0.0, hi = 0.0;
-            if (m <= steps) {
-                double lo0, hi0, lo1, hi1;
-                dirichlet(o, exp(-o.r * (tau0 + (double)(m - 1) * dt)), lo0, hi0);
-                dirichlet(o, exp(-o.r * (tau0 + (double)m * dt)), lo1, hi1);
-                lo = fma(e, lo0, h * lo1);
-                hi = fma(e, hi0, h * hi1);
-            }
-            ftab[i] = lo;
-            ftab[kForceChunk + i] = hi;
-        }
-        __syncthreads();
+        fill_piped_table<T>(o, tau0, dt, steps, theta, m0, n, ftab);
     };
     typename BlockTri<64, MC>::Pipe P;
     int n = min(CH, steps);
-    if (!homog) fill(0, n);
+    if (!homog && !prefilled) fill(0, n);
     S.pipe_begin(V, homog ? 0.0 : ftab[0], homog ? 0.0 : ftab[kForceChunk], P);
     int sv = 0;
     for (int m0 = 0; m0 < steps;) {
@@ -169,13 +179,21 @@ __device__ __forceinline__ bool piped_run(const BlockTri<64, MC>& S, const Optio
     return true;
 }
 
+// True when theta_steps takes the pipelined one-wavefront path.
+template <bool EX, class Solver>
+__device__ __forceinline__ bool piped_path(const Solver& S) {
+    if constexpr (IsWaveSolver<Solver>::value) return !EX || S.mu == 1.0;
+    return false;
+}
+
 // Runs `steps` theta-steps on V.  POLL (one-wavefront solver only): stop early
-// when *stop is set, returning false.
+// when *stop is set, returning false.  prefilled: on the pipelined path the
+// first forcing table is already in ftab (fill_piped_table with m0 = 0).
 template <int T, int MC, bool EX, class Solver, bool POLL = false>
 __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
                                             double (&V)[MC], double tau0, double dt, int steps,
                                             double theta, bool homog, double* lds, double* ftab,
-                                            const int* stop = nullptr) {
+                                            const int* stop = nullptr, bool prefilled = false) {
     // The pipelined one-wavefront steps cover mu = 1 (Crank-Nicolson) and
     // mu = 0 (implicit Euler); any other theta takes the plain step loop.
     if constexpr (IsWaveSolver<Solver>::value) if (!EX || S.mu == 1.0) {
@@ -183,7 +201,8 @@ __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
         // carries forcing; homogeneous runs have none.
         const bool hi = !homog && S.fc.r_hi != MC - 1;
 #define BSP_RUN(NST_, HI_) \
-    return piped_run<MC, EX, NST_, HI_, POLL>(S, o, V, tau0, dt, steps, theta, homog, ftab, stop)
+    return piped_run<MC, EX, NST_, HI_, POLL>(S, o, V, tau0, dt, steps, theta, homog, ftab, stop, \
+                                              prefilled)
         if (hi) {
             switch (S.nst) {
                 case 0: BSP_RUN(0, true);
@@ -304,7 +323,8 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
             // this iteration's fine result of slice n, then U[n+1] free to overwrite
             if (!pipe_wait(*ps, ps->fdone + n, ps->k, stop, pslot)) return false;
             if constexpr (kPrefetch) load_chunk<T, MC>(Fv + (long)n * M, M, fv);
-            if (n + 1 < N && !pipe_wait(*ps, ps->taken + n + 1, ps->k, stop, pslot)) return false;
+            if (n + 1 < N && !pipe_wait<false>(*ps, ps->taken + n + 1, ps->k, stop, pslot))
+                return false;
         }
         if (predict) {
             store_chunk<T, MC>(un1, M, g);

@@ -355,11 +355,18 @@ struct BlockTri {
     __device__ __forceinline__ void pipe_step(Pipe& P, double flo, double fhi, double flo_n,
                                               double fhi_n) const {
         double y[NI], xi[NI];
-#pragma unroll
-        for (int q = 0; q < NI; ++q) y[q] = fma(P.zl, al[q], fma(P.z, be[q], P.A[q]));
+        // y just ahead of the backward chain that consumes it, so that each
+        // link of the chain has independent work beside it
+        y[NI - 1] = fma(P.zl, al[NI - 1], fma(P.z, be[NI - 1], P.A[NI - 1]));
+        if (NI >= 2) y[NI - 2] = fma(P.zl, al[NI - 2], fma(P.z, be[NI - 2], P.A[NI - 2]));
         xi[NI - 1] = y[NI - 1];
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int q = NI - 2; q >= 0; --q) xi[q] = fma(-ch[q], xi[q + 1], y[q]);
+        for (int q = NI - 2; q >= 0; --q) {
+            if (q >= 1) y[q - 1] = fma(P.zl, al[q - 1], fma(P.z, be[q - 1], P.A[q - 1]));
+            xi[q] = fma(-ch[q], xi[q + 1], y[q]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
         const double xF = dpp_from_next(xi[0]);  // xi_0 of the next chunk
         double D = fma(kap, P.Vi, fma(fc.bhiD, fhi, fma(-aqk, xi[NI - 1], -cqk * xF)));
         // interface reduction

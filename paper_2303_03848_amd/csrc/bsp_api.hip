@@ -158,11 +158,12 @@ static int prof_collect(int slot, double cells) {
     return BS_OK;
 }
 
-// Initial state, network grid (network kinds) and the prediction sweep.
-// ps: progress counters of the overlapped solve (the sweep publishes U[n]).
+// Initial state, network grid (network kinds) and (predict) the prediction
+// sweep.  ps: progress counters of the overlapped solve (the sweep publishes
+// U[n]).
 static int start_impl(const bs_params* prm, const bs_grid* grid, const bs_slices* sl, int kind,
                       const pinn_net* net, void* ws, double* U, const PipeSync* ps,
-                      hipStream_t st) {
+                      hipStream_t st, bool predict = true) {
     int rc;
     const int M = grid->M, N = sl->N;
     const OptionDev o = make_option(*prm, M);
@@ -172,6 +173,7 @@ static int start_impl(const bs_params* prm, const bs_grid* grid, const bs_slices
     if (kind != BS_COARSE_IE) {
         if ((rc = launch_pinn_grid(*net, o, M, N, dT, w.Vt, st))) return rc;
     }
+    if (!predict) return BS_OK;
     SweepArgs a{o, M, N, 0, sl->coarse_steps, kind, 1, dT, U, w.Fv, w.Gold, w.Vt, w.result};
     if (ps) {
         a.ps = *ps;
@@ -372,6 +374,85 @@ static int solve_streams() {
     return BS_OK;
 }
 
+// Whole solve in one launch (grids covered by k_parareal_persist): initial
+// state and network grid, then the persistent kernel, which runs the
+// prediction and every iteration and records each iteration's defect in
+// the host-mapped history; the host reads the history once the stream has
+// drained.  The stop flag must already be clear on st.
+static int solve_persistent(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,
+                            int kind, double tol, const pinn_net* net, int kmax, void* ws,
+                            double* U, int* iters, double* defect_hist, hipStream_t st) {
+    int rc;
+    const int M = grid->M, N = sl->N;
+    SolveState& S = t_solve;
+    for (size_t i = 0; i < 2 * (size_t)(kmax + 1); ++i) S.hist[i] = -1.0;  // not reached
+    Workspace w = ws_layout(ws, M, N, kind);
+    PipeSync ps{};
+    ps.ready = w.flags;
+    ps.taken = w.flags + (N + 1);
+    ps.fdone = w.flags + 2 * (N + 1);
+    ps.err = w.flags + 3 * (N + 1);
+    if ((rc = launch_fill_int(w.flags, flag_count(N), 0, st))) return rc;
+    if ((rc = start_impl(prm, grid, sl, kind, net, ws, U, nullptr, st, false))) return rc;
+    PersistArgs a{};
+    a.o = make_option(*prm, M);
+    a.M = M;
+    a.N = N;
+    a.kmax = kmax;
+    a.fine_steps = sl->fine_steps;
+    a.coarse_steps = sl->coarse_steps;
+    a.kind = kind;
+    a.dT = prm->T / N;
+    a.tol = tol;
+    a.U = U;
+    a.Fv = w.Fv;
+    a.Gold = w.Gold;
+    a.Vt = w.Vt;
+    a.result = w.result;
+    a.stop = reinterpret_cast<int*>(w.result + 4);
+    a.hist = S.hist_dev;
+    a.ps = ps;
+    const bool prof = g_prof.on;
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[0], st));
+    if ((rc = launch_parareal_persist(a, st))) return rc;
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[1], st));
+    int err = 0;
+    BSP_HIP(hipMemcpyAsync(&err, ps.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    BSP_HIP(hipStreamSynchronize(st));
+    if (err) {
+        set_error("Parareal solve: a launch waited longer than its time limit");
+        return BS_ERR_HIP;
+    }
+    // the first iteration that met the stopping rule (or kmax)
+    const volatile double* hist = S.hist;
+    int status = BS_NOT_CONVERGED, last = 0;
+    for (int j = 1; j <= kmax; ++j) {
+        const double d = hist[2 * j], bad = hist[2 * j + 1];
+        if (d < 0.0) break;  // not reached
+        if (defect_hist) defect_hist[j - 1] = d;
+        last = j;
+        if (bad != 0.0) {
+            status = BS_ERR_NONFINITE;
+            break;
+        }
+        if (d <= tol || j == N) {
+            status = BS_OK;
+            break;
+        }
+    }
+    *iters = last;
+    if (prof) {
+        float ms = 0.f;
+        BSP_HIP(hipEventElapsedTime(&ms, g_prof.ev[0], g_prof.ev[1]));
+        g_prof.fine_ms += ms;
+        g_prof.fine_launches += 1;
+        for (int k = 1; k <= last; ++k) g_prof.fine_cells += iteration_cells(grid, sl, k);
+    }
+    if (status == BS_ERR_NONFINITE)
+        set_error("non-finite value in the Parareal state at iteration %d", last);
+    return status;
+}
+
 extern "C" {
 
 int parareal_iterate(const bs_params* prm, const bs_grid* grid, const bs_slices* sl, int kind,
@@ -405,6 +486,9 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
     Workspace w = ws_layout(ws, grid->M, N, kind);
     int* stop = reinterpret_cast<int*>(w.result + 4);
     if ((rc = launch_set_int(stop, 0, st))) return rc;
+    if (persist_capable(grid->M, N))
+        return solve_persistent(prm, grid, sl, kind, tol, net, kmax, ws, U, iters, defect_hist,
+                                st);
 
     // Overlapped iterations (grids the one-block sweep and the per-system
     // fine kernel cover): the fine launch of iteration k runs on a side

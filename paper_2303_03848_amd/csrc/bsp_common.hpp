@@ -159,6 +159,46 @@ __device__ inline bool pipe_wait(const PipeSync& ps, const int* f, int v, const 
     return ok;
 }
 
+// The same for a wavefront working on its own (the block's other wavefronts
+// do unrelated work): every lane polls the same counter, so the outcome is
+// uniform without LDS or a barrier.
+template <bool ACQ = true>
+__device__ inline bool pipe_wait_wave(const PipeSync& ps, const int* f, int v, const int* stop) {
+    bool ok = true;
+    if (__builtin_amdgcn_readfirstlane(pipe_load(f)) < v) {
+        const long long t0 = wall_clock64();
+        while (__builtin_amdgcn_readfirstlane(pipe_load(f)) < v) {
+            if ((stop && __builtin_amdgcn_readfirstlane(pipe_load(stop))) ||
+                __builtin_amdgcn_readfirstlane(pipe_load(ps.err))) {
+                ok = false;
+                break;
+            }
+            if (wall_clock64() - t0 > kPipeSpinTicks) {
+                if ((threadIdx.x & 63) == 0)
+                    __hip_atomic_store(ps.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = false;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    if constexpr (ACQ) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok;
+}
+
+__device__ inline void pipe_signal_wave(int* f, int v) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if ((threadIdx.x & 63) == 0)
+        __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Orders this wavefront's LDS accesses (lanes exchanging data through LDS
+// without a block barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // Publishes *f = v once the block's loads have completed (it wrote nothing
 // the reader needs): after a barrier that follows their use.
 __device__ inline void pipe_mark(int* f, int v) {
@@ -204,6 +244,23 @@ struct SweepArgs {
     PipeSync ps;  // overlapped solve (ps.ready null: not overlapped)
 };
 int launch_sweep(const SweepArgs& a, hipStream_t stream);
+
+// Whole overlapped solve in one cooperative launch (see k_parareal_persist).
+struct PersistArgs {
+    OptionDev o;
+    int M, N, kmax, fine_steps, coarse_steps, kind, nfb, nsb;
+    double dT, tol;
+    double* U;
+    double* Fv;
+    double* Gold;
+    const double* Vt;
+    double* result;
+    int* stop;
+    double* hist;  // host-mapped record [2 (kmax+1)]
+    PipeSync ps;
+};
+bool persist_capable(int M, int N);
+int launch_parareal_persist(const PersistArgs& a, hipStream_t stream);
 int launch_set_int(int* p, int v, hipStream_t stream);  // *p = v in stream order
 int launch_fill_int(int* p, int n, int v, hipStream_t stream);  // p[0..n) = v
 bool pipe_capable(int M);  // the overlapped solve covers grids of this size

@@ -161,14 +161,141 @@ __global__ __launch_bounds__(T) void k_sweep(SweepArgs a) {
     S.setup(a.o.s2, a.o.r, a.dT / (double)a.coarse_steps, 0.0, a.M, lds);
     double dmax = 0.0;
     int bad = 0;
+    const PipeSync ps = a.ps;
     if (!sweep_slices<T, MC>(S, a.o, a.M, a.N, a.n0, a.coarse_steps, a.kind, a.predict != 0, a.dT,
-                             a.U, a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad,
-                             a.ps.ready ? &a.ps : nullptr, a.stop, &pslot))
+                             a.U, a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad, ps,
+                             ps.ready != nullptr, a.stop, &pslot))
         return;
     if (!a.predict) {
         block_defect<T>(dmax, bad, lds);
         if (threadIdx.x == 0) sweep_record(a, dmax, bad);
     }
+}
+
+// ------------------------------------------------------ persistent solve
+
+// A whole Parareal solve in one launch, for grids whose fine kernel is one
+// wavefront per system and whose sweep runs on 256 threads.  Blocks
+// 0 .. nfb-1 hold four fine wavefronts each: wavefront w of block b owns
+// slice n = 4b + w for every iteration, building its factors and forcing
+// table once; per iteration it waits until U[n] holds the previous iterate,
+// propagates it, and publishes Fv[n].  The remaining nsb blocks sweep: block
+// j runs iterations k = j, j + nsb, ... (k = 0 is the coarse prediction), so
+// the sweep of iteration k+1 follows the sweep of iteration k slice by slice
+// instead of waiting for it to end.  Every hand-off goes through the
+// progress counters of PipeSync; the iterates are those of the
+// launch-after-launch iteration with the same block shapes.
+template <int MCF>
+constexpr int persist_fine_lds() {  // doubles per fine wavefront
+    return 2 * kForceChunk + 64 * MCF;
+}
+
+template <int MCF>
+__device__ __forceinline__ void persist_fine(const PersistArgs& a, double* smem) {
+    const int w = threadIdx.x >> 6;
+    const int n = 4 * (int)blockIdx.x + w;
+    if (n >= a.N) return;  // the role has no block-wide barrier
+    double* ftab = smem + w * persist_fine_lds<MCF>();
+    double* stage = ftab + 2 * kForceChunk;
+    const double dt = a.dT / (double)a.fine_steps;
+    const double tau0 = (double)n * a.dT;
+    BlockTri<64, MCF> S;
+    S.setup(a.o.s2, a.o.r, 0.5 * dt, 0.5 * dt, a.M, nullptr);
+    const bool pre = a.fine_steps <= kForceChunk - 1;  // one table serves every iteration
+    if (pre) fill_piped_table<64, true>(a.o, tau0, dt, a.fine_steps, 0.5, 0, a.fine_steps, ftab);
+    const int klast = min(a.kmax, n + 1);  // iteration k propagates slices n >= k-1
+    for (int k = 1; k <= klast; ++k) {
+        if (!pipe_wait_wave(a.ps, a.ps.ready + n, k, a.stop)) return;
+        double V[MCF];
+        load_system<64, MCF, true>(a.U + (long)n * a.M, a.M, V, stage);
+        if ((threadIdx.x & 63) == 0)
+            __hip_atomic_store(a.ps.taken + n, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!theta_steps<64, MCF, true, BlockTri<64, MCF>, true, true>(
+                S, a.o, V, tau0, dt, a.fine_steps, 0.5, false, nullptr, ftab, a.stop, pre))
+            return;
+        if (!pipe_wait_wave<false>(a.ps, a.ps.ready + n + 1, k, a.stop)) return;
+        store_system<64, MCF, true>(a.Fv + (long)n * a.M, a.M, V, stage);
+        pipe_signal_wave(a.ps.fdone + n, k);
+    }
+}
+
+template <int MCS>
+__device__ __forceinline__ void persist_sweep(const PersistArgs& a, int j, double* smem,
+                                              int* pslot) {
+    constexpr int T = 256;
+    double* lds = smem;
+    double* ftab = smem + 4 * T;
+    Solver<T, MCS> S;
+    S.setup(a.o.s2, a.o.r, a.dT / (double)a.coarse_steps, 0.0, a.M, lds);
+    for (int k = j; k <= a.kmax; k += a.nsb) {
+        const bool predict = k == 0;
+        const int n0 = predict ? 0 : min(k - 1, a.N - 1);
+        PipeSync ps = a.ps;
+        ps.k = k;
+        // the sweep's first state U[n0] (iterate k; for k >= 1 written by the
+        // sweep of iteration k-1)
+        if (!predict && !pipe_wait(ps, ps.ready + n0, k, a.stop, pslot)) return;
+        double dmax = 0.0;
+        int bad = 0;
+        if (!sweep_slices<T, MCS>(S, a.o, a.M, a.N, n0, a.coarse_steps, a.kind, predict, a.dT,
+                                  a.U, a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad, ps, true,
+                                  a.stop, pslot))
+            return;
+        if (!predict) {
+            block_defect<T>(dmax, bad, lds);
+            if (threadIdx.x == 0) {
+                SweepArgs sa{};
+                sa.result = a.result;
+                sa.stop = a.stop;
+                sa.hist = a.hist;
+                sa.tol = a.tol;
+                sa.k = k;
+                sweep_record(sa, dmax, bad);
+            }
+        }
+    }
+}
+
+template <int MCF, int MCS>
+__global__ __launch_bounds__(256) void k_parareal_persist(PersistArgs a) {
+    static_assert(4 * persist_fine_lds<MCF>() >= 4 * 256 + 2 * kForceChunk, "sweep LDS");
+    __shared__ double smem[4 * persist_fine_lds<MCF>()];
+    __shared__ int pslot;
+    if ((int)blockIdx.x < a.nfb)
+        persist_fine<MCF>(a, smem);
+    else
+        persist_sweep<MCS>(a, (int)blockIdx.x - a.nfb, smem, &pslot);
+}
+
+constexpr int kPersistMaxN = 512;
+
+bool persist_capable(int M, int N) {
+    const TriShape f = shape_for(0, M), w = shape_for(1, M);
+    return N <= kPersistMaxN && f.T == 64 && (f.MC == 2 || f.MC == 4 || f.MC == 8 ||
+                                              f.MC == 16) && w.T == 256 && w.MC == 4;
+}
+
+int launch_parareal_persist(const PersistArgs& in, hipStream_t stream) {
+    PersistArgs a = in;
+    if (!persist_capable(a.M, a.N)) {
+        set_error("no persistent solve for M = %d, N = %d with the current block shapes", a.M, a.N);
+        return BS_ERR_ARG;
+    }
+    a.nfb = (a.N + 3) / 4;
+    a.nsb = min(3, a.kmax + 1);
+    void* args[] = {&a};
+    const dim3 grid(a.nfb + a.nsb), block(256);
+    const TriShape f = shape_for(0, a.M);
+    const void* fn = nullptr;
+    switch (f.MC) {
+        case 2: fn = (const void*)k_parareal_persist<2, 4>; break;
+        case 4: fn = (const void*)k_parareal_persist<4, 4>; break;
+        case 8: fn = (const void*)k_parareal_persist<8, 4>; break;
+        default: fn = (const void*)k_parareal_persist<16, 4>; break;
+    }
+    // co-resident blocks are required (they wait on each other)
+    BSP_HIP(hipLaunchCooperativeKernel(fn, grid, block, args, 0, stream));
+    return BS_OK;
 }
 
 // ------------------------------------------------------- large grids

@@ -54,33 +54,46 @@ constexpr int smem_doubles() {
     return 4 * T + 2 * kForceChunk;
 }
 
-// Whole-system load through shared memory.  Uses all of smem: call it before
-// the solver's setup.
-template <int T, int MC>
+// Barrier of the threads working on one system: the block, or (WAVE) one
+// wavefront that works on its own system.
+template <bool WAVE>
+__device__ __forceinline__ void system_sync() {
+    if constexpr (WAVE)
+        wave_lds_sync();
+    else
+        __syncthreads();
+}
+
+// Whole-system load through shared memory (T * MC doubles of smem).  Uses
+// all of smem: call it before the solver's setup.  WAVE: T = 64 and the
+// system belongs to the calling wavefront alone.
+template <int T, int MC, bool WAVE = false>
 __device__ __forceinline__ void load_system(const double* __restrict__ src, int M, double (&V)[MC],
                                             double* smem) {
     static_assert(T * MC <= smem_doubles<T>(), "staging area too small");
-    const int p = threadIdx.x;
+    static_assert(!WAVE || T == 64, "one wavefront");
+    const int p = WAVE ? (threadIdx.x & 63) : threadIdx.x;
 #pragma unroll
     for (int k = 0; k < MC; ++k) {
         const int i = k * T + p;
         smem[i] = (i < M) ? src[i] : 0.0;
     }
-    __syncthreads();
+    system_sync<WAVE>();
 #pragma unroll
     for (int q = 0; q < MC; ++q) V[q] = smem[p * MC + q];
-    __syncthreads();
+    system_sync<WAVE>();
 }
 
 // Whole-system store through shared memory, once the solver is done with it.
-template <int T, int MC>
+template <int T, int MC, bool WAVE = false>
 __device__ __forceinline__ void store_system(double* __restrict__ dst, int M, const double (&V)[MC],
                                              double* smem) {
-    const int p = threadIdx.x;
-    __syncthreads();
+    static_assert(!WAVE || T == 64, "one wavefront");
+    const int p = WAVE ? (threadIdx.x & 63) : threadIdx.x;
+    system_sync<WAVE>();
 #pragma unroll
     for (int q = 0; q < MC; ++q) smem[p * MC + q] = V[q];
-    __syncthreads();
+    system_sync<WAVE>();
 #pragma unroll
     for (int k = 0; k < MC; ++k) {
         const int i = k * T + p;
@@ -112,13 +125,13 @@ constexpr int kPollSteps = 64;
 
 // Forcing table of the pipelined steps for steps m0+1 .. m0+n+1 (entries
 // past the last step are zero), built by the block's T threads.
-template <int T>
+template <int T, bool WAVE = false>
 __device__ __forceinline__ void fill_piped_table(const OptionDev& o, double tau0, double dt,
                                                  int steps, double theta, int m0, int n,
                                                  double* ftab) {
     const double h = theta * dt, e = (1.0 - theta) * dt;
-    __syncthreads();
-    for (int i = threadIdx.x; i <= n; i += T) {
+    system_sync<WAVE>();
+    for (int i = WAVE ? (threadIdx.x & 63) : threadIdx.x; i <= n; i += T) {
         const int m = m0 + 1 + i;
         double lo = 0.0, hi = 0.0;
         if (m <= steps) {
@@ -131,18 +144,18 @@ __device__ __forceinline__ void fill_piped_table(const OptionDev& o, double tau0
         ftab[i] = lo;
         ftab[kForceChunk + i] = hi;
     }
-    __syncthreads();
+    system_sync<WAVE>();
 }
 
 // prefilled: the first table (m0 = 0) is already in ftab.
-template <int MC, bool EX, int NST, bool HI, bool POLL>
+template <int MC, bool EX, int NST, bool HI, bool POLL, bool WAVE>
 __device__ __forceinline__ bool piped_run(const BlockTri<64, MC>& S, const OptionDev& o,
                                           double (&V)[MC], double tau0, double dt, int steps,
                                           double theta, bool homog, double* ftab,
                                           const int* stop, bool prefilled) {
     constexpr int T = 64, CH = kForceChunk - 1;
     auto fill = [&](int m0, int n) {  // entries i = 0..n: step m0 + 1 + i
-        fill_piped_table<T>(o, tau0, dt, steps, theta, m0, n, ftab);
+        fill_piped_table<T, WAVE>(o, tau0, dt, steps, theta, m0, n, ftab);
     };
     typename BlockTri<64, MC>::Pipe P;
     int n = min(CH, steps);
@@ -189,11 +202,14 @@ __device__ __forceinline__ bool piped_path(const Solver& S) {
 // Runs `steps` theta-steps on V.  POLL (one-wavefront solver only): stop early
 // when *stop is set, returning false.  prefilled: on the pipelined path the
 // first forcing table is already in ftab (fill_piped_table with m0 = 0).
-template <int T, int MC, bool EX, class Solver, bool POLL = false>
+// WAVE: the calling wavefront works on this system alone (one-wavefront
+// solver, Crank-Nicolson or implicit Euler).
+template <int T, int MC, bool EX, class Solver, bool POLL = false, bool WAVE = false>
 __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
                                             double (&V)[MC], double tau0, double dt, int steps,
                                             double theta, bool homog, double* lds, double* ftab,
                                             const int* stop = nullptr, bool prefilled = false) {
+    static_assert(!WAVE || IsWaveSolver<Solver>::value, "wavefront-level runs need BlockTri");
     // The pipelined one-wavefront steps cover mu = 1 (Crank-Nicolson) and
     // mu = 0 (implicit Euler); any other theta takes the plain step loop.
     if constexpr (IsWaveSolver<Solver>::value) if (!EX || S.mu == 1.0) {
@@ -201,8 +217,8 @@ __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
         // carries forcing; homogeneous runs have none.
         const bool hi = !homog && S.fc.r_hi != MC - 1;
 #define BSP_RUN(NST_, HI_) \
-    return piped_run<MC, EX, NST_, HI_, POLL>(S, o, V, tau0, dt, steps, theta, homog, ftab, stop, \
-                                              prefilled)
+    return piped_run<MC, EX, NST_, HI_, POLL, WAVE>(S, o, V, tau0, dt, steps, theta, homog, ftab, \
+                                                    stop, prefilled)
         if (hi) {
             switch (S.nst) {
                 case 0: BSP_RUN(0, true);
@@ -258,10 +274,10 @@ __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
 //            dmax = max |U_new[n+1] - U_old[n+1]|, bad |= non-finite.
 // S (BlockTri, BlockTriH or BlockTriG) must be set up for implicit Euler with
 // dt = dT / coarse_steps.
-// ps (overlapped solve, else null): the slice's fine result is waited for
-// after the coarse solve, U[n+1] is overwritten only once the fine launch
-// of this iteration has read it, and each finished slice is published.
-// Returns false if the block must stop (see PipeSync).
+// pipe (overlapped solve; ps its counters): the slice's fine result is
+// waited for after the coarse solve, U[n+1] is overwritten only once the
+// fine launch of this iteration has read it, and each finished slice is
+// published.  Returns false if the block must stop (see PipeSync).
 template <int T, int MC, class Solver>
 __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o, int M,
                                              int N, int n0, int coarse_steps, int kind, bool predict,
@@ -270,12 +286,12 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
                                              double* __restrict__ Gold,
                                              const double* __restrict__ Vt, double* lds,
                                              double* ftab, double& dmax, int& bad,
-                                             const PipeSync* ps = nullptr,
+                                             const PipeSync& ps = PipeSync{}, bool pipe = false,
                                              const int* stop = nullptr, int* pslot = nullptr) {
     const double dtc = dT / (double)coarse_steps;
     const int i0 = threadIdx.x * MC;
     const bool net = kind != BS_COARSE_IE;
-    if (ps && predict && n0 == 0) pipe_signal(ps->ready, 1);  // U[0], written before the launch
+    if (pipe && predict && n0 == 0) pipe_signal(ps.ready, 1);  // U[0], written before the launch
     double V[MC];
     load_chunk<T, MC>(U + (long)n0 * M, M, V);
     for (int n = n0; n < N; ++n) {
@@ -286,8 +302,8 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
         constexpr bool kPrefetch = MC <= 4;
         double fv[MC], gold[MC], uold[MC], vt0[MC], vt1[MC];
         if constexpr (kPrefetch) {
-            if (!predict) {
-                if (!ps) load_chunk<T, MC>(Fv + (long)n * M, M, fv);
+            if (!predict && !pipe) {
+                load_chunk<T, MC>(Fv + (long)n * M, M, fv);
                 load_chunk<T, MC>(go, M, gold);
                 load_chunk<T, MC>(un1, M, uold);
             }
@@ -319,11 +335,17 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
             for (int q = 0; q < MC; ++q)
                 g[q] = (kPrefetch ? vt1[q] : ((i0 + q < M) ? vn1[i0 + q] : 0.0)) + g[q];
         }
-        if (ps && !predict) {
+        if (pipe && !predict) {
             // this iteration's fine result of slice n, then U[n+1] free to overwrite
-            if (!pipe_wait(*ps, ps->fdone + n, ps->k, stop, pslot)) return false;
-            if constexpr (kPrefetch) load_chunk<T, MC>(Fv + (long)n * M, M, fv);
-            if (n + 1 < N && !pipe_wait<false>(*ps, ps->taken + n + 1, ps->k, stop, pslot))
+            if (!pipe_wait(ps, ps.fdone + n, ps.k, stop, pslot)) return false;
+            // Fv[n], and (written by the previous iteration's sweep, which has
+            // passed slice n once Fv[n] is written) Gold[n] and U[n+1]
+            if constexpr (kPrefetch) {
+                load_chunk<T, MC>(Fv + (long)n * M, M, fv);
+                load_chunk<T, MC>(go, M, gold);
+                load_chunk<T, MC>(un1, M, uold);
+            }
+            if (n + 1 < N && !pipe_wait<false>(ps, ps.taken + n + 1, ps.k, stop, pslot))
                 return false;
         }
         if (predict) {
@@ -350,7 +372,7 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
                 }
             }
         }
-        if (ps) pipe_signal(ps->ready + n + 1, predict ? 1 : ps->k + 1);
+        if (pipe) pipe_signal(ps.ready + n + 1, predict ? 1 : ps.k + 1);
     }
     return true;
 }

@@ -231,7 +231,7 @@ struct BlockTri {
     // lds is not used (kept for a common interface).
     __device__ void setup(double s2, double r, double h, double e, int M, double* lds) {
         (void)lds;
-        p = threadIdx.x;
+        p = threadIdx.x & 63;  // lane: the block may hold several independent wavefronts
         kap = 1.0 + e / h;
         mu = e / h;
         double a[MC], b[MC], c[MC], alpha1, gammaM;

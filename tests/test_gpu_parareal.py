@@ -193,3 +193,50 @@ def test_solve_stops_at_max_iter_and_repeats():
     ref2 = oracle.parareal(_oracle_params(cfg), M, N, Sf, 1, oracle.COARSE_IE, tol=cfg["tol"])
     assert rc == bsp.BS_OK and iters == ref2["iters"]
     assert normwise(pr.U.cpu().numpy(), ref2["U"]) <= 1e-12
+
+
+@pytest.mark.parametrize("M,N,Sf,MC,is_put,kind,tol,max_iter", [
+    (200, 7, 40, 4, False, bsp.COARSE_IE, 1e-9, None),       # N not a multiple of 4
+    (1000, 9, 64, 16, True, bsp.COARSE_IE, 1e-9, None),      # put, full fine chunk size
+    (100, 1, 30, 2, False, bsp.COARSE_IE, 0.0, None),        # one slice
+    (500, 6, 1500, 8, False, bsp.COARSE_IE, 0.0, None),      # more steps than one forcing table
+    (256, 8, 16, 4, False, bsp.COARSE_IE, 0.0, 3),           # max_iter cut
+    (300, 5, 20, 8, True, bsp.COARSE_PINN_IE, 0.0, None),    # network coarse
+])
+def test_persistent_solve_matches_iterations(M, N, Sf, MC, is_put, kind, tol, max_iter):
+    """The whole-solve launch (fine wavefronts and sweep blocks waiting on each
+    other) gives bitwise the iterates, defects and iteration count of the
+    synchronous one-iteration-at-a-time path with the same block shapes."""
+    cuda()
+    say(f"persistent solve M={M} N={N} Sf={Sf} MC={MC} put={is_put} kind={kind}")
+    cfg = dict(SMALL_CALL, M=M, N=N, fine_steps=Sf, is_put=is_put, n_in=2, depth=2, width=16)
+    p = option_params(cfg)
+    net = None
+    if kind != bsp.COARSE_IE:
+        th = _seeded_net(cfg, seed=3)
+        net = bsp.PinnNet(to_dev(th, torch.float32), 2, cfg["depth"], cfg["width"], bsp.PREC_FP32)
+    try:
+        bsp.bs_tune_reset()
+        bsp.bs_tune_set_shape(0, M, M, 64, MC)
+        bsp.bs_tune_set_shape(1, M, M, 256, 4)
+        pr = bsp.Parareal(p, M, N, Sf, 1, kind, net)
+        for rep in range(2):  # a second solve on the same workspace repeats the first
+            iters, defects, rc = pr.solve(tol, max_iter=max_iter)
+            U = pr.U.cpu().numpy()
+            ref = bsp.Parareal(p, M, N, Sf, 1, kind, net)
+            ref.start()
+            d_ref = []
+            for k in range(1, iters + 1):
+                d_ref.append(ref.iterate(k))
+            assert np.array_equal(U, ref.U.cpu().numpy()), rep
+            assert defects == d_ref
+            if max_iter is not None:
+                assert iters == max_iter and rc == bsp.BS_NOT_CONVERGED
+            elif tol == 0.0:
+                assert iters == N and rc == bsp.BS_OK
+            else:
+                # stopped at the first defect <= tol, or by finite termination at k = N
+                assert rc == bsp.BS_OK and (d_ref[-1] <= tol or iters == N)
+                assert all(d > tol for d in d_ref[:-1])
+    finally:
+        bsp.bs_tune_reset()

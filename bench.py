@@ -198,13 +198,26 @@ def main():
     ev1.record()
     ev1.synchronize()
     f_ms = ev0.elapsed_time(ev1) / reps_f
+    if args.calibrate_copy > 0:
+        # counter runs: the same launch over fewer slices as well, so that a
+        # fit separates the bytes per system from the bytes per launch
+        for ns in (8, 16, 24):
+            bsp.bs_fine_propagate_batch(p, M, tau_f[:ns], p["T"] / N, Sf, u_f[:ns], out_f[:ns])
+        torch.cuda.synchronize()
     sys_per_launch = float(N)
     achieved = sys_per_launch * Sf * M * FLOPS_PER_CELL / (f_ms / 1e3) / 1e12
     # algorithmic HBM bytes of one F launch: each system reads its slice state
     # and writes F of it, M doubles each way
     alg_bytes = 16.0 * M * sys_per_launch
     traffic = measured_traffic(shapes, M)
-    sweep_ms = (prof["sweep_ms"] / prof["sweep_launches"]) if prof["sweep_launches"] else None
+    # the serial sweep on its own: the sweep launch of one synchronous
+    # iteration (iteration 1: all N slices), timed with events
+    pr.start()
+    bsp.bs_profile_enable(True)
+    pr.iterate(1)
+    prof1 = bsp.bs_profile_read()
+    bsp.bs_profile_enable(False)
+    sweep_ms = prof1["sweep_ms"] / max(prof1["sweep_launches"], 1)
     log(f"[bench] F alone: {f_ms * 1e3:.1f} us per launch ({N} slices x {Sf} steps); "
         f"solve launches: {solve_launch_ms * 1e3:.1f} us each")
 
@@ -237,7 +250,7 @@ def main():
         "block_shapes": shapes,
         "solve_launch_ms": solve_launch_ms,
         "solve_launches_per_solve": prof["fine_launches"] / args.steps,
-        "sweep_avg_launch_ms": sweep_ms,
+        "sweep_alone_ms": sweep_ms,
     }
     if train_info is not None:
         out["training"] = train_info
@@ -276,7 +289,7 @@ def main():
         comp["serial_fine_gpu_ms"] = 1e3 * (time.perf_counter() - t0)
         # speedup bound of the paper's eq. (8) with measured per-slice costs (P = N)
         c_f = f_ms
-        c_c = (sweep_ms if sweep_ms is not None else 0.0) / N
+        c_c = sweep_ms / N
         K_it = iters_all[-1]
         comp["speedup_bound_eq8"] = 1.0 / ((1 + K_it / N) * c_c / c_f + K_it / N)
         comp["speedup_vs_serial_fine"] = comp["serial_fine_gpu_ms"] / ms_per_step

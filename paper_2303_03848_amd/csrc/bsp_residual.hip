@@ -74,7 +74,7 @@ struct ResWs {
     size_t bytes;
 };
 
-constexpr int kResPartBlocks = 64;
+constexpr int kResPartBlocks = 256;
 constexpr int kPartRows = 256;  // partial rows in the workspace: max over the split kernels
 
 static size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -276,24 +276,38 @@ static int launch_res_gemm_f32(const float* Wl, const float* bl, const float* in
 __global__ void k_res_head(const float* __restrict__ prm, long off_wo, long off_bo, Points P,
                            long n, long n_pad, int W, const float* __restrict__ clast,
                            float* __restrict__ g, float* __restrict__ lossc) {
-    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_pad) return;
+    // eight lanes per point: lane u sums units j = u, u + 8, ... (a point's
+    // lanes read consecutive units of its row), then an xor tree over the
+    // eight lanes; lane 0 finishes the point
+    const int u = threadIdx.x & 7;
+    const long i = (long)blockIdx.x * (blockDim.x >> 3) + (threadIdx.x >> 3);
+    const long plane = n_pad * W;
+    const float* wo = prm + off_wo;
+    float v = 0.f, vt = 0.f, vx = 0.f, vxx = 0.f;
+    if (i < n) {
+        for (int j = u; j < W; j += 8) {
+            float a, at, ax, axx;
+            streams_from_cache(clast, plane, i * W + j, a, at, ax, axx);
+            v = fmaf(wo[j], a, v);
+            vt = fmaf(wo[j], at, vt);
+            vx = fmaf(wo[j], ax, vx);
+            vxx = fmaf(wo[j], axx, vxx);
+        }
+    }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+        v += __shfl_xor(v, o, 8);
+        vt += __shfl_xor(vt, o, 8);
+        vx += __shfl_xor(vx, o, 8);
+        vxx += __shfl_xor(vxx, o, 8);
+    }
+    if (u != 0 || i >= n_pad) return;
     if (i >= n) {
         g[i] = g[n_pad + i] = g[2 * n_pad + i] = g[3 * n_pad + i] = 0.f;
         lossc[i] = 0.f;
         return;
     }
-    const long plane = n_pad * W;
-    const float* wo = prm + off_wo;
-    float v = prm[off_bo], vt = 0.f, vx = 0.f, vxx = 0.f;
-    for (int j = 0; j < W; ++j) {
-        float a, at, ax, axx;
-        streams_from_cache(clast, plane, i * W + j, a, at, ax, axx);
-        v = fmaf(wo[j], a, v);
-        vt = fmaf(wo[j], at, vt);
-        vx = fmaf(wo[j], ax, vx);
-        vxx = fmaf(wo[j], axx, vxx);
-    }
+    v += prm[off_bo];
     const float* x = point_row(P, i);
     const float sig = P.n_in == 4 ? x[2] : P.sigma;
     const float rr = P.n_in == 4 ? x[3] : P.r;
@@ -490,21 +504,34 @@ __global__ void k_res_grad_first(const float* __restrict__ zbar, Points P, long 
     chunk_range(n, lo, hi);
     const long plane = n_pad * W;
     const int nw = W * P.n_in, count = nw + W;
+    // four running sums over the points i = lo + 4m + u (the loads of four
+    // points are in flight together), added in a fixed order
     for (int x = threadIdx.x; x < count; x += blockDim.x) {
-        float acc = 0.f;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
         if (x < nw) {
             const int j = x / P.n_in, c = x - j * P.n_in;
-            for (long i = lo; i < hi; ++i) {
-                const long idx = i * W + j;
-                acc = fmaf(zbar[idx], point_row(P, i)[c], acc);
-                if (c == 0) acc += zbar[plane + idx];
-                if (c == 1) acc += zbar[2 * plane + idx];
+            const long off = (c == 0) ? plane : (c == 1) ? 2 * plane : -1;
+            for (long i0 = lo; i0 < hi; i0 += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const long i = i0 + u;
+                    if (i < hi) {
+                        const long idx = i * W + j;
+                        float t = zbar[idx] * point_row(P, i)[c];
+                        if (off >= 0) t += zbar[off + idx];
+                        acc[u] += t;
+                    }
+                }
             }
         } else {
             const int j = x - nw;
-            for (long i = lo; i < hi; ++i) acc += zbar[i * W + j];
+            for (long i0 = lo; i0 < hi; i0 += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (i0 + u < hi) acc[u] += zbar[(i0 + u) * W + j];
+            }
         }
-        part[(long)blockIdx.x * count + x] = acc;
+        part[(long)blockIdx.x * count + x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     }
 }
 
@@ -516,20 +543,31 @@ __global__ void k_res_grad_out(const float* __restrict__ g, const float* __restr
     const long plane = n_pad * W;
     const int count = W + 1;
     for (int x = threadIdx.x; x < count; x += blockDim.x) {
-        float acc = 0.f;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
         if (x < W) {
-            for (long i = lo; i < hi; ++i) {
-                float a, at, ax, axx;
-                streams_from_cache(clast, plane, i * W + x, a, at, ax, axx);
-                acc = fmaf(g[i], a, acc);
-                acc = fmaf(g[n_pad + i], at, acc);
-                acc = fmaf(g[2 * n_pad + i], ax, acc);
-                acc = fmaf(g[3 * n_pad + i], axx, acc);
+            for (long i0 = lo; i0 < hi; i0 += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const long i = i0 + u;
+                    if (i < hi) {
+                        float a, at, ax, axx;
+                        streams_from_cache(clast, plane, i * W + x, a, at, ax, axx);
+                        float t = g[i] * a;
+                        t = fmaf(g[n_pad + i], at, t);
+                        t = fmaf(g[2 * n_pad + i], ax, t);
+                        t = fmaf(g[3 * n_pad + i], axx, t);
+                        acc[u] += t;
+                    }
+                }
             }
         } else {
-            for (long i = lo; i < hi; ++i) acc += g[i];
+            for (long i0 = lo; i0 < hi; i0 += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (i0 + u < hi) acc[u] += g[i0 + u];
+            }
         }
-        part[(long)blockIdx.x * count + x] = acc;
+        part[(long)blockIdx.x * count + x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     }
 }
 
@@ -595,7 +633,7 @@ extern "C" int pinn_residual_fwd_bwd(const pinn_net* net, const bs_params* prm, 
                 return rc;
         }
     }
-    hipLaunchKernelGGL(k_res_head, grid_for(np, 256), dim3(256), 0, st, P0, L.off_wo, L.off_bo,
+    hipLaunchKernelGGL(k_res_head, grid_for(np, 32), dim3(256), 0, st, P0, L.off_wo, L.off_bo,
                        P, n, np, W, cache(d), w.g, w.lossc);
     BSP_LAUNCHED();
     hipLaunchKernelGGL(k_res_loss, dim3(1), dim3(256), 0, st, w.lossc, n_f, n_e, n_b, loss3);

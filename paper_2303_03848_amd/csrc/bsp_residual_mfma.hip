@@ -179,18 +179,38 @@ __global__ __launch_bounds__(256) void k_res_bwd_bf16(const float* __restrict__ 
     if (tid < W) out[W * W + tid] = gb;
 }
 
-// grad[x] = sum over blocks of part[b][x], x < count (fixed block order).
-__global__ void k_res_reduce(const float* __restrict__ part, int nblk, int count,
-                             float* __restrict__ grad) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= count) return;
-    float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += part[(long)b * count + x];
-    grad[x] = s;
+// grad[x] = sum over blocks b of part[b][x], x < count.  A block takes 32
+// consecutive x; its 8 row groups sum the partials b = g, g + 8, ... (four
+// running sums each, so the loads overlap), then the groups are added in
+// order: a fixed summation order for every x, independent of timing.
+__global__ __launch_bounds__(256) void k_res_reduce(const float* __restrict__ part, int nblk,
+                                                    int count, float* __restrict__ grad) {
+    __shared__ float acc[8][33];
+    const int tx = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int x = blockIdx.x * 32 + tx;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    if (x < count) {
+        int b = g;
+        for (; b + 24 < nblk; b += 32) {
+            s0 += part[(long)b * count + x];
+            s1 += part[(long)(b + 8) * count + x];
+            s2 += part[(long)(b + 16) * count + x];
+            s3 += part[(long)(b + 24) * count + x];
+        }
+        for (; b < nblk; b += 8) s0 += part[(long)b * count + x];
+    }
+    acc[g][tx] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (g == 0 && x < count) {
+        float s = acc[0][tx];
+#pragma unroll
+        for (int r = 1; r < 8; ++r) s += acc[r][tx];
+        grad[x] = s;
+    }
 }
 
 int launch_res_reduce(const float* part, int nblk, int count, float* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_res_reduce, dim3((count + 255) / 256), dim3(256), 0, st, part, nblk, count,
+    hipLaunchKernelGGL(k_res_reduce, dim3((count + 31) / 32), dim3(256), 0, st, part, nblk, count,
                        out);
     BSP_LAUNCHED();
     return BS_OK;
@@ -234,10 +254,7 @@ int launch_res_gemm_bf16(int which, const float* Wl, const float* bl, const floa
     const int count = W * W + W;
     // dW and db are contiguous in the parameter packing (W_l then b_l)
     (void)gb;
-    hipLaunchKernelGGL(k_res_reduce, dim3((count + 255) / 256), dim3(256), 0, st, part, nblk, count,
-                       gW);
-    BSP_LAUNCHED();
-    return BS_OK;
+    return launch_res_reduce(part, nblk, count, gW, st);
 }
 
 }  // namespace bsp

@@ -19,8 +19,8 @@ import torch
 
 import paper_2303_03848_amd as bsp
 
-BUILT_SHAPES = [(64, 2), (64, 4), (64, 8), (64, 16), (128, 4), (128, 8), (256, 4), (256, 8),
-                (512, 8)]
+BUILT_SHAPES = [(64, 2), (64, 4), (64, 8), (64, 16), (128, 4), (128, 8), (128, 16), (256, 4),
+                (256, 8), (256, 16), (512, 8)]
 FINE, SWEEP = 0, 1
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(T) void k_batch_fine(const BatchOpt* __restrict__ o
                                                   const int* __restrict__ kglob,
                                                   const double* __restrict__ U,
                                                   double* __restrict__ Fv) {
-    __shared__ double smem[smem_doubles<T>()];
+    __shared__ double smem[smem_doubles<T, MC>()];
     double* lds = smem;
     double* ftab = smem + 4 * T;
     const FItem it = items[blockIdx.x];

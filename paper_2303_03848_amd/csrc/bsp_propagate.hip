@@ -99,7 +99,7 @@ template <int T, int MC, bool PIPE>
 __device__ __forceinline__ void theta_body(const ThetaArgs& a, double* smem, int* pslot) {
     double* lds = smem;
     double* ftab = smem + 4 * T;
-    double* stage = PIPE ? smem + smem_doubles<T>() : smem;
+    double* stage = PIPE ? smem + smem_doubles<T, MC>() : smem;
     if (stopped(a.stop)) return;
     const int sys = blockIdx.x;
     const int n = sys + a.sys_offset;
@@ -111,7 +111,7 @@ __device__ __forceinline__ void theta_body(const ThetaArgs& a, double* smem, int
     if constexpr (PIPE) {
         S.setup(a.o.s2, a.o.r, a.theta * a.dt, (1.0 - a.theta) * a.dt, a.M, lds);
         const bool ex = a.theta != 1.0;
-        if (!a.homog && (ex ? piped_path<true>(S) : piped_path<false>(S))) {
+        if (!a.homog && (ex ? piped_path<true>(S, a.steps) : piped_path<false>(S, a.steps))) {
             fill_piped_table<T>(a.o, tau0, a.dt, a.steps, a.theta, 0,
                                 min(kForceChunk - 1, a.steps), ftab);
             prefilled = true;
@@ -138,13 +138,16 @@ __device__ __forceinline__ void theta_body(const ThetaArgs& a, double* smem, int
 
 template <int T, int MC>
 __global__ __launch_bounds__(T) void k_theta_batch(ThetaArgs a) {
-    __shared__ double smem[smem_doubles<T>()];
+    __shared__ double smem[smem_doubles<T, MC>()];
     theta_body<T, MC, false>(a, smem, nullptr);
 }
 
+// One block per compute unit is the intended occupancy of the large-chunk
+// shapes: the compiler may use the whole register file (no scratch spills).
 template <int T, int MC>
-__global__ __launch_bounds__(T) void k_theta_pipe(ThetaArgs a) {
-    __shared__ double smem[smem_doubles<T>() + T * MC];
+__global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_theta_pipe(
+    ThetaArgs a) {
+    __shared__ double smem[smem_doubles<T, MC>() + T * MC];
     __shared__ int pslot;
     theta_body<T, MC, true>(a, smem, &pslot);
 }
@@ -201,7 +204,8 @@ __device__ __forceinline__ void persist_fine(const PersistArgs& a, double* smem)
     const double tau0 = (double)n * a.dT;
     BlockTri<64, MCF> S;
     S.setup(a.o.s2, a.o.r, 0.5 * dt, 0.5 * dt, a.M, nullptr);
-    const bool pre = a.fine_steps <= kForceChunk - 1;  // one table serves every iteration
+    // one table serves every iteration
+    const bool pre = a.fine_steps <= kForceChunk - 1 && piped_path<true>(S, a.fine_steps);
     if (pre) fill_piped_table<64, true>(a.o, tau0, dt, a.fine_steps, 0.5, 0, a.fine_steps, ftab);
     const int klast = min(a.kmax, n + 1);  // iteration k propagates slices n >= k-1
     for (int k = 1; k <= klast; ++k) {
@@ -374,16 +378,17 @@ static int launch_large_setup(const OptionDev& o, int M, double h, double e, dou
 // ------------------------------------------------------------ dispatch
 
 // Default block shapes.  The F kernel favours one wavefront per system (no
-// barriers) while its registers allow; the serial sweep is one block for the
-// whole grid and favours more threads per system.
+// barriers) while its registers allow, then as few wavefronts of 16 nodes
+// per lane as cover the grid; the serial sweep is one block for the whole
+// grid and favours more threads per system.
 static TriShape default_shape(int kernel, int M) {
     if (kernel == 0) {
         if (M <= 128) return {64, 2};
         if (M <= 256) return {64, 4};
         if (M <= 512) return {64, 8};
         if (M <= 1024) return {64, 16};
-        if (M <= 2048) return {256, 8};
-        if (M <= 4096) return {512, 8};
+        if (M <= 2048) return {128, 16};
+        if (M <= 4096) return {256, 16};
         if (M <= 8192) return {512, 16};
         if (M <= 16384) return {512, 32};
     } else {

@@ -25,7 +25,8 @@ using Solver = typename SolverSel<T, MC>::type;
 
 // Block shapes (threads, nodes per thread) the tridiagonal kernels are built for.
 #define BSP_TRI_SHAPES(X) \
-    X(64, 2) X(64, 4) X(64, 8) X(64, 16) X(128, 4) X(128, 8) X(256, 4) X(256, 8) X(512, 8)
+    X(64, 2) X(64, 4) X(64, 8) X(64, 16) X(128, 4) X(128, 8) X(128, 16) X(256, 4) X(256, 8) \
+        X(256, 16) X(512, 8)
 
 template <int T, int MC>
 __device__ __forceinline__ void load_chunk(const double* __restrict__ src, int M, double (&V)[MC]) {
@@ -48,10 +49,11 @@ constexpr int kForceChunk = 1024;
 // Shared memory of a tridiagonal kernel: the solver's 4T doubles followed by
 // the two forcing tables.  Loads and stores of a whole system are staged
 // through it so that consecutive lanes touch consecutive doubles (whole
-// 128-byte lines per wavefront access) instead of MC-strided chunks.
-template <int T>
+// 128-byte lines per wavefront access) instead of MC-strided chunks; it is
+// at least T * MC doubles for that.
+template <int T, int MC>
 constexpr int smem_doubles() {
-    return 4 * T + 2 * kForceChunk;
+    return 4 * T + 2 * kForceChunk > T * MC ? 4 * T + 2 * kForceChunk : T * MC;
 }
 
 // Barrier of the threads working on one system: the block, or (WAVE) one
@@ -70,7 +72,7 @@ __device__ __forceinline__ void system_sync() {
 template <int T, int MC, bool WAVE = false>
 __device__ __forceinline__ void load_system(const double* __restrict__ src, int M, double (&V)[MC],
                                             double* smem) {
-    static_assert(T * MC <= smem_doubles<T>(), "staging area too small");
+    static_assert(T * MC <= smem_doubles<T, MC>(), "staging area too small");
     static_assert(!WAVE || T == 64, "one wavefront");
     const int p = WAVE ? (threadIdx.x & 63) : threadIdx.x;
 #pragma unroll
@@ -111,6 +113,13 @@ template <class S>
 struct IsWaveSolver : std::false_type {};
 template <int MC>
 struct IsWaveSolver<BlockTri<64, MC>> : std::true_type {};
+// Solvers with the pipelined step interface (pipe_begin / pipe_step / pipe_end).
+template <class S>
+struct HasPipe : std::false_type {};
+template <int MC>
+struct HasPipe<BlockTri<64, MC>> : std::true_type {};
+template <int W, int MC>
+struct HasPipe<BlockTriH<W, MC>> : std::true_type {};
 
 // One-wavefront blocks: the pipelined steps of BlockTri (pipe_begin /
 // pipe_step / pipe_end), with the reduction stage count as a compile-time
@@ -148,16 +157,16 @@ __device__ __forceinline__ void fill_piped_table(const OptionDev& o, double tau0
 }
 
 // prefilled: the first table (m0 = 0) is already in ftab.
-template <int MC, bool EX, int NST, bool HI, bool POLL, bool WAVE>
-__device__ __forceinline__ bool piped_run(const BlockTri<64, MC>& S, const OptionDev& o,
-                                          double (&V)[MC], double tau0, double dt, int steps,
-                                          double theta, bool homog, double* ftab,
+template <class S_t, int MC, bool EX, int NST, bool HI, bool POLL, bool WAVE>
+__device__ __forceinline__ bool piped_run(const S_t& S, const OptionDev& o, double (&V)[MC],
+                                          double tau0, double dt, int steps, double theta,
+                                          bool homog, double* lds, double* ftab,
                                           const int* stop, bool prefilled) {
-    constexpr int T = 64, CH = kForceChunk - 1;
+    constexpr int T = S_t::kThreads, CH = kForceChunk - 1;
     auto fill = [&](int m0, int n) {  // entries i = 0..n: step m0 + 1 + i
         fill_piped_table<T, WAVE>(o, tau0, dt, steps, theta, m0, n, ftab);
     };
-    typename BlockTri<64, MC>::Pipe P;
+    typename S_t::Pipe P;
     int n = min(CH, steps);
     if (!homog && !prefilled) fill(0, n);
     S.pipe_begin(V, homog ? 0.0 : ftab[0], homog ? 0.0 : ftab[kForceChunk], P);
@@ -168,7 +177,7 @@ __device__ __forceinline__ bool piped_run(const BlockTri<64, MC>& S, const Optio
             for (int i = i0; i < i1; ++i) {
                 const double lo_n = homog ? 0.0 : ftab[i + 1];
                 const double hi_n = homog ? 0.0 : ftab[kForceChunk + i + 1];
-                S.template pipe_step<EX, NST, HI>(P, lo, hi, lo_n, hi_n);
+                S.template pipe_step<EX, NST, HI>(P, lo, hi, lo_n, hi_n, lds);
                 lo = lo_n;
                 hi = hi_n;
             }
@@ -176,7 +185,10 @@ __device__ __forceinline__ bool piped_run(const BlockTri<64, MC>& S, const Optio
         if constexpr (POLL) {
             for (int i0 = 0; i0 < n; i0 += kPollSteps) {
                 if (sv) return false;
-                sv = pipe_load(stop);
+                if constexpr (T == 64)
+                    sv = pipe_load(stop);  // one wavefront: the loaded value is uniform
+                else
+                    sv = __syncthreads_or(pipe_load(stop) != 0);  // the same decision in every wavefront
                 run(i0, min(n, i0 + kPollSteps));
             }
         } else {
@@ -192,10 +204,14 @@ __device__ __forceinline__ bool piped_run(const BlockTri<64, MC>& S, const Optio
     return true;
 }
 
-// True when theta_steps takes the pipelined one-wavefront path.
+// The pipelined steps pay off over a run of steps; a single step (the
+// coarse propagator) takes the plain step.
+constexpr int kPipeMinSteps = 2;
+
+// True when theta_steps takes the pipelined path.
 template <bool EX, class Solver>
-__device__ __forceinline__ bool piped_path(const Solver& S) {
-    if constexpr (IsWaveSolver<Solver>::value) return !EX || S.mu == 1.0;
+__device__ __forceinline__ bool piped_path(const Solver& S, int steps) {
+    if constexpr (HasPipe<Solver>::value) return (!EX || S.mu == 1.0) && steps >= kPipeMinSteps;
     return false;
 }
 
@@ -210,17 +226,18 @@ __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
                                             double theta, bool homog, double* lds, double* ftab,
                                             const int* stop = nullptr, bool prefilled = false) {
     static_assert(!WAVE || IsWaveSolver<Solver>::value, "wavefront-level runs need BlockTri");
-    // The pipelined one-wavefront steps cover mu = 1 (Crank-Nicolson) and
-    // mu = 0 (implicit Euler); any other theta takes the plain step loop.
-    if constexpr (IsWaveSolver<Solver>::value) if (!EX || S.mu == 1.0) {
+    // The pipelined steps cover mu = 1 (Crank-Nicolson) and mu = 0 (implicit
+    // Euler) over runs of kPipeMinSteps or more; the rest takes the plain
+    // step loop.
+    if constexpr (HasPipe<Solver>::value) if (piped_path<EX>(S, steps)) {
         // HI: row M-1 lies inside a chunk (grid not a multiple of MC) and
         // carries forcing; homogeneous runs have none.
         const bool hi = !homog && S.fc.r_hi != MC - 1;
-#define BSP_RUN(NST_, HI_) \
-    return piped_run<MC, EX, NST_, HI_, POLL, WAVE>(S, o, V, tau0, dt, steps, theta, homog, ftab, \
-                                                    stop, prefilled)
+#define BSP_RUN(NST_, HI_)                                                                  \
+    return piped_run<Solver, MC, EX, NST_, HI_, POLL, WAVE>(S, o, V, tau0, dt, steps, theta, \
+                                                            homog, lds, ftab, stop, prefilled)
         if (hi) {
-            switch (S.nst) {
+            switch (S.stages()) {
                 case 0: BSP_RUN(0, true);
                 case 1: BSP_RUN(1, true);
                 case 2: BSP_RUN(2, true);
@@ -228,7 +245,7 @@ __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
                 default: BSP_RUN(-1, true);
             }
         } else {
-            switch (S.nst) {
+            switch (S.stages()) {
                 case 0: BSP_RUN(0, false);
                 case 1: BSP_RUN(1, false);
                 case 2: BSP_RUN(2, false);
@@ -242,8 +259,8 @@ __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
     for (int m0 = 0; m0 < steps; m0 += kForceChunk) {
         const int nch = min(kForceChunk, steps - m0);
         if (!homog) {
-            __syncthreads();  // the previous chunk's table has been consumed
-            for (int i = threadIdx.x; i < nch; i += T) {
+            system_sync<WAVE>();  // the previous chunk's table has been consumed
+            for (int i = WAVE ? (threadIdx.x & 63) : threadIdx.x; i < nch; i += T) {
                 const int mm = m0 + i;
                 double lo0, hi0, lo1, hi1;
                 dirichlet(o, exp(-o.r * (tau0 + (double)mm * dt)), lo0, hi0);
@@ -251,7 +268,7 @@ __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
                 ftab[i] = fma(e, lo0, h * lo1);
                 ftab[kForceChunk + i] = fma(e, hi0, h * hi1);
             }
-            __syncthreads();
+            system_sync<WAVE>();
         }
         double flo_n = homog ? 0.0 : ftab[0];
         double fhi_n = homog ? 0.0 : ftab[kForceChunk];

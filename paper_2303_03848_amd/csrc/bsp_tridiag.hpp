@@ -202,6 +202,7 @@ struct BlockTri {
     static_assert(MC >= 2, "at least one interior row per chunk");
     static constexpr int LOGT = 6;
     static constexpr int NI = MC - 1;
+    static constexpr int kThreads = 64;
 
     ChunkLU<MC> lu;
     Forcing fc;
@@ -213,6 +214,8 @@ struct BlockTri {
     double al[NI], be[NI], lh[NI], ch[NI];
     double aqk, cqk, blok, bhik;
     int p, nst;
+
+    __device__ __forceinline__ int stages() const { return nst; }
 
     __device__ __forceinline__ double up(double x, int s) const {
         if (s == 1) return dpp_from_prev(x);
@@ -229,7 +232,8 @@ struct BlockTri {
 
     // h = theta*dt > 0 (implicit weight), e = (1-theta)*dt (explicit weight).
     // lds is not used (kept for a common interface).
-    __device__ void setup(double s2, double r, double h, double e, int M, double* lds) {
+    __device__ __forceinline__ void setup(double s2, double r, double h, double e, int M,
+                                          double* lds) {
         (void)lds;
         p = threadIdx.x & 63;  // lane: the block may hold several independent wavefronts
         kap = 1.0 + e / h;
@@ -353,7 +357,7 @@ struct BlockTri {
     // lane, so the step body stays free of branches.
     template <bool EX, int NST, bool HI>
     __device__ __forceinline__ void pipe_step(Pipe& P, double flo, double fhi, double flo_n,
-                                              double fhi_n) const {
+                                              double fhi_n, double* /*lds: unused*/ = nullptr) const {
         double y[NI], xi[NI];
         // y just ahead of the backward chain that consumes it, so that each
         // link of the chain has independent work beside it

@@ -43,7 +43,8 @@ struct BlockTriG {
 
     // h = theta*dt > 0, e = (1-theta)*dt; tables built by k_large_setup for
     // the same (s2, r, h, e, M).
-    __device__ void load(const double* tab_, const double* ptab_, double s2, double r, double h,
+    __device__ __forceinline__ void load(const double* tab_, const double* ptab_, double s2,
+                                         double r, double h,
                          double e, int M) {
         tab = tab_;
         ptab = ptab_;

@@ -201,6 +201,7 @@ def test_solve_stops_at_max_iter_and_repeats():
     (100, 1, 30, 2, False, bsp.COARSE_IE, 0.0, None),        # one slice
     (500, 6, 1500, 8, False, bsp.COARSE_IE, 0.0, None),      # more steps than one forcing table
     (256, 8, 16, 4, False, bsp.COARSE_IE, 0.0, 3),           # max_iter cut
+    (600, 5, 1, 16, False, bsp.COARSE_IE, 0.0, None),        # one fine step: the plain step
     (300, 5, 20, 8, True, bsp.COARSE_PINN_IE, 0.0, None),    # network coarse
 ])
 def test_persistent_solve_matches_iterations(M, N, Sf, MC, is_put, kind, tol, max_iter):

@@ -1,6 +1,7 @@
 // Network forward pass on the matrix cores: bfloat16 operands, float32
 // accumulation, tanh in float32 (the BS_PREC_BF16 path of pinn_forward and
-// of the network coarse propagator).
+// of the network coarse propagator).  tanh is evaluated through the
+// exponential (tanh_bf16_act): the activations are rounded to bfloat16.
 //
 // One block of 4 wavefronts takes P = 128 points through every layer without
 // leaving the CU: activations ping-pong between two LDS tiles [P][W] (bf16).
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(const float* __restrict__ prm,
         const int i = e / W, j = e - i * W;
         float z = prm[W * n_in + j];
         for (int c = 0; c < n_in; ++c) z = fmaf(prm[j * n_in + c], xin[i][c], z);
-        act[0][i * LDA + j] = (__bf16)tanh_f32(z);
+        act[0][i * LDA + j] = (__bf16)tanh_bf16_act(z);
     }
     long off = (long)W * n_in + W;
     int cur = 0;
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(const float* __restrict__ prm,
 #pragma unroll
                 for (int v = 0; v < 16; ++v)
                     act[cur ^ 1][(mt * 32 + mfma_row(v, lane)) * LDA + j] =
-                        (__bf16)tanh_f32(acc[mt][v] + bj);
+                        (__bf16)tanh_bf16_act(acc[mt][v] + bj);
         }
         cur ^= 1;
         off += (long)W * W + W;

@@ -100,8 +100,9 @@ def main():
                          "counter profile of this command has a copy kernel of known size")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the slices would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (the "
+              "slices would shard across GPUs in contiguous blocks, the serial sweep passing "
+              "the boundary state from one GPU to the next)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -204,14 +204,19 @@ __device__ __forceinline__ bool piped_run(const S_t& S, const OptionDev& o, doub
     return true;
 }
 
-// The pipelined steps pay off over a run of steps; a single step (the
-// coarse propagator) takes the plain step.
+// On several wavefronts the pipelined steps pay off over a run of steps; a
+// single step (the coarse propagator) takes the plain step there.
 constexpr int kPipeMinSteps = 2;
 
 // True when theta_steps takes the pipelined path.
 template <bool EX, class Solver>
 __device__ __forceinline__ bool piped_path(const Solver& S, int steps) {
-    if constexpr (HasPipe<Solver>::value) return (!EX || S.mu == 1.0) && steps >= kPipeMinSteps;
+    if constexpr (IsWaveSolver<Solver>::value) {
+        (void)steps;
+        return !EX || S.mu == 1.0;
+    } else if constexpr (HasPipe<Solver>::value) {
+        return (!EX || S.mu == 1.0) && steps >= kPipeMinSteps;
+    }
     return false;
 }
 
@@ -227,8 +232,8 @@ __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
                                             const int* stop = nullptr, bool prefilled = false) {
     static_assert(!WAVE || IsWaveSolver<Solver>::value, "wavefront-level runs need BlockTri");
     // The pipelined steps cover mu = 1 (Crank-Nicolson) and mu = 0 (implicit
-    // Euler) over runs of kPipeMinSteps or more; the rest takes the plain
-    // step loop.
+    // Euler) (on several wavefronts: runs of kPipeMinSteps or more); the rest
+    // takes the plain step loop.
     if constexpr (HasPipe<Solver>::value) if (piped_path<EX>(S, steps)) {
         // HI: row M-1 lies inside a chunk (grid not a multiple of MC) and
         // carries forcing; homogeneous runs have none.

@@ -205,7 +205,7 @@ __device__ __forceinline__ void persist_fine(const PersistArgs& a, double* smem)
     BlockTri<64, MCF> S;
     S.setup(a.o.s2, a.o.r, 0.5 * dt, 0.5 * dt, a.M, nullptr);
     // one table serves every iteration
-    const bool pre = a.fine_steps <= kForceChunk - 1 && piped_path<true>(S, a.fine_steps);
+    const bool pre = a.fine_steps <= kForceChunk - 1 && piped_path<true, true>(S, a.fine_steps);
     if (pre) fill_piped_table<64, true>(a.o, tau0, dt, a.fine_steps, 0.5, 0, a.fine_steps, ftab);
     const int klast = min(a.kmax, n + 1);  // iteration k propagates slices n >= k-1
     for (int k = 1; k <= klast; ++k) {

@@ -208,10 +208,13 @@ __device__ __forceinline__ bool piped_run(const S_t& S, const OptionDev& o, doub
 // single step (the coarse propagator) takes the plain step there.
 constexpr int kPipeMinSteps = 2;
 
-// True when theta_steps takes the pipelined path.
-template <bool EX, class Solver>
+// True when theta_steps takes the pipelined path.  A block-level run on one
+// wavefront takes it for any step count (the form that generates the best
+// code for the standalone fine kernel); a wavefront working alone (WAVE)
+// and several wavefronts need kPipeMinSteps.
+template <bool EX, bool WAVE = false, class Solver>
 __device__ __forceinline__ bool piped_path(const Solver& S, int steps) {
-    if constexpr (IsWaveSolver<Solver>::value) {
+    if constexpr (IsWaveSolver<Solver>::value && !WAVE) {
         (void)steps;
         return !EX || S.mu == 1.0;
     } else if constexpr (HasPipe<Solver>::value) {
@@ -234,7 +237,7 @@ __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
     // The pipelined steps cover mu = 1 (Crank-Nicolson) and mu = 0 (implicit
     // Euler) (on several wavefronts: runs of kPipeMinSteps or more); the rest
     // takes the plain step loop.
-    if constexpr (HasPipe<Solver>::value) if (piped_path<EX>(S, steps)) {
+    if constexpr (HasPipe<Solver>::value) if (piped_path<EX, WAVE>(S, steps)) {
         // HI: row M-1 lies inside a chunk (grid not a multiple of MC) and
         // carries forcing; homogeneous runs have none.
         const bool hi = !homog && S.fc.r_hi != MC - 1;

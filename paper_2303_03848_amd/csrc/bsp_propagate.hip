@@ -313,10 +313,11 @@ __global__ __launch_bounds__(T) void k_large_theta(ThetaArgs a, const double* __
                                                    const double* __restrict__ ptab) {
     __shared__ double lds[4 * T];
     __shared__ double ftab[2 * kForceChunk];
+    __shared__ double kst[2 * BlockTriG<T, MC>::LOGT * T];
     if (stopped(a.stop)) return;
     const int sys = blockIdx.x;
     BlockTriG<T, MC> S;
-    S.load(tab, ptab, a.o.s2, a.o.r, a.theta * a.dt, (1.0 - a.theta) * a.dt, a.M);
+    S.load(tab, ptab, a.o.s2, a.o.r, a.theta * a.dt, (1.0 - a.theta) * a.dt, a.M, kst);
     const double tau0 =
         a.tau0 ? a.tau0[sys] : a.tau_start + (double)(sys + a.sys_offset) * a.tau_stride;
     double V[MC];
@@ -333,9 +334,10 @@ __global__ __launch_bounds__(T) void k_large_sweep(SweepArgs a, const double* __
                                                    const double* __restrict__ ptab) {
     __shared__ double lds[4 * T];
     __shared__ double ftab[2 * kForceChunk];
+    __shared__ double kst[2 * BlockTriG<T, MC>::LOGT * T];
     if (stopped(a.stop)) return;
     BlockTriG<T, MC> S;
-    S.load(tab, ptab, a.o.s2, a.o.r, a.dT / (double)a.coarse_steps, 0.0, a.M);
+    S.load(tab, ptab, a.o.s2, a.o.r, a.dT / (double)a.coarse_steps, 0.0, a.M, kst);
     double dmax = 0.0;
     int bad = 0;
     sweep_slices<T, MC>(S, a.o, a.M, a.N, a.n0, a.coarse_steps, a.kind, a.predict != 0, a.dT, a.U,

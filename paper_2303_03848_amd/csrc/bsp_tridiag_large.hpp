@@ -33,6 +33,7 @@ struct BlockTriG {
 
     const double* tab;
     const double* ptab;
+    const double* kst;  // LDS copy of this block's stage multipliers [2][LOGT][T]
     Forcing fc;
     double aq, cq, invB, kap, mu;
     int p, nst;
@@ -43,12 +44,19 @@ struct BlockTriG {
 
     // h = theta*dt > 0, e = (1-theta)*dt; tables built by k_large_setup for
     // the same (s2, r, h, e, M).
+    // kst_lds: 2 * LOGT * T doubles of LDS for the stage multipliers (each
+    // thread reads only its own, so no barrier is needed after the copy).
     __device__ __forceinline__ void load(const double* tab_, const double* ptab_, double s2,
-                                         double r, double h,
-                         double e, int M) {
+                                         double r, double h, double e, int M, double* kst_lds) {
         tab = tab_;
         ptab = ptab_;
         p = threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < LOGT; ++k) {
+            kst_lds[k * T + p] = ptab[(8 + k) * T + p];
+            kst_lds[(LOGT + k) * T + p] = ptab[(24 + k) * T + p];
+        }
+        kst = kst_lds;
         kap = 1.0 + e / h;
         mu = e / h;
         aq = ptab[0 * T + p];
@@ -64,15 +72,15 @@ struct BlockTriG {
     }
 
     // One step (see BlockTri::step).  lds: 4*T doubles; the stage multipliers
-    // are re-read from ptab.
+    // are read from their LDS copy (a global read after each stage's barrier
+    // would put its latency on the critical path).
     template <bool EX>
     __device__ __forceinline__ void step(double (&V)[MC], double flo, double fhi,
                                          double* lds) const {
         // Opaque per step: the compiler must not hoist the table loads out of
         // the step loop (that is the register footprint this solver avoids).
         const double* tb = tab;
-        const double* pt = ptab;
-        asm volatile("" : "+v"(tb), "+v"(pt));
+        asm volatile("" : "+v"(tb));
         double d[MC];
         fc.rhs(V, flo, fhi, d);
 #pragma unroll
@@ -104,7 +112,7 @@ struct BlockTriG {
             __syncthreads();
             const double Dm = (p - s >= 0) ? buf[p - s] : 0.0;
             const double Dp = (p + s < T) ? buf[p + s] : 0.0;
-            D = fma(-pt[(8 + k) * T + p], Dm, fma(-pt[(24 + k) * T + p], Dp, D));
+            D = fma(-kst[k * T + p], Dm, fma(-kst[(LOGT + k) * T + p], Dp, D));
         }
         const double z = D * invB;
         zbuf[p] = z;

@@ -249,3 +249,36 @@ def test_persistent_solve_matches_iterations(M, N, Sf, MC, is_put, kind, tol, ma
                 assert all(d > tol for d in d_ref[:-1])
     finally:
         bsp.bs_tune_reset()
+
+
+@pytest.mark.parametrize("M,N,Sf,is_put,tol,max_iter", [
+    (2048, 6, 20, False, 1e-9, None),   # two wavefronts per fine system
+    (3000, 5, 16, True, 0.0, None),     # four wavefronts, grid not a multiple of the chunk
+    (2048, 8, 12, False, 0.0, 3),       # max_iter cut: the queued fine launch stops early
+])
+def test_overlapped_solve_multiwave(M, N, Sf, is_put, tol, max_iter):
+    """Grids of 1025-4096 nodes: F of iteration k+1 on side streams alongside
+    the sweep of iteration k (multi-wavefront pipelined solver, stop flag
+    polled block-wide).  Same iterates as the one-iteration path, and the
+    oracle's to the iterate tolerance."""
+    cuda()
+    say(f"overlapped multi-wavefront solve M={M} N={N} Sf={Sf} put={is_put}")
+    cfg = dict(SMALL_CALL, M=M, N=N, fine_steps=Sf, is_put=is_put)
+    p = option_params(cfg)
+    pr = bsp.Parareal(p, M, N, Sf, 1, bsp.COARSE_IE)
+    iters, defects, rc = pr.solve(tol, max_iter=max_iter)
+    U = pr.U.cpu().numpy()
+    ref = bsp.Parareal(p, M, N, Sf, 1, bsp.COARSE_IE)
+    ref.start()
+    d_ref = [ref.iterate(k) for k in range(1, iters + 1)]
+    assert np.array_equal(U, ref.U.cpu().numpy())
+    assert defects == d_ref
+    ora = oracle.parareal(_oracle_params(cfg), M, N, Sf, 1, oracle.COARSE_IE, tol=tol,
+                          max_iter=max_iter)
+    assert iters == ora["iters"]
+    # normwise bound from the conditioning of the steps (as for the propagators)
+    dt = p["T"] / (N * Sf)
+    bound = max(1e-11, 16 * np.finfo(float).eps * N * Sf * (1 + dt * (p["sigma"] * M) ** 2))
+    assert normwise(U, ora["U"]) <= bound
+    if max_iter is not None:
+        assert rc == bsp.BS_NOT_CONVERGED

@@ -181,13 +181,18 @@ int parareal_iterate(const bs_params* prm, const bs_grid* grid, const bs_slices*
  * BS_COARSE_IE.  Returns BS_OK, BS_NOT_CONVERGED (max_iter hit first) or an
  * error.
  * For grids of up to 4096 nodes the iterations overlap (same iterates as
- * parareal_iterate called for k = 1, 2, ...): F of iteration k runs on one
- * of two library-owned side streams of the calling thread and starts each
- * slice once the sweep of iteration k-1 has produced its initial value; the
- * sweep of iteration k, on `stream`, takes each slice's F as soon as it is
- * written.  The launches synchronise through progress counters in ws; every
- * wait also ends on the stop flag, and after about 2 s the solve fails with
- * BS_ERR_HIP.  `stream` is joined with the side streams before returning. */
+ * parareal_iterate called for k = 1, 2, ... with the same block shapes):
+ * the fine propagation of iteration k starts each slice once the sweep of
+ * iteration k-1 has produced its initial value, and the sweep of iteration
+ * k takes each slice's F as soon as it is written.  With the one-wavefront
+ * fine shapes and the 256 x 4 sweep shape (grids up to 1024 nodes by
+ * default, N <= 512) the whole solve is one cooperative launch on `stream`;
+ * otherwise F runs on one of two library-owned side streams of the calling
+ * thread and the sweep on `stream`, which is joined with them before
+ * returning.  The launches synchronise through progress counters in ws;
+ * every wait also ends on the stop flag, and after about 2 s the solve
+ * fails with BS_ERR_HIP.  Beyond 4096 nodes the iterations run one after
+ * the other. */
 int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,
                    int coarse_kind, double tol, const pinn_net* net, int max_iter, void* ws,
                    size_t ws_bytes, double* U, int* iters, double* defect_hist, void* stream);

@@ -84,8 +84,9 @@ __global__ __launch_bounds__(T) void k_batch_sweep(const BatchOpt* __restrict__ 
                                                    double* __restrict__ U, const double* Fv,
                                                    double* Gold, const double* Vt,
                                                    int* __restrict__ active) {
-    __shared__ double lds[4 * T];
-    __shared__ double ftab[2 * kForceChunk];
+    __shared__ double smem[sweep_smem_doubles<T, MC>()];
+    double* lds = smem;
+    double* ftab = smem + 4 * T;
     const int oi = list[blockIdx.x];
     BatchState& st = state[oi];
     if (st.done) return;

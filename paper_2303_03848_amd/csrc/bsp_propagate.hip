@@ -156,8 +156,9 @@ __global__ __launch_bounds__(T) __attribute__((amdgpu_waves_per_eu(1, 1))) void 
 
 template <int T, int MC>
 __global__ __launch_bounds__(T) void k_sweep(SweepArgs a) {
-    __shared__ double lds[4 * T];
-    __shared__ double ftab[2 * kForceChunk];
+    __shared__ double smem[sweep_smem_doubles<T, MC>()];
+    double* lds = smem;
+    double* ftab = smem + 4 * T;
     __shared__ int pslot;
     if (stopped(a.stop)) return;
     Solver<T, MC> S;
@@ -332,9 +333,10 @@ __global__ __launch_bounds__(T) void k_large_theta(ThetaArgs a, const double* __
 template <int T, int MC>
 __global__ __launch_bounds__(T) void k_large_sweep(SweepArgs a, const double* __restrict__ tab,
                                                    const double* __restrict__ ptab) {
-    __shared__ double lds[4 * T];
-    __shared__ double ftab[2 * kForceChunk];
+    __shared__ double smem[sweep_smem_doubles<T, MC>()];
     __shared__ double kst[2 * BlockTriG<T, MC>::LOGT * T];
+    double* lds = smem;
+    double* ftab = smem + 4 * T;
     if (stopped(a.stop)) return;
     BlockTriG<T, MC> S;
     S.load(tab, ptab, a.o.s2, a.o.r, a.dT / (double)a.coarse_steps, 0.0, a.M, kst);

@@ -292,13 +292,113 @@ __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
     return true;
 }
 
+// Staged correction of one slice (chunks of MC >= 8 nodes per thread, where
+// a chunk-order access puts a whole wavefront on 64 different cache lines).
+// The coarse values g, in chunk order (thread p holds nodes p*MC ..
+// p*MC + MC-1), go through shared memory in rows of MC + 1 doubles (the pad
+// keeps both access orders free of bank conflicts); consecutive threads then
+// read and write consecutive nodes of Fv, Gold and U; the new values come
+// back to chunk order in g (zero past the grid).  predict: U[n+1] = Gold[n]
+// = g and g is left as it is.  A pass covers the chunks of
+// staged_chunks<T, MC>() threads (at most 4096 nodes), so the staging area is
+// staged_doubles<T, MC>() doubles of `stage`, which the forcing tables may
+// share (they are refilled by every run of steps; barriers separate the two).
+template <int T, int MC>
+constexpr int staged_chunks() {
+    return T * MC <= 4096 ? T : 4096 / MC;
+}
+template <int T, int MC>
+constexpr int staged_doubles() {
+    return staged_chunks<T, MC>() * (MC + 1);
+}
+// Shared memory of a sweep kernel: the solver's 4T doubles (which hold
+// factors kept from the setup: the staging area stays clear of them), then
+// the forcing tables with the staging area of the correction over them.
+template <int T, int MC>
+constexpr int sweep_smem_doubles() {
+    return 4 * T +
+           (2 * kForceChunk > staged_doubles<T, MC>() ? 2 * kForceChunk : staged_doubles<T, MC>());
+}
+
+template <int T, int MC>
+__device__ __forceinline__ void correct_staged(double (&g)[MC], int M, bool predict,
+                                               const double* __restrict__ fv,
+                                               double* __restrict__ go, double* __restrict__ un1,
+                                               double* stage, double& dmax, int& bad) {
+    constexpr int CH = staged_chunks<T, MC>();
+    constexpr int J = CH * MC / T;  // nodes per thread and pass
+    static_assert(CH * MC % T == 0 && T % CH == 0, "whole passes");
+    const int p = threadIdx.x;
+#pragma unroll 1
+    for (int c0 = 0; c0 < T; c0 += CH) {
+        const int pl = p - c0;
+        const bool mine = pl >= 0 && pl < CH;
+        __syncthreads();  // earlier readers of this shared memory are done
+        if (mine) {
+#pragma unroll
+            for (int q = 0; q < MC; ++q) stage[pl * (MC + 1) + q] = g[q];
+        }
+        __syncthreads();
+        const int base = c0 * MC;
+        if (predict) {
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int t = j * T + p, i = base + t;
+                if (i < M) {
+                    const double gg = stage[t + t / MC];
+                    un1[i] = gg;
+                    go[i] = gg;
+                }
+            }
+            continue;
+        }
+        // groups of G nodes per thread: the loads of a group are issued
+        // together, with few registers held beside the chunk
+        constexpr int G = J < 4 ? J : 4;
+        static_assert(J % G == 0, "whole groups");
+#pragma unroll
+        for (int j0 = 0; j0 < J; j0 += G) {
+            double f[G], gl[G], uo[G];
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int i = base + (j0 + j) * T + p;
+                f[j] = (i < M) ? fv[i] : 0.0;
+                gl[j] = (i < M) ? go[i] : 0.0;
+                uo[j] = (i < M) ? un1[i] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int t = (j0 + j) * T + p, i = base + t;
+                if (i < M) {
+                    const double gg = stage[t + t / MC];
+                    const double unew = f[j] + (gg - gl[j]);
+                    go[i] = gg;
+                    un1[i] = unew;
+                    dmax = fmax(dmax, fabs(unew - uo[j]));
+                    bad |= !isfinite(unew);
+                    stage[t + t / MC] = unew;
+                }
+            }
+        }
+        __syncthreads();
+        if (mine) {
+#pragma unroll
+            for (int q = 0; q < MC; ++q)
+                g[q] = (p * MC + q < M) ? stage[pl * (MC + 1) + q] : 0.0;
+        }
+    }
+    __syncthreads();  // the next coarse solve may overwrite the staging area
+}
+
 // One option's serial Parareal sweep over slices n = n0..N-1 in one block:
 //   g = G(U[n])                       (state carried in registers)
 //   predict: U[n+1] = g, Gold[n] = g
 //   else:    U[n+1] = Fv[n] + (g - Gold[n]), Gold[n] = g,
 //            dmax = max |U_new[n+1] - U_old[n+1]|, bad |= non-finite.
 // S (BlockTri, BlockTriH or BlockTriG) must be set up for implicit Euler with
-// dt = dT / coarse_steps.
+// dt = dT / coarse_steps.  For MC >= 8, lds must hold sweep_smem_doubles<T,
+// MC>() doubles with ftab = lds + 4T (the staged correction uses the space
+// after the solver's 4T doubles).
 // pipe (overlapped solve; ps its counters): the slice's fine result is
 // waited for after the coarse solve, U[n+1] is overwritten only once the
 // fine launch of this iteration has read it, and each finished slice is
@@ -373,7 +473,14 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
             if (n + 1 < N && !pipe_wait<false>(ps, ps.taken + n + 1, ps.k, stop, pslot))
                 return false;
         }
-        if (predict) {
+        if constexpr (!kPrefetch) {
+            // chunks of 8 or more nodes: the slice's global traffic goes
+            // through the staged, node-order correction
+            correct_staged<T, MC>(g, M, predict, Fv + (long)n * M, go, un1, lds + 4 * T, dmax,
+                                  bad);
+#pragma unroll
+            for (int q = 0; q < MC; ++q) V[q] = g[q];
+        } else if (predict) {
             store_chunk<T, MC>(un1, M, g);
             store_chunk<T, MC>(go, M, g);
 #pragma unroll

@@ -131,11 +131,14 @@ def test_network_coarse_full_size_converges_to_fine():
     assert normwise(U.cpu().numpy(), ref["U"]) <= 1e-10
 
 
-def test_large_grid_iterates():
-    """A grid beyond 4096 nodes (streamed-coefficient solver) through every
-    Parareal iterate against the oracle."""
+@pytest.mark.parametrize("M", [6000, 9000])
+def test_large_grid_iterates(M):
+    """A grid beyond 4096 nodes (streamed-coefficient solver; 16 and 32 nodes
+    per thread, the sweep's correction in passes of 4096 nodes, the last one
+    on the grid ragged) through every Parareal iterate against the oracle."""
     cuda()
-    cfg = dict(SMALL_CALL, M=9000, N=4, fine_steps=6, is_put=True)
+    say(f"large grid iterates M={M}")
+    cfg = dict(SMALL_CALL, M=M, N=4, fine_steps=6, is_put=True)
     M, N, Sf = cfg["M"], cfg["N"], cfg["fine_steps"]
     ref = oracle.parareal(_oracle_params(cfg), M, N, Sf, 1, oracle.COARSE_IE, tol=0.0,
                           keep_iterates=True)

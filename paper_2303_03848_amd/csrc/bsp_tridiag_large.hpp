@@ -38,8 +38,17 @@ struct BlockTriG {
     double aq, cq, invB, kap, mu;
     int p, nst;
 
-    __device__ __forceinline__ double coef(const double* tb, int f, int q) const {
-        return tb[((long)f * MC + q) * T + p];
+    // Table reads are raw buffer loads: one descriptor over this shape's
+    // table, the lane offset p*8 in one register and the row offset
+    // (f*MC + q)*T*8 as a scalar, so no per-lane address arithmetic; they are
+    // not flat loads either, whose completion every LDS wait would also have
+    // to await.  Reads past the table's size return zero.
+    static constexpr int kTabBytes = kLgFields * MC * T * 8;
+    using Rsrc = __amdgpu_buffer_rsrc_t;
+
+    __device__ __forceinline__ double coef(Rsrc rs, int f, int q) const {
+        return __builtin_bit_cast(
+            double, __builtin_amdgcn_raw_buffer_load_b64(rs, p * 8, (f * MC + q) * T * 8, 0));
     }
 
     // h = theta*dt > 0, e = (1-theta)*dt; tables built by k_large_setup for
@@ -71,6 +80,28 @@ struct BlockTriG {
         fc.init(p, MC, M, alpha1, gammaM, kap);
     }
 
+    // Coefficient stream of one step, in the order the step consumes it:
+    // forward elimination l_1 .. l_{NI-1}; back substitution kappa/u_{NI-1},
+    // then (c/u_q, kappa/u_q) for q = NI-2 .. 0; responses (v_q, w_q) for
+    // q = 0 .. NI-1.  Each load is issued kPD positions ahead of its use (a
+    // ring of kPD registers), so the chains wait on L2 latency once per step
+    // instead of once per node; the last prefetches are in flight across the
+    // interface reduction.
+    static constexpr int kNF = NI - 1, kNB = 1 + 2 * (NI - 1), kNS = kNF + kNB + 2 * NI;
+    // loads ahead (fewer for 32-node chunks, whose state and right-hand side
+    // already take 128 registers); nodes per scheduling group
+    static constexpr int kPD = MC >= 32 ? 8 : 16, kG = 4;
+    static constexpr int sfield(int s) {
+        return s < kNF ? kLgL
+               : s < kNF + kNB ? ((s == kNF || ((s - kNF - 1) & 1)) ? kLgKU : kLgCU)
+                               : (((s - kNF - kNB) & 1) ? kLgW : kLgV);
+    }
+    static constexpr int sq(int s) {
+        return s < kNF ? s + 1
+               : s < kNF + kNB ? (s == kNF ? NI - 1 : NI - 2 - (s - kNF - 1) / 2)
+                               : (s - kNF - kNB) / 2;
+    }
+
     // One step (see BlockTri::step).  lds: 4*T doubles; the stage multipliers
     // are read from their LDS copy (a global read after each stage's barrier
     // would put its latency on the critical path).
@@ -79,16 +110,64 @@ struct BlockTriG {
                                          double* lds) const {
         // Opaque per step: the compiler must not hoist the table loads out of
         // the step loop (that is the register footprint this solver avoids).
-        const double* tb = tab;
-        asm volatile("" : "+v"(tb));
+        const double* tb0 = tab;
+        asm volatile("" : "+s"(tb0));
+        // dword 3: the raw-buffer format word of gfx9-family descriptors
+        const Rsrc tb = __builtin_amdgcn_make_buffer_rsrc((void*)tb0, (short)0, kTabBytes,
+                                                          0x00020000);
+        double ring[kPD];
+#pragma unroll
+        for (int s = 0; s < kPD; ++s) ring[s] = coef(tb, sfield(s), sq(s));
         double d[MC];
         fc.rhs(V, flo, fhi, d);
+        // forward elimination, kG nodes per group: take the group's
+        // coefficients, issue the loads kPD positions on, then compute
 #pragma unroll
-        for (int q = 1; q < NI; ++q) d[q] = fma(-coef(tb, kLgL, q), d[q - 1], d[q]);
-        d[NI - 1] *= coef(tb, kLgKU, NI - 1);
+        for (int q0 = 1; q0 < NI; q0 += kG) {
+            double c[kG];
 #pragma unroll
-        for (int q = NI - 2; q >= 0; --q)
-            d[q] = fma(-coef(tb, kLgCU, q), d[q + 1], d[q] * coef(tb, kLgKU, q));
+            for (int j = 0; j < kG; ++j) {
+                const int s = q0 - 1 + j;
+                if (q0 + j < NI) {
+                    c[j] = ring[s % kPD];
+                    if (s + kPD < kNS) ring[s % kPD] = coef(tb, sfield(s + kPD), sq(s + kPD));
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < kG; ++j)
+                if (q0 + j < NI) d[q0 + j] = fma(-c[j], d[q0 + j - 1], d[q0 + j]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // back substitution: kappa/u_{NI-1} alone, then (c/u_q, kappa/u_q)
+        {
+            const int s = kNF;
+            const double ku = ring[s % kPD];
+            if (s + kPD < kNS) ring[s % kPD] = coef(tb, sfield(s + kPD), sq(s + kPD));
+            d[NI - 1] *= ku;
+        }
+#pragma unroll
+        for (int e0 = 0; e0 < NI - 1; e0 += kG) {  // e: q = NI-2-e
+            double cu[kG], ku[kG];
+#pragma unroll
+            for (int j = 0; j < kG; ++j) {
+                const int s = kNF + 1 + 2 * (e0 + j);
+                if (e0 + j < NI - 1) {
+                    cu[j] = ring[s % kPD];
+                    if (s + kPD < kNS) ring[s % kPD] = coef(tb, sfield(s + kPD), sq(s + kPD));
+                    ku[j] = ring[(s + 1) % kPD];
+                    if (s + 1 + kPD < kNS)
+                        ring[(s + 1) % kPD] = coef(tb, sfield(s + 1 + kPD), sq(s + 1 + kPD));
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < kG; ++j) {
+                const int q = NI - 2 - (e0 + j);
+                if (e0 + j < NI - 1) d[q] = fma(-cu[j], d[q + 1], d[q] * ku[j]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
 
         double* ybuf = lds;
         double* pb0 = lds + T;
@@ -118,9 +197,27 @@ struct BlockTriG {
         zbuf[p] = z;
         __syncthreads();
         const double zl = (p > 0) ? zbuf[p - 1] : 0.0;
+        // interior values from the responses (v_q, w_q)
 #pragma unroll
-        for (int q = 0; q < NI; ++q)
-            V[q] = fma(zl, coef(tb, kLgV, q), fma(z, coef(tb, kLgW, q), d[q]));
+        for (int q0 = 0; q0 < NI; q0 += kG) {
+            double vv[kG], ww[kG];
+#pragma unroll
+            for (int j = 0; j < kG; ++j) {
+                const int s = kNF + kNB + 2 * (q0 + j);
+                if (q0 + j < NI) {
+                    vv[j] = ring[s % kPD];
+                    if (s + kPD < kNS) ring[s % kPD] = coef(tb, sfield(s + kPD), sq(s + kPD));
+                    ww[j] = ring[(s + 1) % kPD];
+                    if (s + 1 + kPD < kNS)
+                        ring[(s + 1) % kPD] = coef(tb, sfield(s + 1 + kPD), sq(s + 1 + kPD));
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int j = 0; j < kG; ++j)
+                if (q0 + j < NI) V[q0 + j] = fma(zl, vv[j], fma(z, ww[j], d[q0 + j]));
+            __builtin_amdgcn_sched_barrier(0);
+        }
         V[MC - 1] = z + rz;
     }
 };

@@ -149,6 +149,47 @@ def test_large_grid_iterates(M):
         assert normwise(pr.U.cpu().numpy(), ref["iterates"][k]) <= 1e-11, k
 
 
+@pytest.mark.parametrize("T,MC,is_put,kind", [
+    (64, 8, False, bsp.COARSE_IE), (64, 16, True, bsp.COARSE_IE), (128, 8, False, bsp.COARSE_IE),
+    (128, 16, False, bsp.COARSE_PINN_IE), (256, 8, True, bsp.COARSE_IE),
+    (256, 16, True, bsp.COARSE_IE), (512, 8, False, bsp.COARSE_PINN_IE)])
+def test_sweep_block_shapes(T, MC, is_put, kind):
+    """Every built sweep shape with 8 or more nodes per thread (the staged,
+    node-order correction; any of them may be installed by the autotuner) on
+    a ragged grid 37 nodes short of the shape, through every Parareal
+    iterate against the oracle."""
+    cuda()
+    M = T * MC - 37
+    say(f"sweep shape ({T},{MC}) M={M} put={is_put} kind={kind}")
+    cfg = dict(SMALL_CALL, M=M, N=4, fine_steps=6, is_put=is_put, n_in=2, depth=2, width=16)
+    po = _oracle_params(cfg)
+    net, Vt = None, None
+    if kind != bsp.COARSE_IE:
+        th = _seeded_net(cfg, seed=5)
+        net = bsp.PinnNet(to_dev(th, torch.float32), 2, cfg["depth"], cfg["width"], bsp.PREC_FP32)
+        taus = np.arange(cfg["N"] + 1) * (po.T / cfg["N"])
+        Vt = mlp.grid_values(th.astype(np.float64), 2, cfg["depth"], cfg["width"], po.K, taus,
+                             oracle.grid(po, M))
+    ref = oracle.parareal(po, M, cfg["N"], cfg["fine_steps"], 1,
+                          oracle.COARSE_IE if net is None else oracle.COARSE_PINN_IE, Vt=Vt,
+                          tol=0.0, keep_iterates=True)
+    try:
+        bsp.bs_tune_reset()
+        bsp.bs_tune_set_shape(1, M, M, T, MC)
+        pr = bsp.Parareal(option_params(cfg), M, cfg["N"], cfg["fine_steps"], 1, kind, net)
+        # the network grid (call prices) is evaluated in FP32 on the GPU, in
+        # FP64 by the oracle: the iterates before the last differ at that level
+        tol = 1e-11 if net is None else 1e-6
+        assert normwise(pr.start().cpu().numpy(), ref["iterates"][0]) <= tol
+        for k in range(1, cfg["N"] + 1):
+            pr.iterate(k)
+            assert normwise(pr.U.cpu().numpy(), ref["iterates"][k]) <= tol, k
+        # after N iterations every slice holds the serial fine solution
+        assert normwise(pr.U.cpu().numpy(), ref["iterates"][cfg["N"]]) <= 1e-11
+    finally:
+        bsp.bs_tune_reset()
+
+
 def test_large_put_workload_sampled():
     """The large put (M = 16384, N = 256 slices, 2048 CN steps per slice,
     256 x 6 BF16 network coarse, tol 1e-10) at full size: the converged

@@ -3,13 +3,15 @@
 // of the network coarse propagator).  tanh is evaluated through the
 // exponential (tanh_bf16_act): the activations are rounded to bfloat16.
 //
-// One block of 4 wavefronts takes P = 128 points through every layer without
-// leaving the CU: activations ping-pong between two LDS tiles [P][W] (bf16).
+// One block of 4 wavefronts (8 for width 256) takes P = 128 points through
+// every layer without leaving the CU: activations ping-pong between two LDS
+// tiles [P][W] (bf16).
 // Each wavefront owns 32-unit column blocks of a layer's output and all P/32
 // row tiles; a weight fragment (8 consecutive inputs of one unit) is read
 // from global memory (the layer stays in L2), converted to bf16 in
 // registers and used for all row tiles before the next one, so weights are
-// neither staged in LDS nor re-read per 32 points.  One
+// neither staged in LDS nor re-read per 32 points; the fragments are loaded
+// eight K-steps ahead of their use.  One
 // v_mfma_f32_32x32x16_bf16 per row tile and 16-wide K step.  The tiny first
 // layer (2 or 4 inputs) and the output dot product run on the vector units.
 #include "bsp_common.hpp"
@@ -19,14 +21,22 @@ namespace bsp {
 
 constexpr int kMlpPoints = 128;  // points per block
 
+// Wavefronts per block: 8 for the widest layers, so that two wavefronts share
+// each SIMD and one's tanh epilogue overlaps the other's matrix products.
 template <int W>
-__global__ __launch_bounds__(256) void k_mlp_bf16(const float* __restrict__ prm, int depth, long n,
+constexpr int mlp_waves() {
+    return W >= 256 ? 8 : 4;
+}
+
+template <int W>
+__global__ __launch_bounds__(64 * mlp_waves<W>()) void k_mlp_bf16(const float* __restrict__ prm, int depth, long n,
                                                   NetInput in, float* __restrict__ out32,
                                                   double* __restrict__ out64, double scale) {
     constexpr int P = kMlpPoints;
     constexpr int MT = P / 32;                  // row tiles
     constexpr int LDA = W + 8;                  // row stride of the activation tiles (bf16)
-    constexpr int NB = W >= 128 ? W / 128 : 1;  // output column blocks per wavefront
+    constexpr int NW = mlp_waves<W>(), NT = 64 * NW;
+    constexpr int NB = W >= 32 * NW ? W / (32 * NW) : 1;  // output column blocks per wavefront
     __shared__ __align__(16) __bf16 act[2][P * LDA];
     __shared__ float xin[P][4];
     __shared__ int ok[P];
@@ -36,14 +46,14 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(const float* __restrict__ prm,
     const long base = (long)blockIdx.x * P;
     const int n_in = in.n_in;
 
-    for (int t = tid; t < P; t += 256) {
+    for (int t = tid; t < P; t += NT) {
         float x[4] = {0.f, 0.f, 0.f, 0.f};
         ok[t] = base + t < n && net_input(in, base + t, x);
 #pragma unroll
         for (int c = 0; c < 4; ++c) xin[t][c] = x[c];
     }
     __syncthreads();
-    for (int e = tid; e < P * W; e += 256) {
+    for (int e = tid; e < P * W; e += NT) {
         const int i = e / W, j = e - i * W;
         float z = prm[W * n_in + j];
         for (int c = 0; c < n_in; ++c) z = fmaf(prm[j * n_in + c], xin[i][c], z);
@@ -57,19 +67,34 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(const float* __restrict__ prm,
         __syncthreads();  // act[cur] complete
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int cb = wave + 4 * b;
+            const int cb = wave + NW * b;
             if (cb * 32 >= W) continue;
             f32x16 acc[MT];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int v = 0; v < 16; ++v) acc[mt][v] = 0.f;
-            // unit j = cb*32 + r32; this lane's inputs 16 t + 8 h .. + 7
+            // unit j = cb*32 + r32; this lane's inputs 16 t + 8 h .. + 7.
+            // The weight fragments are loaded PD K-steps ahead of their use
+            // (a ring of registers): with one wavefront per SIMD nothing else
+            // hides the L2 latency.
             const float* wrow = Wl + (long)(cb * 32 + r32) * W + 8 * h;
+            constexpr int KT = W / 16, PD = KT < 8 ? KT : 8;
+            float4 wr0[PD], wr1[PD];
 #pragma unroll
-            for (int t = 0; t < W / 16; ++t) {
-                const float4 w0 = *reinterpret_cast<const float4*>(wrow + 16 * t);
-                const float4 w1 = *reinterpret_cast<const float4*>(wrow + 16 * t + 4);
+            for (int t = 0; t < PD; ++t) {
+                wr0[t] = *reinterpret_cast<const float4*>(wrow + 16 * t);
+                wr1[t] = *reinterpret_cast<const float4*>(wrow + 16 * t + 4);
+            }
+#pragma unroll
+            for (int t = 0; t < KT; ++t) {
+                const float4 w0 = wr0[t % PD];
+                const float4 w1 = wr1[t % PD];
+                if (t + PD < KT) {
+                    wr0[t % PD] = *reinterpret_cast<const float4*>(wrow + 16 * (t + PD));
+                    wr1[t % PD] = *reinterpret_cast<const float4*>(wrow + 16 * (t + PD) + 4);
+                }
+                __builtin_amdgcn_sched_barrier(0);
                 bf16x8 bb;
                 bb[0] = (__bf16)w0.x; bb[1] = (__bf16)w0.y; bb[2] = (__bf16)w0.z; bb[3] = (__bf16)w0.w;
                 bb[4] = (__bf16)w1.x; bb[5] = (__bf16)w1.y; bb[6] = (__bf16)w1.z; bb[7] = (__bf16)w1.w;
@@ -94,7 +119,7 @@ __global__ __launch_bounds__(256) void k_mlp_bf16(const float* __restrict__ prm,
     __syncthreads();
     // output layer: 8 threads per point, then a reduction over those 8 lanes
     const int part = tid & 7;
-    for (int i = tid >> 3; i < P; i += 32) {
+    for (int i = tid >> 3; i < P; i += NT / 8) {
         float s = 0.f;
         for (int j = part; j < W; j += 8) s = fmaf(prm[off + j], (float)act[cur][i * LDA + j], s);
         s += __shfl_xor(s, 1);
@@ -110,7 +135,8 @@ int launch_mlp_bf16(const pinn_net& net, long n, const NetInput& in, float* out3
     switch (net.width) {
 #define BSP_W(W_)                                                                                 \
     case W_:                                                                                      \
-        hipLaunchKernelGGL(k_mlp_bf16<W_>, grid, dim3(256), 0, stream, net.params, net.depth, n, \
+        hipLaunchKernelGGL(k_mlp_bf16<W_>, grid, dim3(64 * mlp_waves<W_>()), 0, stream,         \
+                           net.params, net.depth, n,                                              \
                            in, out32, out64, scale);                                              \
         break;
         BSP_W(32) BSP_W(64) BSP_W(128) BSP_W(256)

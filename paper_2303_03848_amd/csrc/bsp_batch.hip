@@ -221,6 +221,51 @@ static int make_plan(int n_opt, const bs_params* prm, const bs_grid* grids, cons
     return BS_OK;
 }
 
+// Streams for the shape classes of one phase.  The launches of a phase touch
+// disjoint items (fine) or options (sweep), so they run side by side: fork
+// from the caller's stream, one stream per class, join back on it (the same
+// calls build parallel branches when the iteration is captured in a graph).
+// Created once per thread and device, kept until the process ends.
+constexpr int kMaxClasses = 16;
+struct ClassStreams {
+    int dev = -1;
+    hipStream_t s[kMaxClasses] = {};
+    hipEvent_t fork[2] = {}, join[2][kMaxClasses] = {};
+};
+static thread_local ClassStreams t_cls;
+
+static int class_streams() {
+    ClassStreams& C = t_cls;
+    int dev = 0;
+    BSP_HIP(hipGetDevice(&dev));
+    if (C.dev == dev) return BS_OK;
+    for (int i = 0; i < kMaxClasses; ++i) {
+        BSP_HIP(hipStreamCreateWithFlags(&C.s[i], hipStreamNonBlocking));
+        for (int ph = 0; ph < 2; ++ph)
+            BSP_HIP(hipEventCreateWithFlags(&C.join[ph][i], hipEventDisableTiming));
+    }
+    for (int ph = 0; ph < 2; ++ph) BSP_HIP(hipEventCreateWithFlags(&C.fork[ph], hipEventDisableTiming));
+    C.dev = dev;
+    return BS_OK;
+}
+
+// launch(c, stream) for the n classes of phase ph (0 fine, 1 sweep) on the
+// class streams, joined on st before the call returns.
+template <class F>
+static int run_phase(int ph, int n, hipStream_t st, F&& launch) {
+    if (n == 1) return launch(0, st);
+    ClassStreams& C = t_cls;
+    BSP_HIP(hipEventRecord(C.fork[ph], st));
+    for (int c = 0; c < n; ++c) {
+        BSP_HIP(hipStreamWaitEvent(C.s[c], C.fork[ph], 0));
+        const int rc = launch(c, C.s[c]);
+        if (rc) return rc;
+        BSP_HIP(hipEventRecord(C.join[ph][c], C.s[c]));
+        BSP_HIP(hipStreamWaitEvent(st, C.join[ph][c], 0));
+    }
+    return BS_OK;
+}
+
 static int launch_fine_class(TriShape sh, int nitems, const BatchWs& w, const FItem* items,
                              const double* U, hipStream_t st) {
 #define BSP_CASE(T_, MC_)                                                                       \
@@ -342,10 +387,14 @@ extern "C" int parareal_solve_batch(int n_opt, const bs_params* prm, const bs_gr
     hipLaunchKernelGGL(k_batch_initial, dim3(n_opt), dim3(256), 0, st, w.opts, grids[0].payoff_mode, U);
     BSP_LAUNCHED();
     if (is_net && (rc = launch_pinn_batch_grid(*net, w.opts, w.tiles, P.vt_total, w.Vt, st))) return rc;
-    for (size_t c = 0; c < P.sweep_cls.size(); ++c)
-        if ((rc = launch_sweep_class(P.sweep_cls[c], (int)P.sweep_lists[c].size(), w,
-                                     w.lists + list_off[c], 1, kind, tol, max_iter, U, st)))
-            return rc;
+    BSP_CHECK_ARG(P.fine_cls.size() <= (size_t)kMaxClasses && P.sweep_cls.size() <= (size_t)kMaxClasses,
+                  "too many block-shape classes");
+    if ((rc = class_streams())) return rc;
+    rc = run_phase(1, (int)P.sweep_cls.size(), st, [&](int c, hipStream_t s) {
+        return launch_sweep_class(P.sweep_cls[c], (int)P.sweep_lists[c].size(), w,
+                                  w.lists + list_off[c], 1, kind, tol, max_iter, U, s);
+    });
+    if (rc) return rc;
     hipLaunchKernelGGL(k_batch_set, dim3(1), dim3(1), 0, st, w.counters, w.counters + 1, 1, n_opt);
     BSP_LAUNCHED();
 
@@ -354,15 +403,16 @@ extern "C" int parareal_solve_batch(int n_opt, const bs_params* prm, const bs_gr
     kmax = max_iter < kmax ? max_iter : kmax;
 
     auto iteration = [&]() -> int {
-        int r;
-        for (size_t c = 0; c < P.fine_cls.size(); ++c)
-            if ((r = launch_fine_class(P.fine_cls[c], (int)P.fine_items[c].size(), w,
-                                       w.items + item_off[c], U, st)))
-                return r;
-        for (size_t c = 0; c < P.sweep_cls.size(); ++c)
-            if ((r = launch_sweep_class(P.sweep_cls[c], (int)P.sweep_lists[c].size(), w,
-                                        w.lists + list_off[c], 0, kind, tol, max_iter, U, st)))
-                return r;
+        int r = run_phase(0, (int)P.fine_cls.size(), st, [&](int c, hipStream_t s) {
+            return launch_fine_class(P.fine_cls[c], (int)P.fine_items[c].size(), w,
+                                     w.items + item_off[c], U, s);
+        });
+        if (r) return r;
+        r = run_phase(1, (int)P.sweep_cls.size(), st, [&](int c, hipStream_t s) {
+            return launch_sweep_class(P.sweep_cls[c], (int)P.sweep_lists[c].size(), w,
+                                      w.lists + list_off[c], 0, kind, tol, max_iter, U, s);
+        });
+        if (r) return r;
         hipLaunchKernelGGL(k_batch_tick, dim3(1), dim3(1), 0, st, w.counters);
         BSP_LAUNCHED();
         return BS_OK;

@@ -44,8 +44,22 @@ enum {
     BS_ERR_ARG = -1,       /* invalid argument (null pointer, size out of range, ...) */
     BS_ERR_HIP = -2,       /* a HIP runtime call failed */
     BS_ERR_NONFINITE = -3, /* a NaN or Inf appeared in the Parareal state */
+    BS_ERR_DIVERGED = -4,  /* the defect grew by bs_divergence_growth() over the first one */
     BS_ERR_WORKSPACE = -5  /* workspace pointer null or too small */
 };
+
+/* Divergence guard of parareal_solve and parareal_solve_batch.  Eq. (7)
+ * reaches the serial fine solution after N iterations whatever G is (Sec.
+ * 3.1), but an iteration whose defect grows instead of shrinking is not
+ * converging and, in floating point, amplifies rounding errors: the solve
+ * stops at the first iteration k >= 2 whose defect exceeds `growth` times
+ * the defect of iteration 1 and returns BS_ERR_DIVERGED (the state is that
+ * iterate).  Default BS_DIVERGENCE_GROWTH; bs_set_divergence_growth(g) sets
+ * it for later solves of the whole process (g > 0, INFINITY turns the guard
+ * off; BS_ERR_ARG otherwise). */
+#define BS_DIVERGENCE_GROWTH 1.0e3
+int bs_set_divergence_growth(double growth);
+double bs_divergence_growth(void);
 
 /* Option and model coefficients (eq. (1)): strike K, riskless rate r,
  * volatility sigma, expiry T, truncation S_max of the asset axis.
@@ -127,17 +141,22 @@ int bs_coarse_numeric(const bs_params* prm, const bs_grid* grid, int nsys, const
  * X: device float32 [n][n_in]; v_out: device float32 [n]. */
 int pinn_forward(const pinn_net* net, int n, const float* X, float* v_out, void* stream);
 
-/* Bytes of device workspace pinn_residual_fwd_bwd needs. */
-size_t pinn_residual_workspace_size(const pinn_net* net, int n_f, int n_e, int n_b);
+/* *bytes (host, out) = bytes of device workspace pinn_residual_fwd_bwd needs
+ * for these point counts.  BS_ERR_ARG on an invalid network or counts. */
+int pinn_residual_workspace_size(const pinn_net* net, int n_f, int n_e, int n_b, size_t* bytes);
 
 /* PINN loss and its gradient (eqs. (11)-(14)), one fused pass.
  * Interior points X_f [n_f][n_in]: residual
  *     f = v_tau - sigma^2 x^2 v_xx / 2 - r x v_x + r v   (eq. (1) in tau, x = S/K, v = V/K),
  *   with v_tau, v_x, v_xx differentiated through the network by hand-written
  *   forward-mode streams (the paper uses automatic differentiation).
- * Terminal points X_e [n_e][n_in] (tau = 0): target max(x-1,0) (call) or
- *   max(1-x,0) (put), eq. (2).
- * Boundary points X_b [n_b][n_in]: x == 0 is the lower boundary (call 0, put
+ * Terminal points X_e [n_e][n_in]: target y_e[i] (device float32 [n_e]) or,
+ *   with y_e NULL, the expiry condition of eq. (2) at tau = 0, max(x-1,0)
+ *   (call) or max(1-x,0) (put).  With targets given the set is any set of
+ *   value-matching points (e.g. fine-propagator data, and with n_f = n_b = 0
+ *   the loss of a network trained on data alone).
+ * Boundary points X_b [n_b][n_in]: target y_b[i] (device float32 [n_b]) or,
+ *   with y_b NULL, eqs. (3)-(4): x == 0 is the lower boundary (call 0, put
  *   exp(-r tau)); any other x is the upper one (call x - exp(-r tau), put 0).
  * sigma and r come from `prm` when n_in == 2 and from columns 2, 3 of X when
  * n_in == 4; prm->is_put selects the targets (prm must not be NULL; K, T,
@@ -147,12 +166,16 @@ size_t pinn_residual_workspace_size(const pinn_net* net, int n_f, int n_e, int n
  * ws: device workspace of pinn_residual_workspace_size() bytes.
  * n_f, n_e, n_b >= 0; an empty set contributes 0 to loss and gradient. */
 int pinn_residual_fwd_bwd(const pinn_net* net, const bs_params* prm, int n_f, const float* X_f,
-                          int n_e, const float* X_e, int n_b, const float* X_b, float* loss3,
-                          float* grad, void* ws, size_t ws_bytes, void* stream);
+                          int n_e, const float* X_e, const float* y_e, int n_b, const float* X_b,
+                          const float* y_b, float* loss3, float* grad, void* ws, size_t ws_bytes,
+                          void* stream);
 
-/* Bytes of device workspace one Parareal solve needs (F and coarse values,
- * progress counters, and the network grid for the network kinds). */
-size_t parareal_workspace_size(const bs_grid* grid, const bs_slices* sl, int coarse_kind);
+/* *bytes (host, out) = bytes of device workspace one Parareal solve needs (F
+ * and coarse values, progress counters, a second state buffer for the
+ * one-launch solve, and the network grid for the network kinds).  BS_ERR_ARG
+ * on an invalid grid, slice count or kind. */
+int parareal_workspace_size(const bs_grid* grid, const bs_slices* sl, int coarse_kind,
+                            size_t* bytes);
 
 /* Start a Parareal solve: U[0] = expiry payoff; for the network kinds the
  * network is evaluated at every (tau_n, S_j), n = 0..N; then the coarse
@@ -178,8 +201,9 @@ int parareal_iterate(const bs_params* prm, const bs_grid* grid, const bs_slices*
  * (the iterate then equals serial fine integration) or k == max_iter.
  * SYNCHRONOUS.  iters (host, out): iterations done; defect_hist (host,
  * [max_iter] or NULL): defect of each iteration.  net may be NULL for
- * BS_COARSE_IE.  Returns BS_OK, BS_NOT_CONVERGED (max_iter hit first) or an
- * error.
+ * BS_COARSE_IE.  Returns BS_OK, BS_NOT_CONVERGED (max_iter hit first),
+ * BS_ERR_NONFINITE, BS_ERR_DIVERGED (see bs_set_divergence_growth; U then
+ * holds the iterate that tripped the guard) or another error.
  * For grids of up to 4096 nodes the iterations overlap (same iterates as
  * parareal_iterate called for k = 1, 2, ... with the same block shapes):
  * the fine propagation of iteration k starts each slice once the sweep of
@@ -197,10 +221,11 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
                    int coarse_kind, double tol, const pinn_net* net, int max_iter, void* ws,
                    size_t ws_bytes, double* U, int* iters, double* defect_hist, void* stream);
 
-/* Bytes of device workspace parareal_solve_batch needs for these options
- * (host arrays of n_opt entries); 0 if an argument is invalid. */
-size_t parareal_batch_workspace_size(int n_opt, const bs_params* prm, const bs_grid* grids,
-                                     const bs_slices* sl, int coarse_kind);
+/* *bytes (host, out) = bytes of device workspace parareal_solve_batch needs
+ * for these options (host arrays of n_opt entries).  BS_ERR_ARG if an option
+ * is invalid (bs_last_error names it). */
+int parareal_batch_workspace_size(int n_opt, const bs_params* prm, const bs_grid* grids,
+                                  const bs_slices* sl, int coarse_kind, size_t* bytes);
 
 /* Solve n_opt independent Parareal problems together (batched options with
  * uneven grids and slice counts).  Every phase of an iteration is one launch
@@ -219,8 +244,9 @@ size_t parareal_batch_workspace_size(int n_opt, const bs_params* prm, const bs_g
  *    V_put = K v - S + K exp(-r tau).
  * iters (host [n_opt], out): iterations per option; defects (host [n_opt] or
  * NULL, out): last defect per option.  SYNCHRONOUS.  Returns BS_OK,
- * BS_NOT_CONVERGED (some option hit max_iter first), BS_ERR_NONFINITE, or an
- * argument / workspace / HIP error. */
+ * BS_NOT_CONVERGED (some option hit max_iter first), BS_ERR_NONFINITE,
+ * BS_ERR_DIVERGED (an option tripped the divergence guard; it stops there, the
+ * others go on), or an argument / workspace / HIP error. */
 int parareal_solve_batch(int n_opt, const bs_params* prm, const bs_grid* grids,
                          const bs_slices* sl, int coarse_kind, double tol, const pinn_net* net,
                          int max_iter, void* ws, size_t ws_bytes, double* U, const long* offsets,
@@ -249,6 +275,14 @@ int bs_tune_reset(void);
  * thread-safe: for a single measuring thread. */
 int bs_profile_enable(int on);
 int bs_profile_read(double* out);
+
+/* Releases what the library keeps between calls for the calling thread and
+ * the current device (pinned per-iteration record, side streams and events,
+ * coefficient tables of the large-grid solver, timing events).  The next call
+ * that needs them creates them again.  Call it once no call of this thread is
+ * in flight, before the HIP runtime shuts down (the Python binding does so at
+ * interpreter exit). */
+int bs_release_resources(void);
 
 #ifdef __cplusplus
 }

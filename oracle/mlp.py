@@ -161,18 +161,29 @@ def _mean(a):
     return float(np.mean(a)) if a.size else 0.0
 
 
-def loss3(theta, X_f, X_e, X_b, n_in, depth, width, is_put=False, sigma=None, r=None):
-    """(MSE_f, MSE_exp, MSE_b), eqs. (12)-(14); their sum is eq. (11)."""
+def _targets(X_e, X_b, is_put, r, y_e, y_b):
+    """Value targets of the terminal and boundary sets: given, or eqs. (2)-(4)."""
+    ye = terminal_target(X_e, is_put) if y_e is None else np.asarray(y_e, dtype=np.float64)
+    yb = boundary_target(X_b, is_put, r) if y_b is None else np.asarray(y_b, dtype=np.float64)
+    return ye, yb
+
+
+def loss3(theta, X_f, X_e, X_b, n_in, depth, width, is_put=False, sigma=None, r=None,
+          y_e=None, y_b=None):
+    """(MSE_f, MSE_exp, MSE_b), eqs. (12)-(14); their sum is eq. (11).  y_e, y_b:
+    value targets replacing eq. (2) at the X_e points and eqs. (3)-(4) at the
+    X_b points (a network fitted to data: n_f = 0 and y_e the data)."""
     f = residual(theta, X_f, n_in, depth, width, sigma, r)
     ve = forward(theta, X_e, n_in, depth, width)
     vb = forward(theta, X_b, n_in, depth, width)
-    ye = terminal_target(X_e, is_put)
-    yb = boundary_target(X_b, is_put, r)
+    ye, yb = _targets(X_e, X_b, is_put, r, y_e, y_b)
     return (_mean(f * f), _mean((ve - ye) ** 2), _mean((vb - yb) ** 2))
 
 
-def loss_grad(theta, X_f, X_e, X_b, n_in, depth, width, is_put=False, sigma=None, r=None):
-    """Gradient of MSE_f + MSE_exp + MSE_b with respect to the flat parameters.
+def loss_grad(theta, X_f, X_e, X_b, n_in, depth, width, is_put=False, sigma=None, r=None,
+              y_e=None, y_b=None):
+    """Gradient of MSE_f + MSE_exp + MSE_b with respect to the flat parameters
+    (targets y_e, y_b as in loss3).
 
     Reverse pass, written by hand, through the value and derivative streams.
     Output adjoints per point (gv, gt, gx, gxx) for (v, v_tau, v_x, v_xx):
@@ -202,6 +213,7 @@ def loss_grad(theta, X_f, X_e, X_b, n_in, depth, width, is_put=False, sigma=None
     v_t, v_x, v_xx = a_t @ wo, a_x @ wo, a_xx @ wo
 
     n = X.shape[0]
+    ye, yb = _targets(X_e, X_b, is_put, r, y_e, y_b)
     gv, gt, gx, gxx = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
     if n_f:
         sl = slice(0, n_f)
@@ -215,10 +227,10 @@ def loss_grad(theta, X_f, X_e, X_b, n_in, depth, width, is_put=False, sigma=None
         gxx[sl] = -0.5 * sg * sg * x * x * df
     if n_e:
         sl = slice(n_f, n_f + n_e)
-        gv[sl] = 2.0 * (v[sl] - terminal_target(X_e, is_put)) / n_e
+        gv[sl] = 2.0 * (v[sl] - ye) / n_e
     if n_b:
         sl = slice(n_f + n_e, n)
-        gv[sl] = 2.0 * (v[sl] - boundary_target(X_b, is_put, r)) / n_b
+        gv[sl] = 2.0 * (v[sl] - yb) / n_b
 
     grads = []
     g_wo = gv @ a + gt @ a_t + gx @ a_x + gxx @ a_xx

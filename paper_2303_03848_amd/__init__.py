@@ -14,6 +14,7 @@ Names follow the C ABI one to one:
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
 from dataclasses import dataclass
@@ -24,7 +25,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbsparareal.so")
 
 BS_OK, BS_NOT_CONVERGED = 0, 1
-BS_ERR_ARG, BS_ERR_HIP, BS_ERR_NONFINITE, BS_ERR_WORKSPACE = -1, -2, -3, -5
+BS_ERR_ARG, BS_ERR_HIP, BS_ERR_NONFINITE, BS_ERR_DIVERGED, BS_ERR_WORKSPACE = -1, -2, -3, -4, -5
+BS_DIVERGENCE_GROWTH = 1.0e3
 COARSE_IE, COARSE_PINN, COARSE_PINN_IE = 0, 1, 2
 PREC_FP32, PREC_BF16 = 0, 1
 
@@ -32,7 +34,8 @@ EXPORTS = ("bs_last_error", "bs_initial", "bs_fine_propagate_batch", "bs_coarse_
            "pinn_forward", "pinn_residual_workspace_size", "pinn_residual_fwd_bwd",
            "parareal_workspace_size", "parareal_start", "parareal_iterate", "parareal_solve",
            "parareal_batch_workspace_size", "parareal_solve_batch",
-           "bs_tune_set_shape", "bs_tune_reset", "bs_profile_enable", "bs_profile_read")
+           "bs_tune_set_shape", "bs_tune_reset", "bs_profile_enable", "bs_profile_read",
+           "bs_set_divergence_growth", "bs_divergence_growth", "bs_release_resources")
 
 
 class BsError(RuntimeError):
@@ -73,32 +76,50 @@ def load_library(path: str = LIB_PATH):
     P, G, S, N = (ctypes.POINTER(c) for c in (_Params, _Grid, _Slices, _Net))
     vp, i, d, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
     ip, dp = ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double)
+    szp = ctypes.POINTER(ctypes.c_size_t)
     sig = {
         "bs_last_error": (ctypes.c_char_p, []),
         "bs_initial": (i, [P, G, vp, vp]),
         "bs_fine_propagate_batch": (i, [P, G, i, vp, d, i, vp, vp, vp]),
         "bs_coarse_numeric": (i, [P, G, i, vp, d, i, vp, vp, vp]),
         "pinn_forward": (i, [N, i, vp, vp, vp]),
-        "pinn_residual_workspace_size": (sz, [N, i, i, i]),
-        "pinn_residual_fwd_bwd": (i, [N, P, i, vp, i, vp, i, vp, vp, vp, vp, sz, vp]),
-        "parareal_workspace_size": (sz, [G, S, i]),
+        "pinn_residual_workspace_size": (i, [N, i, i, i, szp]),
+        "pinn_residual_fwd_bwd": (i, [N, P, i, vp, i, vp, vp, i, vp, vp, vp, vp, vp, sz, vp]),
+        "parareal_workspace_size": (i, [G, S, i, szp]),
         "parareal_start": (i, [P, G, S, i, N, vp, sz, vp, vp]),
         "parareal_iterate": (i, [P, G, S, i, N, vp, sz, vp, i, dp, ip, vp]),
         "parareal_solve": (i, [P, G, S, i, d, N, i, vp, sz, vp, ip, dp, vp]),
-        "parareal_batch_workspace_size": (sz, [i, P, G, S, i]),
+        "parareal_batch_workspace_size": (i, [i, P, G, S, i, szp]),
         "parareal_solve_batch": (i, [i, P, G, S, i, d, N, i, vp, sz, vp,
                                      ctypes.POINTER(ctypes.c_long), ip, dp, i, vp]),
         "bs_tune_set_shape": (i, [i, i, i, i, i]),
         "bs_tune_reset": (i, []),
         "bs_profile_enable": (i, [i]),
         "bs_profile_read": (i, [dp]),
+        "bs_set_divergence_growth": (i, [d]),
+        "bs_divergence_growth": (d, []),
+        "bs_release_resources": (i, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    # the library's pinned buffers, streams and tables go before the HIP
+    # runtime shuts down
+    atexit.register(_release_at_exit)
     return lib
+
+
+def _release_at_exit():
+    if _lib is not None:
+        try:
+            import torch as _t
+            if _t.cuda.is_initialized():
+                _t.cuda.synchronize()
+                _lib.bs_release_resources()
+        except Exception:  # interpreter shutdown: nothing left to report to
+            pass
 
 
 def _check(rc: int) -> int:
@@ -179,11 +200,16 @@ def pinn_forward(net: PinnNet, X: torch.Tensor, out: torch.Tensor | None = None)
 
 
 def pinn_residual_workspace_size(net: PinnNet, n_f: int, n_e: int, n_b: int) -> int:
-    return load_library().pinn_residual_workspace_size(ctypes.byref(net.c()), n_f, n_e, n_b)
+    b = ctypes.c_size_t()
+    _check(load_library().pinn_residual_workspace_size(ctypes.byref(net.c()), n_f, n_e, n_b,
+                                                       ctypes.byref(b)))
+    return b.value
 
 
-def pinn_residual_fwd_bwd(net: PinnNet, p: dict, X_f, X_e, X_b, ws=None, loss3=None, grad=None):
-    """(loss3 [3] = MSE_f, MSE_exp, MSE_b; grad [n_params]) on the GPU."""
+def pinn_residual_fwd_bwd(net: PinnNet, p: dict, X_f, X_e, X_b, ws=None, loss3=None, grad=None,
+                          y_e=None, y_b=None):
+    """(loss3 [3] = MSE_f, MSE_exp, MSE_b; grad [n_params]) on the GPU.  y_e / y_b:
+    value targets of the terminal / boundary sets (None: eqs. (2)-(4))."""
     n_f, n_e, n_b = X_f.shape[0], X_e.shape[0], X_b.shape[0]
     need = pinn_residual_workspace_size(net, n_f, n_e, n_b)
     if ws is None or ws.numel() < need:
@@ -191,9 +217,17 @@ def pinn_residual_fwd_bwd(net: PinnNet, p: dict, X_f, X_e, X_b, ws=None, loss3=N
     loss3 = torch.empty(3, dtype=torch.float32, device="cuda") if loss3 is None else loss3
     grad = torch.empty_like(net.params) if grad is None else grad
     ptr = lambda t: _dev(t, torch.float32, "X") if t.shape[0] else None  # noqa: E731
+
+    def target(y, n, name):
+        if y is None or n == 0:
+            return None
+        if y.numel() != n:
+            raise ValueError(f"{name} must hold one target per point")
+        return _dev(y, torch.float32, name)
     _check(load_library().pinn_residual_fwd_bwd(
-        ctypes.byref(net.c()), ctypes.byref(_params(p)), n_f, ptr(X_f), n_e, ptr(X_e), n_b,
-        ptr(X_b), _dev(loss3, torch.float32, "loss3"), _dev(grad, torch.float32, "grad"),
+        ctypes.byref(net.c()), ctypes.byref(_params(p)), n_f, ptr(X_f), n_e, ptr(X_e),
+        target(y_e, n_e, "y_e"), n_b, ptr(X_b), target(y_b, n_b, "y_b"),
+        _dev(loss3, torch.float32, "loss3"), _dev(grad, torch.float32, "grad"),
         ws.data_ptr(), ws.numel(), _stream()))
     return loss3, grad
 
@@ -209,8 +243,10 @@ class Parareal:
         self._g = _Grid(M, payoff_mode)
         self._s = _Slices(N, fine_steps, coarse_steps)
         lib = load_library()
-        self.ws_bytes = lib.parareal_workspace_size(ctypes.byref(self._g), ctypes.byref(self._s),
-                                                    coarse_kind)
+        b = ctypes.c_size_t()
+        _check(lib.parareal_workspace_size(ctypes.byref(self._g), ctypes.byref(self._s),
+                                           coarse_kind, ctypes.byref(b)))
+        self.ws_bytes = b.value
         self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device="cuda")
         self.U = torch.empty((N + 1, M), dtype=torch.float64, device="cuda")
 
@@ -252,6 +288,21 @@ def bs_tune_reset():
     _check(load_library().bs_tune_reset())
 
 
+def bs_set_divergence_growth(growth: float = BS_DIVERGENCE_GROWTH):
+    """Divergence guard of the solves: stop with BS_ERR_DIVERGED once an
+    iteration's defect exceeds `growth` x the first one (process-wide)."""
+    _check(load_library().bs_set_divergence_growth(float(growth)))
+
+
+def bs_divergence_growth() -> float:
+    return load_library().bs_divergence_growth()
+
+
+def bs_release_resources():
+    """Free the library's per-thread pinned buffers, streams and tables."""
+    _check(load_library().bs_release_resources())
+
+
 def bs_profile_enable(on: bool = True):
     _check(load_library().bs_profile_enable(int(bool(on))))
 
@@ -290,9 +341,9 @@ def parareal_solve_batch(options, coarse_kind: int = COARSE_IE, tol: float = 1e-
         tot += (o["N"] + 1) * o["M"]
     Oa = (ctypes.c_long * n)(*offs)
     lib = load_library()
-    wsb = lib.parareal_batch_workspace_size(n, Pa, Ga, Sa, coarse_kind)
-    if wsb == 0:
-        raise BsError(BS_ERR_ARG, "invalid batch description")
+    b = ctypes.c_size_t()
+    _check(lib.parareal_batch_workspace_size(n, Pa, Ga, Sa, coarse_kind, ctypes.byref(b)))
+    wsb = b.value
     ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     U = torch.empty(tot, dtype=torch.float64, device="cuda")
     it = (ctypes.c_int * n)()

@@ -1,6 +1,7 @@
 // C ABI entry points: argument checks, workspace layout, and the host side of
 // the Parareal iteration (one F launch over all unconverged slices, one sweep
 // launch, one 16-byte read-back of the defect per iteration).
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <vector>
@@ -49,17 +50,20 @@ static int check_slices(const bs_slices* s) {
 }
 
 // Parareal workspace: [result 256 B | Fv N*M | Gold N*M | progress counters
-// 3(N+1)+1 ints | Vt (N+1)*M (network kinds)].  result: [0] defect, [1]
-// non-finite flag, int at [4]: stop flag of the asynchronous solve.
+// 4(N+1)+3 ints | U2 (N+1)*M (grids the one-launch solve may cover) | Vt
+// (N+1)*M (network kinds)].  result: [0] defect, [1] status of the last
+// iteration (0, 1 non-finite, 2 diverged), [2] defect of iteration 1, int at
+// [4]: stop flag of the asynchronous solve.
 struct Workspace {
     double* result;
     double* Fv;
     double* Gold;
-    int* flags;  // ready[N+1], taken[N+1], fdone[N+1], err
+    int* flags;  // ready[N+1], taken[N+1], fdone[N+1], err, decided[N+1], exited, stop_rank
+    double* U2;
     double* Vt;
 };
 
-static int flag_count(int N) { return 3 * (N + 1) + 1; }
+static int flag_count(int N) { return 4 * (N + 1) + 3; }
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -68,6 +72,7 @@ static size_t ws_bytes(int M, int N, int kind) {
     b += align256(sizeof(double) * (size_t)N * M);
     b += align256(sizeof(double) * (size_t)N * M);
     b += align256(sizeof(int) * (size_t)flag_count(N));
+    if (persist_possible(M, N)) b += align256(sizeof(double) * (size_t)(N + 1) * M);
     if (kind != BS_COARSE_IE) b += align256(sizeof(double) * (size_t)(N + 1) * M);
     return b;
 }
@@ -83,9 +88,30 @@ static Workspace ws_layout(void* ws, int M, int N, int kind) {
     p += align256(sizeof(double) * (size_t)N * M);
     w.flags = (int*)p;
     p += align256(sizeof(int) * (size_t)flag_count(N));
+    w.U2 = nullptr;
+    if (persist_possible(M, N)) {
+        w.U2 = (double*)p;
+        p += align256(sizeof(double) * (size_t)(N + 1) * M);
+    }
     w.Vt = (kind != BS_COARSE_IE) ? (double*)p : nullptr;
     return w;
 }
+
+static PipeSync pipe_sync(const Workspace& w, int N) {
+    PipeSync ps{};
+    ps.ready = w.flags;
+    ps.taken = w.flags + (N + 1);
+    ps.fdone = w.flags + 2 * (N + 1);
+    ps.err = w.flags + 3 * (N + 1);
+    return ps;
+}
+
+// Divergence guard (bs_set_divergence_growth).
+static std::atomic<double> g_growth{BS_DIVERGENCE_GROWTH};
+
+// Status of one iteration in the per-iteration record: 0, 1 non-finite, 2 diverged.
+static int record_status(double flag) { return flag == 1.0 ? BS_ERR_NONFINITE
+                                               : flag == 2.0 ? BS_ERR_DIVERGED : BS_OK; }
 
 static int check_parareal(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,
                           int kind, const pinn_net* net, void* ws, size_t ws_size, double* U) {
@@ -175,6 +201,7 @@ static int start_impl(const bs_params* prm, const bs_grid* grid, const bs_slices
     }
     if (!predict) return BS_OK;
     SweepArgs a{o, M, N, 0, sl->coarse_steps, kind, 1, dT, U, w.Fv, w.Gold, w.Vt, w.result};
+    a.growth = INFINITY;
     if (ps) {
         a.ps = *ps;
         a.ps.k = 0;
@@ -189,6 +216,15 @@ using namespace bsp;
 extern "C" {
 
 const char* bs_last_error(void) { return g_err; }
+
+int bs_set_divergence_growth(double growth) {
+    clear_error();
+    BSP_CHECK_ARG(growth > 0 && !std::isnan(growth), "growth must be > 0 (got %g)", growth);
+    g_growth.store(growth);
+    return BS_OK;
+}
+
+double bs_divergence_growth(void) { return g_growth.load(); }
 
 int bs_profile_enable(int on) {
     clear_error();
@@ -247,9 +283,19 @@ int bs_coarse_numeric(const bs_params* prm, const bs_grid* grid, int nsys, const
     return propagate_checked(prm, grid, nsys, tau0, dtau, steps, u_in, u_out, 1.0, stream);
 }
 
-size_t parareal_workspace_size(const bs_grid* grid, const bs_slices* sl, int coarse_kind) {
-    if (!grid || !sl || grid->M < 1 || sl->N < 1) return 0;
-    return ws_bytes(grid->M, sl->N, coarse_kind);
+int parareal_workspace_size(const bs_grid* grid, const bs_slices* sl, int coarse_kind,
+                            size_t* bytes) {
+    clear_error();
+    int rc;
+    BSP_CHECK_ARG(bytes != nullptr, "bytes is NULL");
+    *bytes = 0;
+    if ((rc = check_grid(grid))) return rc;
+    if ((rc = check_slices(sl))) return rc;
+    BSP_CHECK_ARG(coarse_kind == BS_COARSE_IE || coarse_kind == BS_COARSE_PINN ||
+                      coarse_kind == BS_COARSE_PINN_IE,
+                  "unknown coarse kind %d", coarse_kind);
+    *bytes = ws_bytes(grid->M, sl->N, coarse_kind);
+    return BS_OK;
 }
 
 int parareal_start(const bs_params* prm, const bs_grid* grid, const bs_slices* sl, int kind,
@@ -266,11 +312,11 @@ int parareal_start(const bs_params* prm, const bs_grid* grid, const bs_slices* s
 // the sweep on st.  stop/hist/tol: device-side stopping of the asynchronous
 // solve (null for a single synchronous iteration).  ps: progress counters of
 // the overlapped solve (null: fst == st and the launches follow each other).
-// slot: profiling slot.
+// slot: profiling slot.  growth: divergence guard (INFINITY: none).
 static int enqueue_iteration(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,
                              int kind, void* ws, double* U, int k, int* stop, double* hist,
-                             double tol, int slot, const PipeSync* ps, hipStream_t fst,
-                             hipStream_t st) {
+                             double tol, double growth, int slot, const PipeSync* ps,
+                             hipStream_t fst, hipStream_t st) {
     const int M = grid->M, N = sl->N;
     const OptionDev o = make_option(*prm, M);
     const double dT = prm->T / N;
@@ -291,6 +337,7 @@ static int enqueue_iteration(const bs_params* prm, const bs_grid* grid, const bs
     if (prof) BSP_HIP(hipEventRecord(g_prof.ev[4 * slot + 2], st));
     SweepArgs a{o,      M,      N,      first,    sl->coarse_steps, kind, 0, dT, U, w.Fv,
                 w.Gold, w.Vt,   w.result, stop,   hist,             tol,  k,  pk};
+    a.growth = growth;
     if ((rc = launch_sweep(a, st))) return rc;
     if (prof) BSP_HIP(hipEventRecord(g_prof.ev[4 * slot + 3], st));
     return BS_OK;
@@ -306,15 +353,15 @@ static int iterate_impl(const bs_params* prm, const bs_grid* grid, const bs_slic
                         void* ws, double* U, int k, double* defect, int* nonfinite,
                         hipStream_t st) {
     Workspace w = ws_layout(ws, grid->M, sl->N, kind);
-    int rc = enqueue_iteration(prm, grid, sl, kind, ws, U, k, nullptr, nullptr, 0.0, 0, nullptr,
-                               st, st);
+    int rc = enqueue_iteration(prm, grid, sl, kind, ws, U, k, nullptr, nullptr, 0.0, INFINITY, 0,
+                               nullptr, st, st);
     if (rc) return rc;
     double res[2];
     BSP_HIP(hipMemcpyAsync(res, w.result, sizeof(res), hipMemcpyDeviceToHost, st));
     BSP_HIP(hipStreamSynchronize(st));
     if (g_prof.on && (rc = prof_collect(0, iteration_cells(grid, sl, k)))) return rc;
     *defect = res[0];
-    *nonfinite = res[1] != 0.0;
+    *nonfinite = res[1] == 1.0;
     if (*nonfinite) {
         set_error("non-finite value in the Parareal state at iteration %d", k);
         return BS_ERR_NONFINITE;
@@ -359,12 +406,20 @@ static int solve_reserve(int kmax) {
 }
 
 // Side streams and their events on the current device (those made for
-// another device are kept until the process ends).
+// another device are released first).
 static int solve_streams() {
     SolveState& S = t_solve;
     int dev = 0;
     BSP_HIP(hipGetDevice(&dev));
     if (S.dev == dev) return BS_OK;
+    if (S.dev >= 0) {  // made on another device
+        for (int i = 0; i < 2; ++i) {
+            BSP_HIP(hipStreamDestroy(S.side[i]));
+            BSP_HIP(hipEventDestroy(S.side_done[i]));
+        }
+        BSP_HIP(hipEventDestroy(S.go));
+        S.dev = -1;
+    }
     for (int i = 0; i < 2; ++i) {
         BSP_HIP(hipStreamCreateWithFlags(&S.side[i], hipStreamNonBlocking));
         BSP_HIP(hipEventCreateWithFlags(&S.side_done[i], hipEventDisableTiming));
@@ -376,22 +431,20 @@ static int solve_streams() {
 
 // Whole solve in one launch (grids covered by k_parareal_persist): initial
 // state and network grid, then the persistent kernel, which runs the
-// prediction and every iteration and records each iteration's defect in
-// the host-mapped history; the host reads the history once the stream has
-// drained.  The stop flag must already be clear on st.
+// prediction and every iteration, records each iteration's defect in the
+// host-mapped history and leaves the final iterate in U; the host reads the
+// history once the stream has drained.  The stop flag must already be clear
+// on st.
 static int solve_persistent(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,
-                            int kind, double tol, const pinn_net* net, int kmax, void* ws,
-                            double* U, int* iters, double* defect_hist, hipStream_t st) {
+                            int kind, double tol, double growth, const pinn_net* net, int kmax,
+                            void* ws, double* U, int* iters, double* defect_hist,
+                            hipStream_t st) {
     int rc;
     const int M = grid->M, N = sl->N;
     SolveState& S = t_solve;
     for (size_t i = 0; i < 2 * (size_t)(kmax + 1); ++i) S.hist[i] = -1.0;  // not reached
     Workspace w = ws_layout(ws, M, N, kind);
-    PipeSync ps{};
-    ps.ready = w.flags;
-    ps.taken = w.flags + (N + 1);
-    ps.fdone = w.flags + 2 * (N + 1);
-    ps.err = w.flags + 3 * (N + 1);
+    const PipeSync ps = pipe_sync(w, N);
     if ((rc = launch_fill_int(w.flags, flag_count(N), 0, st))) return rc;
     if ((rc = start_impl(prm, grid, sl, kind, net, ws, U, nullptr, st, false))) return rc;
     PersistArgs a{};
@@ -404,13 +457,18 @@ static int solve_persistent(const bs_params* prm, const bs_grid* grid, const bs_
     a.kind = kind;
     a.dT = prm->T / N;
     a.tol = tol;
+    a.growth = growth;
     a.U = U;
+    a.U2 = w.U2;
     a.Fv = w.Fv;
     a.Gold = w.Gold;
     a.Vt = w.Vt;
     a.result = w.result;
     a.stop = reinterpret_cast<int*>(w.result + 4);
     a.hist = S.hist_dev;
+    a.decided = w.flags + 3 * (N + 1) + 1;
+    a.exited = a.decided + (N + 1);
+    a.stop_rank = a.exited + 1;
     a.ps = ps;
     const bool prof = g_prof.on;
     if (prof) BSP_HIP(hipEventRecord(g_prof.ev[0], st));
@@ -427,18 +485,16 @@ static int solve_persistent(const bs_params* prm, const bs_grid* grid, const bs_
     const volatile double* hist = S.hist;
     int status = BS_NOT_CONVERGED, last = 0;
     for (int j = 1; j <= kmax; ++j) {
-        const double d = hist[2 * j], bad = hist[2 * j + 1];
+        const double d = hist[2 * j], flag = hist[2 * j + 1];
         if (d < 0.0) break;  // not reached
         if (defect_hist) defect_hist[j - 1] = d;
         last = j;
-        if (bad != 0.0) {
-            status = BS_ERR_NONFINITE;
-            break;
-        }
+        if ((status = record_status(flag)) != BS_OK) break;
         if (d <= tol || j == N) {
             status = BS_OK;
             break;
         }
+        status = BS_NOT_CONVERGED;
     }
     *iters = last;
     if (prof) {
@@ -450,6 +506,8 @@ static int solve_persistent(const bs_params* prm, const bs_grid* grid, const bs_
     }
     if (status == BS_ERR_NONFINITE)
         set_error("non-finite value in the Parareal state at iteration %d", last);
+    else if (status == BS_ERR_DIVERGED)
+        set_error("Parareal diverging: defect of iteration %d above %g x the first", last, growth);
     return status;
 }
 
@@ -478,6 +536,7 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
     hipStream_t st = (hipStream_t)stream;
     const int N = sl->N;
     const int kmax = max_iter < N ? max_iter : N;
+    const double growth = g_growth.load();
     *iters = 0;
     if ((rc = solve_reserve(kmax))) return rc;
     if (g_prof.on && (rc = prof_reserve(kmax))) return rc;
@@ -487,8 +546,8 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
     int* stop = reinterpret_cast<int*>(w.result + 4);
     if ((rc = launch_set_int(stop, 0, st))) return rc;
     if (persist_capable(grid->M, N))
-        return solve_persistent(prm, grid, sl, kind, tol, net, kmax, ws, U, iters, defect_hist,
-                                st);
+        return solve_persistent(prm, grid, sl, kind, tol, growth, net, kmax, ws, U, iters,
+                                defect_hist, st);
 
     // Overlapped iterations (grids the one-block sweep and the per-system
     // fine kernel cover): the fine launch of iteration k runs on a side
@@ -503,10 +562,7 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
     PipeSync ps{};
     if (pipe) {
         if ((rc = solve_streams())) return rc;
-        ps.ready = w.flags;
-        ps.taken = w.flags + (N + 1);
-        ps.fdone = w.flags + 2 * (N + 1);
-        ps.err = w.flags + 3 * (N + 1);
+        ps = pipe_sync(w, N);
         if ((rc = launch_fill_int(w.flags, flag_count(N), 0, st))) return rc;
         BSP_HIP(hipEventRecord(S.go, st));
         for (int i = 0; i < 2; ++i) BSP_HIP(hipStreamWaitEvent(S.side[i], S.go, 0));
@@ -520,23 +576,21 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
     const volatile double* hist = S.hist;
     int status = BS_NOT_CONVERGED, last = 0, enq = 0;
     auto decide = [&](int j) {
-        const double d = hist[2 * j], bad = hist[2 * j + 1];
+        const double d = hist[2 * j];
         if (defect_hist) defect_hist[j - 1] = d;
         last = j;
-        if (bad != 0.0) {
-            status = BS_ERR_NONFINITE;
-            return true;
-        }
+        if ((status = record_status(hist[2 * j + 1])) != BS_OK) return true;
         if (d <= tol || j == N) {
             status = BS_OK;
             return true;
         }
-        return j == kmax;  // BS_NOT_CONVERGED
+        status = BS_NOT_CONVERGED;
+        return j == kmax;
     };
     bool decided = false;
     for (int k = 1; k <= kmax && !decided; ++k) {
-        if ((rc = enqueue_iteration(prm, grid, sl, kind, ws, U, k, stop, S.hist_dev, tol, k - 1,
-                                    pipe ? &ps : nullptr, pipe ? S.side[k & 1] : st, st)))
+        if ((rc = enqueue_iteration(prm, grid, sl, kind, ws, U, k, stop, S.hist_dev, tol, growth,
+                                    k - 1, pipe ? &ps : nullptr, pipe ? S.side[k & 1] : st, st)))
             return rc;
         BSP_HIP(hipEventRecord(S.done[k], st));
         enq = k;
@@ -570,7 +624,36 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
     }
     if (status == BS_ERR_NONFINITE)
         set_error("non-finite value in the Parareal state at iteration %d", last);
+    else if (status == BS_ERR_DIVERGED)
+        set_error("Parareal diverging: defect of iteration %d above %g x the first", last, growth);
     return status;
+}
+
+int bs_release_resources(void) {
+    clear_error();
+    SolveState& S = t_solve;
+    if (S.hist) BSP_HIP(hipHostFree(S.hist));
+    S.hist = S.hist_dev = nullptr;
+    S.cap = 0;
+    for (hipEvent_t e : S.done) BSP_HIP(hipEventDestroy(e));
+    S.done.clear();
+    if (S.dev >= 0) {
+        for (int i = 0; i < 2; ++i) {
+            BSP_HIP(hipStreamDestroy(S.side[i]));
+            BSP_HIP(hipEventDestroy(S.side_done[i]));
+            S.side[i] = nullptr;
+            S.side_done[i] = nullptr;
+        }
+        BSP_HIP(hipEventDestroy(S.go));
+        S.go = nullptr;
+        S.dev = -1;
+    }
+    for (hipEvent_t e : g_prof.ev) BSP_HIP(hipEventDestroy(e));
+    g_prof.ev.clear();
+    g_prof.on = false;
+    int rc;
+    if ((rc = release_large_tables())) return rc;
+    return release_batch_resources();
 }
 
 }  // extern "C"

@@ -80,7 +80,8 @@ __global__ __launch_bounds__(T) void k_batch_sweep(const BatchOpt* __restrict__ 
                                                    BatchState* __restrict__ state,
                                                    const int* __restrict__ list,
                                                    const int* __restrict__ kglob, int predict,
-                                                   int kind, double tol, int max_iter,
+                                                   int kind, double tol, double growth,
+                                                   int max_iter,
                                                    double* __restrict__ U, const double* Fv,
                                                    double* Gold, const double* Vt,
                                                    int* __restrict__ active) {
@@ -98,15 +99,19 @@ __global__ __launch_bounds__(T) void k_batch_sweep(const BatchOpt* __restrict__ 
     double dmax = 0.0;
     int bad = 0;
     sweep_slices<T, MC>(S, b.o, b.M, b.N, n0, b.coarse_steps, kind, predict != 0, b.dT,
-                        U + b.u_off, Fv + b.w_off, Gold + b.w_off, Vt ? Vt + b.vt_off : nullptr,
+                        U + b.u_off, U + b.u_off, Fv + b.w_off, Gold + b.w_off,
+                        Vt ? Vt + b.vt_off : nullptr,
                         lds, ftab, dmax, bad);
     if (predict) return;
     block_defect<T>(dmax, bad, lds);
     if (threadIdx.x == 0) {
+        if (k == 1) st.first = dmax;
+        // 1 non-finite; 2 diverged (the defect grew by `growth` over iteration 1's)
+        const int status = bad ? 1 : (k >= 2 && dmax > growth * st.first) ? 2 : 0;
         st.defect = dmax;
         st.iters = k;
-        st.bad = bad;
-        if (bad || dmax <= tol || k >= b.N || k >= max_iter) {
+        st.bad = status;
+        if (status || dmax <= tol || k >= b.N || k >= max_iter) {
             st.done = 1;
             atomicSub(active, 1);
         }
@@ -230,21 +235,40 @@ constexpr int kMaxClasses = 16;
 struct ClassStreams {
     int dev = -1;
     hipStream_t s[kMaxClasses] = {};
+    hipStream_t own = nullptr;  // stands in for the legacy default stream under capture
     hipEvent_t fork[2] = {}, join[2][kMaxClasses] = {};
 };
 static thread_local ClassStreams t_cls;
+
+int release_batch_resources() {
+    ClassStreams& C = t_cls;
+    if (C.dev < 0) return BS_OK;
+    for (int i = 0; i < kMaxClasses; ++i) {
+        BSP_HIP(hipStreamDestroy(C.s[i]));
+        for (int ph = 0; ph < 2; ++ph) BSP_HIP(hipEventDestroy(C.join[ph][i]));
+    }
+    for (int ph = 0; ph < 2; ++ph) BSP_HIP(hipEventDestroy(C.fork[ph]));
+    BSP_HIP(hipStreamDestroy(C.own));
+    C = ClassStreams{};
+    return BS_OK;
+}
 
 static int class_streams() {
     ClassStreams& C = t_cls;
     int dev = 0;
     BSP_HIP(hipGetDevice(&dev));
     if (C.dev == dev) return BS_OK;
+    if (C.dev >= 0) {  // made on another device: release them first
+        int rc = release_batch_resources();
+        if (rc) return rc;
+    }
     for (int i = 0; i < kMaxClasses; ++i) {
         BSP_HIP(hipStreamCreateWithFlags(&C.s[i], hipStreamNonBlocking));
         for (int ph = 0; ph < 2; ++ph)
             BSP_HIP(hipEventCreateWithFlags(&C.join[ph][i], hipEventDisableTiming));
     }
     for (int ph = 0; ph < 2; ++ph) BSP_HIP(hipEventCreateWithFlags(&C.fork[ph], hipEventDisableTiming));
+    BSP_HIP(hipStreamCreateWithFlags(&C.own, hipStreamNonBlocking));
     C.dev = dev;
     return BS_OK;
 }
@@ -282,13 +306,13 @@ static int launch_fine_class(TriShape sh, int nitems, const BatchWs& w, const FI
 }
 
 static int launch_sweep_class(TriShape sh, int nopt, const BatchWs& w, const int* list,
-                              int predict, int kind, double tol, int max_iter, double* U,
-                              hipStream_t st) {
+                              int predict, int kind, double tol, double growth, int max_iter,
+                              double* U, hipStream_t st) {
 #define BSP_CASE(T_, MC_)                                                                      \
     if (sh.T == T_ && sh.MC == MC_) {                                                          \
         hipLaunchKernelGGL((k_batch_sweep<T_, MC_>), dim3(nopt), dim3(T_), 0, st, w.opts,     \
-                           w.state, list, w.counters, predict, kind, tol, max_iter, U, w.Fv,  \
-                           w.Gold, w.Vt, w.counters + 1);                                      \
+                           w.state, list, w.counters, predict, kind, tol, growth, max_iter,   \
+                           U, w.Fv, w.Gold, w.Vt, w.counters + 1);                             \
         BSP_LAUNCHED();                                                                        \
         return BS_OK;                                                                          \
     }
@@ -318,16 +342,25 @@ static int batch_checks(int n_opt, const bs_params* prm, const bs_grid* grids,
     return BS_OK;
 }
 
-extern "C" size_t parareal_batch_workspace_size(int n_opt, const bs_params* prm,
-                                                const bs_grid* grids, const bs_slices* sl,
-                                                int coarse_kind) {
-    if (n_opt < 1 || !prm || !grids || !sl) return 0;
+extern "C" int parareal_batch_workspace_size(int n_opt, const bs_params* prm,
+                                             const bs_grid* grids, const bs_slices* sl,
+                                             int coarse_kind, size_t* bytes) {
+    clear_error();
+    BSP_CHECK_ARG(bytes != nullptr, "bytes is NULL");
+    *bytes = 0;
+    BSP_CHECK_ARG(n_opt >= 1, "n_opt must be >= 1");
+    BSP_CHECK_ARG(prm && grids && sl, "host option arrays must be non-NULL");
+    BSP_CHECK_ARG(coarse_kind == BS_COARSE_IE || coarse_kind == BS_COARSE_PINN ||
+                      coarse_kind == BS_COARSE_PINN_IE,
+                  "unknown coarse kind %d", coarse_kind);
     std::vector<long> offs(n_opt, 0);
     BatchPlan P;
-    if (make_plan(n_opt, prm, grids, sl, offs.data(), coarse_kind != BS_COARSE_IE, P)) return 0;
+    int rc = make_plan(n_opt, prm, grids, sl, offs.data(), coarse_kind != BS_COARSE_IE, P);
+    if (rc) return rc;
     long n_items = 0;
     for (auto& v : P.fine_items) n_items += (long)v.size();
-    return batch_layout(P, n_items, coarse_kind != BS_COARSE_IE, nullptr).bytes;
+    *bytes = batch_layout(P, n_items, coarse_kind != BS_COARSE_IE, nullptr).bytes;
+    return BS_OK;
 }
 
 extern "C" int parareal_solve_batch(int n_opt, const bs_params* prm, const bs_grid* grids,
@@ -351,13 +384,13 @@ extern "C" int parareal_solve_batch(int n_opt, const bs_params* prm, const bs_gr
         return BS_ERR_WORKSPACE;
     }
     hipStream_t st = (hipStream_t)stream;
+    const double growth = bs_divergence_growth();
     // The legacy default stream cannot be captured: a graph run on it uses a
-    // library stream instead (the call is synchronous either way).
-    static hipStream_t own = nullptr;
+    // library stream of this thread instead (the call is synchronous either way).
     if (use_graph && st == nullptr) {
         BSP_HIP(hipDeviceSynchronize());
-        if (!own) BSP_HIP(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
-        st = own;
+        if ((rc = class_streams())) return rc;
+        st = t_cls.own;
     }
 
     // tables -> device (one staging copy)
@@ -392,7 +425,7 @@ extern "C" int parareal_solve_batch(int n_opt, const bs_params* prm, const bs_gr
     if ((rc = class_streams())) return rc;
     rc = run_phase(1, (int)P.sweep_cls.size(), st, [&](int c, hipStream_t s) {
         return launch_sweep_class(P.sweep_cls[c], (int)P.sweep_lists[c].size(), w,
-                                  w.lists + list_off[c], 1, kind, tol, max_iter, U, s);
+                                  w.lists + list_off[c], 1, kind, tol, growth, max_iter, U, s);
     });
     if (rc) return rc;
     hipLaunchKernelGGL(k_batch_set, dim3(1), dim3(1), 0, st, w.counters, w.counters + 1, 1, n_opt);
@@ -410,7 +443,8 @@ extern "C" int parareal_solve_batch(int n_opt, const bs_params* prm, const bs_gr
         if (r) return r;
         r = run_phase(1, (int)P.sweep_cls.size(), st, [&](int c, hipStream_t s) {
             return launch_sweep_class(P.sweep_cls[c], (int)P.sweep_lists[c].size(), w,
-                                      w.lists + list_off[c], 0, kind, tol, max_iter, U, s);
+                                      w.lists + list_off[c], 0, kind, tol, growth, max_iter,
+                                      U, s);
         });
         if (r) return r;
         hipLaunchKernelGGL(k_batch_tick, dim3(1), dim3(1), 0, st, w.counters);
@@ -459,13 +493,19 @@ extern "C" int parareal_solve_batch(int n_opt, const bs_params* prm, const bs_gr
     std::vector<BatchState> out(n_opt);
     BSP_HIP(hipMemcpyAsync(out.data(), w.state, sizeof(BatchState) * n_opt, hipMemcpyDeviceToHost, st));
     BSP_HIP(hipStreamSynchronize(st));
+    // Worst outcome over the options: non-finite, then diverged, then not converged.
     int status = BS_OK;
     for (int i = 0; i < n_opt; ++i) {
         iters[i] = out[i].iters;
         if (defects) defects[i] = out[i].defect;
-        if (out[i].bad) {
-            set_error("non-finite value in option %d", i);
+        if (out[i].bad == 1) {
+            if (status != BS_ERR_NONFINITE) set_error("non-finite value in option %d", i);
             status = BS_ERR_NONFINITE;
+        } else if (out[i].bad == 2) {
+            if (status != BS_ERR_NONFINITE && status != BS_ERR_DIVERGED)
+                set_error("option %d diverging: defect of iteration %d above %g x the first", i,
+                          out[i].iters, growth);
+            if (status != BS_ERR_NONFINITE) status = BS_ERR_DIVERGED;
         } else if (status == BS_OK && !(out[i].defect <= tol) && out[i].iters < P.opts[i].N) {
             status = BS_NOT_CONVERGED;
         }

@@ -231,34 +231,45 @@ struct SweepArgs {
     const double* Fv;              // [N][M]
     double* Gold;                  // [N][M]
     const double* Vt;              // [N+1][M] or nullptr
-    double* result;                // [0] defect, [1] non-finite flag (as double)
+    double* result;                // [0] defect, [1] status, [2] defect of iteration 1
     // Device-side stopping (asynchronous solve; all three may be null):
     // the sweep returns at once while *stop is set, and on finishing
-    // iteration k it writes hist[2k] = defect, hist[2k+1] = non-finite and
-    // sets *stop when the iteration is the last one (defect <= tol or
-    // non-finite).
+    // iteration k it writes hist[2k] = defect, hist[2k+1] = status (0; 1
+    // non-finite; 2 diverged: k >= 2 and defect > growth x the defect of
+    // iteration 1) and sets *stop when the iteration is the last one
+    // (defect <= tol or status != 0).
     int* stop;
     double* hist;
     double tol;
     int k;
     PipeSync ps;  // overlapped solve (ps.ready null: not overlapped)
+    double growth = __builtin_inf();  // divergence guard (infinite: none)
 };
 int launch_sweep(const SweepArgs& a, hipStream_t stream);
 
-// Whole overlapped solve in one cooperative launch (see k_parareal_persist).
+// Whole overlapped solve in one launch (see k_parareal_persist).  Iterate k
+// lives in U (k even) or U2 (k odd); the launch leaves the last iterate in U.
 struct PersistArgs {
     OptionDev o;
     int M, N, kmax, fine_steps, coarse_steps, kind, nfb, nsb;
     double dT, tol;
     double* U;
+    double* U2;
     double* Fv;
     double* Gold;
     const double* Vt;
     double* result;
     int* stop;
-    double* hist;  // host-mapped record [2 (kmax+1)]
+    double* hist;     // host-mapped record [2 (kmax+1)]
+    int* decided;     // [kmax+1]: the sweep of iteration k has recorded its defect
+    int* exited;      // blocks that have finished
+    int* stop_rank;   // kmax + 1 - (first iteration that met the stopping rule), 0: none
     PipeSync ps;
+    double growth;    // divergence guard, as in SweepArgs
 };
+// The one-launch solve can cover this problem size (block shapes aside).
+constexpr int kPersistMaxN = 512, kPersistMaxM = 1024;
+inline bool persist_possible(int M, int N) { return M <= kPersistMaxM && N <= kPersistMaxN; }
 bool persist_capable(int M, int N);
 int launch_parareal_persist(const PersistArgs& a, hipStream_t stream);
 int launch_set_int(int* p, int v, hipStream_t stream);  // *p = v in stream order
@@ -282,8 +293,8 @@ struct BatchOpt {
     long vt_off;  // option's network grid (N+1)*M in the packed grid array
 };
 struct BatchState {
-    int done, iters, bad, pad;
-    double defect;
+    int done, iters, bad, pad;  // bad: 1 non-finite, 2 diverged (as SweepArgs' status)
+    double defect, first;       // last defect, defect of iteration 1
 };
 struct BatchTile {
     int opt, pad;
@@ -291,6 +302,8 @@ struct BatchTile {
 };
 
 int check_net(const pinn_net* net);
+int release_large_tables();     // coefficient tables of the large-grid solver, this device
+int release_batch_resources();  // class streams and events of this thread
 long net_param_count(const pinn_net& net);
 
 }  // namespace bsp

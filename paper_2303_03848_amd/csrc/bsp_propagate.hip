@@ -75,16 +75,29 @@ int launch_set_int(int* p, int v, hipStream_t stream) {
     return BS_OK;
 }
 
+// Status of iteration k with defect dmax: 1 non-finite, 2 diverged (k >= 2
+// and the defect above growth x first, the defect of iteration 1), else 0.
+__device__ __forceinline__ int sweep_status(int k, double dmax, int bad, double first,
+                                            double growth) {
+    if (bad) return 1;
+    return (k >= 2 && dmax > growth * first) ? 2 : 0;
+}
+
 // Iteration record of the asynchronous solve (thread 0, after block_defect).
-__device__ __forceinline__ void sweep_record(const SweepArgs& a, double dmax, int bad) {
+// result[2] holds the defect of iteration 1 (written by that iteration's
+// sweep, which has completed when k >= 2).  Returns the status.
+__device__ __forceinline__ int sweep_record(const SweepArgs& a, double dmax, int bad) {
+    if (a.k == 1) a.result[2] = dmax;
+    const int status = sweep_status(a.k, dmax, bad, a.result[2], a.growth);
     a.result[0] = dmax;
-    a.result[1] = bad ? 1.0 : 0.0;
+    a.result[1] = (double)status;
     if (a.hist) {  // host memory: visible to the host once the launch completes
         a.hist[2 * a.k] = dmax;
-        a.hist[2 * a.k + 1] = bad ? 1.0 : 0.0;
+        a.hist[2 * a.k + 1] = (double)status;
         __threadfence_system();
     }
-    if (a.stop && (bad || dmax <= a.tol)) *a.stop = 1;
+    if (a.stop && (status || dmax <= a.tol)) *a.stop = 1;
+    return status;
 }
 
 // One block per system.  PIPE (overlapped Parareal solve): system sys is
@@ -167,7 +180,7 @@ __global__ __launch_bounds__(T) void k_sweep(SweepArgs a) {
     int bad = 0;
     const PipeSync ps = a.ps;
     if (!sweep_slices<T, MC>(S, a.o, a.M, a.N, a.n0, a.coarse_steps, a.kind, a.predict != 0, a.dT,
-                             a.U, a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad, ps,
+                             a.U, a.U, a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad, ps,
                              ps.ready != nullptr, a.stop, &pslot))
         return;
     if (!a.predict) {
@@ -189,9 +202,20 @@ __global__ __launch_bounds__(T) void k_sweep(SweepArgs a) {
 // instead of waiting for it to end.  Every hand-off goes through the
 // progress counters of PipeSync; the iterates are those of the
 // launch-after-launch iteration with the same block shapes.
+//
+// Two state buffers: iterate k is written to U (k even) or U2 (k odd), so the
+// sweep of iteration k+1, which runs while iteration k's defect is still
+// being reduced, never touches iterate k.  The sweep of iteration k writes
+// over iterate k-2, and first waits until iteration k-2 has been decided (if
+// the solve stopped there or earlier it returns without writing).  The last
+// block to finish copies the final iterate to U when it lies in U2.
 template <int MCF>
 constexpr int persist_fine_lds() {  // doubles per fine wavefront
     return 2 * kForceChunk + 64 * MCF;
+}
+
+__device__ __forceinline__ double* persist_buf(const PersistArgs& a, int k) {
+    return (k & 1) ? a.U2 : a.U;
 }
 
 template <int MCF>
@@ -212,7 +236,7 @@ __device__ __forceinline__ void persist_fine(const PersistArgs& a, double* smem)
     for (int k = 1; k <= klast; ++k) {
         if (!pipe_wait_wave(a.ps, a.ps.ready + n, k, a.stop)) return;
         double V[MCF];
-        load_system<64, MCF, true>(a.U + (long)n * a.M, a.M, V, stage);
+        load_system<64, MCF, true>(persist_buf(a, k - 1) + (long)n * a.M, a.M, V, stage);
         if ((threadIdx.x & 63) == 0)
             __hip_atomic_store(a.ps.taken + n, k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (!theta_steps<64, MCF, true, BlockTri<64, MCF>, true, true>(
@@ -237,17 +261,28 @@ __device__ __forceinline__ void persist_sweep(const PersistArgs& a, int j, doubl
         const int n0 = predict ? 0 : min(k - 1, a.N - 1);
         PipeSync ps = a.ps;
         ps.k = k;
+        if (k >= 2) {
+            // Uout holds iterate k-2: keep it until iteration k-2 is decided
+            if (!pipe_wait(ps, a.decided + k - 2, 1, a.stop, pslot)) return;
+            // the solve may have stopped at k-2 or earlier: the same decision
+            // in every thread
+            if (__syncthreads_or(pipe_load(a.stop) != 0)) return;
+        }
         // the sweep's first state U[n0] (iterate k; for k >= 1 written by the
         // sweep of iteration k-1)
         if (!predict && !pipe_wait(ps, ps.ready + n0, k, a.stop, pslot)) return;
         double dmax = 0.0;
         int bad = 0;
+        const double* Uin = persist_buf(a, predict ? 0 : k - 1);
+        double* Uout = persist_buf(a, k);
         if (!sweep_slices<T, MCS>(S, a.o, a.M, a.N, n0, a.coarse_steps, a.kind, predict, a.dT,
-                                  a.U, a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad, ps, true,
-                                  a.stop, pslot))
+                                  Uin, Uout, a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad, ps, true,
+                                  a.stop, pslot, predict ? 0 : 1))
             return;
         if (!predict) {
             block_defect<T>(dmax, bad, lds);
+            // the guard compares with iteration 1's defect: recorded by then
+            if (k >= 2 && !pipe_wait(ps, a.decided + 1, 1, a.stop, pslot)) return;
             if (threadIdx.x == 0) {
                 SweepArgs sa{};
                 sa.result = a.result;
@@ -255,9 +290,14 @@ __device__ __forceinline__ void persist_sweep(const PersistArgs& a, int j, doubl
                 sa.hist = a.hist;
                 sa.tol = a.tol;
                 sa.k = k;
+                sa.growth = a.growth;
+                const double first = k == 1 ? dmax : a.result[2];
+                if (sweep_status(k, dmax, bad, first, a.growth) || dmax <= a.tol)
+                    atomicMax(a.stop_rank, a.kmax + 1 - k);  // before the stop flag
                 sweep_record(sa, dmax, bad);
             }
         }
+        pipe_signal(a.decided + k, 1);  // the prediction too: the sweep of k = 2 waits for it
     }
 }
 
@@ -270,14 +310,44 @@ __global__ __launch_bounds__(256) void k_parareal_persist(PersistArgs a) {
         persist_fine<MCF>(a, smem);
     else
         persist_sweep<MCS>(a, (int)blockIdx.x - a.nfb, smem, &pslot);
+    // every role has returned; the last block to get here moves the final
+    // iterate to U if it lies in U2 (no block writes either buffer any more)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const int before = __hip_atomic_fetch_add(a.exited, 1, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        pslot = before == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!pslot) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int rank = pipe_load(a.stop_rank);
+    const int kfinal = rank ? a.kmax + 1 - rank : a.kmax;
+    if (!(kfinal & 1)) return;
+    const long total = (long)(a.N + 1) * a.M;
+    for (long i = threadIdx.x; i < total; i += blockDim.x) a.U[i] = a.U2[i];
 }
-
-constexpr int kPersistMaxN = 512;
 
 bool persist_capable(int M, int N) {
     const TriShape f = shape_for(0, M), w = shape_for(1, M);
-    return N <= kPersistMaxN && f.T == 64 && (f.MC == 2 || f.MC == 4 || f.MC == 8 ||
-                                              f.MC == 16) && w.T == 256 && w.MC == 4;
+    return persist_possible(M, N) && f.T == 64 &&
+           (f.MC == 2 || f.MC == 4 || f.MC == 8 || f.MC == 16) && w.T == 256 && w.MC == 4;
+}
+
+// Resident-block capacity of one kernel on the current device (blocks per
+// compute unit x compute units), queried once per device.
+static int resident_blocks(const void* fn, int threads, int slot) {
+    static int cache[16][4] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 0;
+    if (cache[dev][slot]) return cache[dev][slot];
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    cache[dev][slot] = per_cu * cus;
+    return cache[dev][slot];
 }
 
 int launch_parareal_persist(const PersistArgs& in, hipStream_t stream) {
@@ -288,18 +358,32 @@ int launch_parareal_persist(const PersistArgs& in, hipStream_t stream) {
     }
     a.nfb = (a.N + 3) / 4;
     a.nsb = min(3, a.kmax + 1);
-    void* args[] = {&a};
     const dim3 grid(a.nfb + a.nsb), block(256);
     const TriShape f = shape_for(0, a.M);
     const void* fn = nullptr;
+    int slot = 0;
     switch (f.MC) {
-        case 2: fn = (const void*)k_parareal_persist<2, 4>; break;
-        case 4: fn = (const void*)k_parareal_persist<4, 4>; break;
-        case 8: fn = (const void*)k_parareal_persist<8, 4>; break;
-        default: fn = (const void*)k_parareal_persist<16, 4>; break;
+        case 2: fn = (const void*)k_parareal_persist<2, 4>; slot = 0; break;
+        case 4: fn = (const void*)k_parareal_persist<4, 4>; slot = 1; break;
+        case 8: fn = (const void*)k_parareal_persist<8, 4>; slot = 2; break;
+        default: fn = (const void*)k_parareal_persist<16, 4>; slot = 3; break;
     }
-    // co-resident blocks are required (they wait on each other)
-    BSP_HIP(hipLaunchCooperativeKernel(fn, grid, block, args, 0, stream));
+    // The blocks wait on each other, so all of them must be resident at once:
+    // an ordinary launch whose grid fits the device's resident capacity (one
+    // block per compute unit here).  Waits that do not end (another kernel
+    // holding the compute units) end at the time limit with an error.
+    const int cap = resident_blocks(fn, 256, slot);
+    if ((int)grid.x > cap) {
+        set_error("one-launch solve needs %u resident blocks, the device holds %d", grid.x, cap);
+        return BS_ERR_HIP;
+    }
+    switch (f.MC) {
+        case 2: hipLaunchKernelGGL((k_parareal_persist<2, 4>), grid, block, 0, stream, a); break;
+        case 4: hipLaunchKernelGGL((k_parareal_persist<4, 4>), grid, block, 0, stream, a); break;
+        case 8: hipLaunchKernelGGL((k_parareal_persist<8, 4>), grid, block, 0, stream, a); break;
+        default: hipLaunchKernelGGL((k_parareal_persist<16, 4>), grid, block, 0, stream, a); break;
+    }
+    BSP_LAUNCHED();
     return BS_OK;
 }
 
@@ -343,7 +427,7 @@ __global__ __launch_bounds__(T) void k_large_sweep(SweepArgs a, const double* __
     double dmax = 0.0;
     int bad = 0;
     sweep_slices<T, MC>(S, a.o, a.M, a.N, a.n0, a.coarse_steps, a.kind, a.predict != 0, a.dT, a.U,
-                        a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad);
+                        a.U, a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad);
     if (!a.predict) {
         block_defect<T>(dmax, bad, lds);
         if (threadIdx.x == 0) sweep_record(a, dmax, bad);
@@ -356,6 +440,16 @@ __global__ __launch_bounds__(T) void k_large_sweep(SweepArgs a, const double* __
 // not overlap in time (they are ordered on one stream in normal use).
 constexpr long kLargeTab = 5L * 32 * 512, kLargePtab = (long)kLgP * 512;
 static double* g_large[16] = {nullptr};
+
+int release_large_tables() {
+    int dev = 0;
+    BSP_HIP(hipGetDevice(&dev));
+    if (dev >= 0 && dev < 16 && g_large[dev]) {
+        BSP_HIP(hipFree(g_large[dev]));
+        g_large[dev] = nullptr;
+    }
+    return BS_OK;
+}
 
 static int large_tables(int slot, double** tab, double** ptab) {
     int dev = 0;

@@ -107,6 +107,7 @@ struct Points {
     int nf, ne, nb, n_in;
     float sigma, r;   // used when n_in == 2
     int is_put;
+    const float *ye, *yb;  // value targets of the terminal / boundary sets, or null
 };
 
 __device__ __forceinline__ const float* point_row(const Points& P, long i) {
@@ -323,14 +324,16 @@ __global__ void k_res_head(const float* __restrict__ prm, long off_wo, long off_
         g3 = -0.5f * sig * sig * xx * xx * df;
     } else if (i < P.nf + P.ne) {
         const float xx = x[1];
-        const float y = P.is_put ? fmaxf(1.0f - xx, 0.0f) : fmaxf(xx - 1.0f, 0.0f);
+        const float y = P.ye ? P.ye[i - P.nf]
+                             : (P.is_put ? fmaxf(1.0f - xx, 0.0f) : fmaxf(xx - 1.0f, 0.0f));
         lc = (v - y) * (v - y);
         g0 = 2.0f * (v - y) / (float)P.ne;
     } else {
         const float tau = x[0], xx = x[1];
         const float disc = expf(-rr * tau);
         const bool lower = xx == 0.0f;
-        const float y = P.is_put ? (lower ? disc : 0.0f) : (lower ? 0.0f : xx - disc);
+        const float y = P.yb ? P.yb[i - P.nf - P.ne]
+                             : (P.is_put ? (lower ? disc : 0.0f) : (lower ? 0.0f : xx - disc));
         lc = (v - y) * (v - y);
         g0 = 2.0f * (v - y) / (float)P.nb;
     }
@@ -583,14 +586,22 @@ static dim3 grid_for(long work, int block) { return dim3((unsigned)((work + bloc
 
 using namespace bsp;
 
-extern "C" size_t pinn_residual_workspace_size(const pinn_net* net, int n_f, int n_e, int n_b) {
-    if (!net || net->width <= 0 || net->depth < 1 || n_f < 0 || n_e < 0 || n_b < 0) return 0;
-    return res_layout(*net, (long)n_f + n_e + n_b, nullptr).bytes;
+extern "C" int pinn_residual_workspace_size(const pinn_net* net, int n_f, int n_e, int n_b,
+                                            size_t* bytes) {
+    clear_error();
+    BSP_CHECK_ARG(bytes != nullptr, "bytes is NULL");
+    *bytes = 0;
+    int rc = check_net(net);
+    if (rc) return rc;
+    BSP_CHECK_ARG(n_f >= 0 && n_e >= 0 && n_b >= 0, "point counts must be >= 0");
+    *bytes = res_layout(*net, (long)n_f + n_e + n_b, nullptr).bytes;
+    return BS_OK;
 }
 
 extern "C" int pinn_residual_fwd_bwd(const pinn_net* net, const bs_params* prm, int n_f,
-                                     const float* X_f, int n_e, const float* X_e, int n_b,
-                                     const float* X_b, float* loss3, float* grad, void* ws,
+                                     const float* X_f, int n_e, const float* X_e,
+                                     const float* y_e, int n_b, const float* X_b,
+                                     const float* y_b, float* loss3, float* grad, void* ws,
                                      size_t ws_bytes, void* stream) {
     clear_error();
     int rc = check_net(net);
@@ -614,7 +625,7 @@ extern "C" int pinn_residual_fwd_bwd(const pinn_net* net, const bs_params* prm, 
     const long np = w.n_pad, plane = np * W, work = np * W;
     const float* P0 = net->params;
     Points P{X_f, X_e, X_b, n_f, n_e, n_b, net->n_in, (float)prm->sigma, (float)prm->r,
-             prm->is_put};
+             prm->is_put, y_e, y_b};
     const bool mfma = net->precision == BS_PREC_BF16;
     auto cache = [&](int l) { return w.cache + (size_t)(l - 1) * 4 * plane; };
 

@@ -298,8 +298,9 @@ __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
 // p*MC + MC-1), go through shared memory in rows of MC + 1 doubles (the pad
 // keeps both access orders free of bank conflicts); consecutive threads then
 // read and write consecutive nodes of Fv, Gold and U; the new values come
-// back to chunk order in g (zero past the grid).  predict: U[n+1] = Gold[n]
-// = g and g is left as it is.  A pass covers the chunks of
+// back to chunk order in g (zero past the grid); uo1 holds the old values of
+// U[n+1], un1 receives the new ones.  predict: U[n+1] = Gold[n] = g and g is
+// left as it is.  A pass covers the chunks of
 // staged_chunks<T, MC>() threads (at most 4096 nodes), so the staging area is
 // staged_doubles<T, MC>() doubles of `stage`, which the forcing tables may
 // share (they are refilled by every run of steps; barriers separate the two).
@@ -323,8 +324,9 @@ constexpr int sweep_smem_doubles() {
 template <int T, int MC>
 __device__ __forceinline__ void correct_staged(double (&g)[MC], int M, bool predict,
                                                const double* __restrict__ fv,
-                                               double* __restrict__ go, double* __restrict__ un1,
-                                               double* stage, double& dmax, int& bad) {
+                                               double* __restrict__ go, const double* uo1,
+                                               double* un1, double* stage, double& dmax,
+                                               int& bad) {
     constexpr int CH = staged_chunks<T, MC>();
     constexpr int J = CH * MC / T;  // nodes per thread and pass
     static_assert(CH * MC % T == 0 && T % CH == 0, "whole passes");
@@ -364,7 +366,7 @@ __device__ __forceinline__ void correct_staged(double (&g)[MC], int M, bool pred
                 const int i = base + (j0 + j) * T + p;
                 f[j] = (i < M) ? fv[i] : 0.0;
                 gl[j] = (i < M) ? go[i] : 0.0;
-                uo[j] = (i < M) ? un1[i] : 0.0;
+                uo[j] = (i < M) ? uo1[i] : 0.0;
             }
 #pragma unroll
             for (int j = 0; j < G; ++j) {
@@ -401,26 +403,40 @@ __device__ __forceinline__ void correct_staged(double (&g)[MC], int M, bool pred
 // after the solver's 4T doubles).
 // pipe (overlapped solve; ps its counters): the slice's fine result is
 // waited for after the coarse solve, U[n+1] is overwritten only once the
-// fine launch of this iteration has read it, and each finished slice is
-// published.  Returns false if the block must stop (see PipeSync).
+// fine launch of iteration k - taken_lag has read it, and each finished
+// slice is published.  Returns false if the block must stop (see PipeSync).
+// Uin / Uout: the previous iterate (the sweep's first state and the old
+// values of the defect) and the buffer the new iterate goes to; the same
+// array except in the one-launch solve, which alternates two buffers by
+// iteration parity (there the first state is also copied to Uout, so that
+// Uout holds a whole iterate, and taken_lag is 1: Uout held iterate k-2).
 template <int T, int MC, class Solver>
 __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o, int M,
                                              int N, int n0, int coarse_steps, int kind, bool predict,
-                                             double dT, double* __restrict__ U,
+                                             double dT, const double* Uin, double* Uout,
                                              const double* __restrict__ Fv,
                                              double* __restrict__ Gold,
                                              const double* __restrict__ Vt, double* lds,
                                              double* ftab, double& dmax, int& bad,
                                              const PipeSync& ps = PipeSync{}, bool pipe = false,
-                                             const int* stop = nullptr, int* pslot = nullptr) {
+                                             const int* stop = nullptr, int* pslot = nullptr,
+                                             int taken_lag = 0) {
     const double dtc = dT / (double)coarse_steps;
     const int i0 = threadIdx.x * MC;
     const bool net = kind != BS_COARSE_IE;
     if (pipe && predict && n0 == 0) pipe_signal(ps.ready, 1);  // U[0], written before the launch
     double V[MC];
-    load_chunk<T, MC>(U + (long)n0 * M, M, V);
+    load_chunk<T, MC>(Uin + (long)n0 * M, M, V);
+    if (Uout != Uin) {
+        // Uout[n0] still holds the iterate the fine launch of iteration
+        // k - taken_lag reads
+        if (pipe && !pipe_wait<false>(ps, ps.taken + n0, ps.k - taken_lag, stop, pslot))
+            return false;
+        store_chunk<T, MC>(Uout + (long)n0 * M, M, V);
+    }
     for (int n = n0; n < N; ++n) {
-        double* un1 = U + (long)(n + 1) * M;
+        const double* uo1 = Uin + (long)(n + 1) * M;
+        double* un1 = Uout + (long)(n + 1) * M;
         double* go = Gold + (long)n * M;
         // Loads that do not depend on the coarse solve go first, so their
         // latency overlaps it (when registers allow: small chunks).
@@ -430,7 +446,7 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
             if (!predict && !pipe) {
                 load_chunk<T, MC>(Fv + (long)n * M, M, fv);
                 load_chunk<T, MC>(go, M, gold);
-                load_chunk<T, MC>(un1, M, uold);
+                load_chunk<T, MC>(uo1, M, uold);
             }
             if (net) {
                 load_chunk<T, MC>(Vt + (long)(n + 1) * M, M, vt1);
@@ -468,16 +484,17 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
             if constexpr (kPrefetch) {
                 load_chunk<T, MC>(Fv + (long)n * M, M, fv);
                 load_chunk<T, MC>(go, M, gold);
-                load_chunk<T, MC>(un1, M, uold);
+                load_chunk<T, MC>(uo1, M, uold);
             }
-            if (n + 1 < N && !pipe_wait<false>(ps, ps.taken + n + 1, ps.k, stop, pslot))
+            if (n + 1 < N &&
+                !pipe_wait<false>(ps, ps.taken + n + 1, ps.k - taken_lag, stop, pslot))
                 return false;
         }
         if constexpr (!kPrefetch) {
             // chunks of 8 or more nodes: the slice's global traffic goes
             // through the staged, node-order correction
-            correct_staged<T, MC>(g, M, predict, Fv + (long)n * M, go, un1, lds + 4 * T, dmax,
-                                  bad);
+            correct_staged<T, MC>(g, M, predict, Fv + (long)n * M, go, uo1, un1, lds + 4 * T,
+                                  dmax, bad);
 #pragma unroll
             for (int q = 0; q < MC; ++q) V[q] = g[q];
         } else if (predict) {
@@ -492,7 +509,7 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
                 if (i0 + q < M) {
                     const double f = kPrefetch ? fv[q] : fvn[i0 + q];
                     const double gl = kPrefetch ? gold[q] : go[i0 + q];
-                    const double uo = kPrefetch ? uold[q] : un1[i0 + q];
+                    const double uo = kPrefetch ? uold[q] : uo1[i0 + q];
                     const double unew = f + (g[q] - gl);
                     go[i0 + q] = g[q];
                     un1[i0 + q] = unew;

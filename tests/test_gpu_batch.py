@@ -10,8 +10,9 @@
   iterations every option equals the serial fine solution (finite
   termination); with tol the iteration counts match the oracle run on the
   oracle's own FP64 network grid (puts priced by put-call parity) within one.
-* The 512-option workload: full batch on the GPU, sampled options against
-  the oracle.
+* Errors: a NaN network weight (BS_ERR_NONFINITE) and the divergence guard
+  (BS_ERR_DIVERGED with the oracle's per-option tripping iterations).
+  (The 512-option workload at full size: tests/test_gpu_xfullsize.py.)
 """
 import numpy as np
 import pytest
@@ -104,35 +105,6 @@ def test_small_batch_network_iterations():
         assert normwise(_opt_U(U, offs, o, i), ref["U"]) <= 1e-6 / max(np.abs(ref["U"]).max(), 1) + 1e-10
 
 
-@pytest.mark.parametrize("kind", [bsp.COARSE_IE, bsp.COARSE_PINN_IE])
-def test_option_batch_workload_sampled(kind):
-    """512 options (M in {256..4096}, N in 16..64, 256 CN steps/slice), one
-    batched solve; 3 options checked against the oracle."""
-    cuda()
-    cfg = OPTION_BATCH
-    opts = [dict(o, fine_steps=cfg["fine_steps"], coarse_steps=1) for o in option_batch(cfg)]
-    net = None
-    th = None
-    if kind != bsp.COARSE_IE:
-        th = perturbed(xavier_normal(4, cfg["depth"], cfg["width"], seed=5), 0.02, 6)
-        net = bsp.PinnNet(to_dev(th, torch.float32), 4, cfg["depth"], cfg["width"], bsp.PREC_BF16)
-    say(f"512-option batch, kind {kind}")
-    U, offs, iters, defects, rc = bsp.parareal_solve_batch(opts, kind, cfg["tol"], net=net)
-    say(f"iterations: min {min(iters)} max {max(iters)} mean {np.mean(iters):.2f}")
-    for i in (0, 201, 511):
-        o = opts[i]
-        po = oracle.params_from(o)
-        ser = oracle.serial_fine(po, o["M"], o["N"], o["fine_steps"])
-        got = _opt_U(U, offs, o, i)
-        # converged to tol in max norm: within a few tol of the serial fine fixed point
-        assert np.max(np.abs(got - ser)) <= 20 * cfg["tol"] + 1e-10 * np.abs(ser).max(), i
-        if kind == bsp.COARSE_IE:
-            ref = oracle.parareal(po, o["M"], o["N"], o["fine_steps"], 1, oracle.COARSE_IE,
-                                  tol=cfg["tol"], nthreads=8)
-            assert iters[i] == ref["iters"]
-            assert normwise(got, ref["U"]) <= 1e-10
-
-
 def test_batch_rejects_grids_beyond_limit():
     """Batched options keep the factorisation in registers: at most 4096 nodes."""
     cuda()
@@ -140,3 +112,72 @@ def test_batch_rejects_grids_beyond_limit():
     big = dict(opts[0], M=4097)
     with pytest.raises(bsp.BsError):
         bsp.parareal_solve_batch([opts[1], big], bsp.COARSE_IE, 1e-8)
+
+
+def test_batch_nonfinite_and_divergence():
+    """A NaN network weight makes every option non-finite (BS_ERR_NONFINITE);
+    the literal network coarse with the divergence guard below its defect
+    ratios stops every option at the oracle's first tripping iteration
+    (BS_ERR_DIVERGED, the per-option iteration counts reported)."""
+    cuda()
+    opts = _small_batch()[:6]
+    th, net = _param_net()
+    bad = th.copy()
+    bad[4 * 32] = np.nan
+    nan_net = bsp.PinnNet(to_dev(bad, torch.float32), 4, 3, 32, bsp.PREC_FP32)
+    with pytest.raises(bsp.BsError) as e:
+        bsp.parareal_solve_batch(opts, bsp.COARSE_PINN_IE, 1e-8, net=nan_net)
+    assert e.value.code == bsp.BS_ERR_NONFINITE
+    growths, expect = [], []
+    for o in opts:
+        Vt = _oracle_vt(th, o, 32, 3)
+        ref = oracle.parareal(oracle.params_from(o), o["M"], o["N"], o["fine_steps"],
+                              o["coarse_steps"], oracle.COARSE_PINN, Vt=Vt, tol=0.0)
+        d = ref["defects"]
+        growths.append(d[1:] / d[0] if len(d) > 1 else np.array([]))
+    # one guard for the batch, strictly inside the gap between the ratios
+    allr = np.sort(np.concatenate(growths))
+    gaps = np.diff(allr)
+    j = int(np.argmax(gaps))
+    growth = 0.5 * (allr[j] + allr[j + 1])
+    for o, r in zip(opts, growths):
+        k = next((i + 2 for i, x in enumerate(r) if x > growth), None)
+        expect.append(k if k is not None else o["N"])
+    try:
+        bsp.bs_set_divergence_growth(growth)
+        with pytest.raises(bsp.BsError) as e:
+            bsp.parareal_solve_batch(opts, bsp.COARSE_PINN, 0.0, net=net)
+        assert e.value.code == bsp.BS_ERR_DIVERGED
+        # iteration counts per option: run again without raising (status only)
+        U, offs, iters, _, rc = _solve_batch_status(opts, bsp.COARSE_PINN, 0.0, net)
+        assert rc == bsp.BS_ERR_DIVERGED
+        assert list(iters) == expect, (iters, expect, growth)
+    finally:
+        bsp.bs_set_divergence_growth()
+
+
+def _solve_batch_status(opts, kind, tol, net):
+    """parareal_solve_batch through the C ABI, returning the status code
+    instead of raising (for the per-option counts of an erroring solve)."""
+    import ctypes
+    lib = bsp.load_library()
+    n = len(opts)
+    Pa = (bsp._Params * n)(*[bsp._params(o) for o in opts])
+    Ga = (bsp._Grid * n)(*[bsp._Grid(o["M"], 1) for o in opts])
+    Sa = (bsp._Slices * n)(*[bsp._Slices(o["N"], o["fine_steps"], o["coarse_steps"]) for o in opts])
+    offs, tot = [], 0
+    for o in opts:
+        offs.append(tot)
+        tot += (o["N"] + 1) * o["M"]
+    b = ctypes.c_size_t()
+    assert lib.parareal_batch_workspace_size(n, Pa, Ga, Sa, kind, ctypes.byref(b)) == 0
+    ws = torch.empty(b.value, dtype=torch.uint8, device="cuda")
+    U = torch.empty(tot, dtype=torch.float64, device="cuda")
+    it = (ctypes.c_int * n)()
+    de = (ctypes.c_double * n)()
+    rc = lib.parareal_solve_batch(n, Pa, Ga, Sa, kind, float(tol), ctypes.byref(net.c()),
+                                  max(o["N"] for o in opts), ws.data_ptr(), b.value, U.data_ptr(),
+                                  (ctypes.c_long * n)(*offs), it, de, 1,
+                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    return U, offs, list(it), list(de), rc

@@ -190,32 +190,6 @@ def test_sweep_block_shapes(T, MC, is_put, kind):
         bsp.bs_tune_reset()
 
 
-def test_large_put_workload_sampled():
-    """The large put (M = 16384, N = 256 slices, 2048 CN steps per slice,
-    256 x 6 BF16 network coarse, tol 1e-10) at full size: the converged
-    iterate satisfies the fine fixed point U_{n+1} = F(U_n) on sampled slices
-    (oracle F), and U_0 is the oracle payoff."""
-    from workloads import LARGE_PUT
-    cuda()
-    cfg = LARGE_PUT
-    M, N, Sf = cfg["M"], cfg["N"], cfg["fine_steps"]
-    th = perturbed(xavier_normal(2, cfg["depth"], cfg["width"], seed=7), 0.02, 8)
-    net = bsp.PinnNet(to_dev(th, torch.float32), 2, cfg["depth"], cfg["width"], bsp.PREC_BF16)
-    say("large put: M=16384 N=256 Sf=2048")
-    U, iters, defects = bsp.parareal_solve(option_params(cfg), M, N, Sf, 1, bsp.COARSE_PINN_IE,
-                                           tol=cfg["tol"], net=net)
-    say(f"large put: {iters} iterations, last defect {defects[-1]:.2e}")
-    U = U.cpu().numpy()
-    po = _oracle_params(cfg)
-    assert np.array_equal(U[0], oracle.initial(po, M))
-    dT = po.T / N
-    scale = np.abs(U).max()
-    for n in (0, 137, N - 1):
-        Fn = oracle.fine(po, M, n * dT, dT, Sf, U[n])
-        # at convergence the iterate is the fine fixed point up to the stopping tolerance
-        assert np.max(np.abs(U[n + 1] - Fn)) <= 100 * cfg["tol"] + 1e-10 * scale, n
-
-
 def test_solve_stops_at_max_iter_and_repeats():
     """The queued-ahead solve: a max_iter cut returns BS_NOT_CONVERGED with the
     iterate of exactly that iteration (the queued iteration after it does
@@ -247,6 +221,11 @@ def test_solve_stops_at_max_iter_and_repeats():
     (256, 8, 16, 4, False, bsp.COARSE_IE, 0.0, 3),           # max_iter cut
     (600, 5, 1, 16, False, bsp.COARSE_IE, 0.0, None),        # one fine step: the plain step
     (300, 5, 20, 8, True, bsp.COARSE_PINN_IE, 0.0, None),    # network coarse
+    # many slices, few fine steps, early stop: the sweep of iteration k+1 runs
+    # while iteration k's defect is reduced (the final iterate odd or even)
+    (256, 256, 4, 4, False, bsp.COARSE_IE, 1e-6, None),
+    (256, 256, 4, 4, False, bsp.COARSE_IE, 1e-9, None),
+    (512, 200, 3, 8, True, bsp.COARSE_PINN_IE, 1e-5, None),
 ])
 def test_persistent_solve_matches_iterations(M, N, Sf, MC, is_put, kind, tol, max_iter):
     """The whole-solve launch (fine wavefronts and sweep blocks waiting on each
@@ -326,3 +305,106 @@ def test_overlapped_solve_multiwave(M, N, Sf, is_put, tol, max_iter):
     assert normwise(U, ora["U"]) <= bound
     if max_iter is not None:
         assert rc == bsp.BS_NOT_CONVERGED
+
+
+def _nan_net(cfg):
+    th = _seeded_net(cfg, seed=9)
+    th[cfg["n_in"] * cfg["width"]] = np.nan  # first bias of the first layer
+    return bsp.PinnNet(to_dev(th, torch.float32), cfg["n_in"], cfg["depth"], cfg["width"],
+                       bsp.PREC_FP32)
+
+
+@pytest.mark.parametrize("M,shapes", [(256, None), (600, ((64, 16), (256, 4))), (3000, None),
+                                      (5000, None)])
+def test_nonfinite_is_reported(M, shapes):
+    """A NaN in the state (written into U between iterations) or coming from
+    the network grid (a NaN weight) ends the iteration and the solve with
+    BS_ERR_NONFINITE, on every solve path: queued iterations (256 nodes),
+    the one-launch solve (600 nodes, 64 x 16 fine / 256 x 4 sweep), the
+    side-stream overlapped solve (3000 nodes), one iteration after the
+    other (5000 nodes)."""
+    cuda()
+    say(f"non-finite M={M}")
+    cfg = dict(SMALL_CALL, M=M, N=6, fine_steps=8, n_in=2, depth=2, width=16)
+    p = option_params(cfg)
+    try:
+        bsp.bs_tune_reset()
+        if shapes:
+            bsp.bs_tune_set_shape(0, M, M, *shapes[0])
+            bsp.bs_tune_set_shape(1, M, M, *shapes[1])
+        pr = bsp.Parareal(p, M, cfg["N"], cfg["fine_steps"], 1, bsp.COARSE_IE)
+        pr.start()
+        pr.U[3, M // 2] = float("nan")
+        with pytest.raises(bsp.BsError) as e:
+            pr.iterate(1)
+        assert e.value.code == bsp.BS_ERR_NONFINITE
+        prn = bsp.Parareal(p, M, cfg["N"], cfg["fine_steps"], 1, bsp.COARSE_PINN_IE, _nan_net(cfg))
+        with pytest.raises(bsp.BsError) as e:
+            prn.solve(1e-8)
+        assert e.value.code == bsp.BS_ERR_NONFINITE
+        assert "non-finite" in str(e.value)
+        # a clean solve on the same objects afterwards is unaffected
+        it, _, rc = pr.solve(1e-8)
+        assert rc in (bsp.BS_OK, bsp.BS_NOT_CONVERGED) and it >= 1
+    finally:
+        bsp.bs_tune_reset()
+
+
+def _expected_divergence(defects, growth):
+    for k in range(2, len(defects) + 1):
+        if defects[k - 1] > growth * defects[0]:
+            return k
+    return None
+
+
+@pytest.mark.parametrize("M,shapes", [(256, None), (600, ((64, 16), (256, 4))), (3000, None),
+                                      (5000, None)])
+def test_divergence_guard(M, shapes):
+    """The literal network coarse (its defects fall slowly, ratios to the
+    first defect 0.66, 0.56, ... on this input) with the guard set below
+    those ratios: every solve path stops at the oracle's first iteration k
+    whose defect exceeds growth x the first one and returns BS_ERR_DIVERGED
+    with that iterate in U; with the default guard the same solve runs to
+    finite termination."""
+    cuda()
+    say(f"divergence guard M={M}")
+    cfg = dict(SMALL_CALL, M=M, N=8, fine_steps=16, n_in=2, depth=2, width=16)
+    p = option_params(cfg)
+    po = _oracle_params(cfg)
+    th = _seeded_net(cfg, seed=0)
+    net = bsp.PinnNet(to_dev(th, torch.float32), 2, cfg["depth"], cfg["width"], bsp.PREC_FP32)
+    S = oracle.grid(po, M)
+    taus = np.arange(cfg["N"] + 1) * (po.T / cfg["N"])
+    Vt = mlp.grid_values(th.astype(np.float64), 2, cfg["depth"], cfg["width"], po.K, taus, S)
+    ref = oracle.parareal(po, M, cfg["N"], cfg["fine_steps"], 1, oracle.COARSE_PINN, Vt=Vt,
+                          tol=0.0, keep_iterates=True)
+    d = ref["defects"]
+    growth = 0.5 * float(np.max(d[1:] / d[0])) + 0.5 * float(np.min(d[1:] / d[0]))
+    k_exp = _expected_divergence(d, growth)
+    assert k_exp is not None
+    try:
+        bsp.bs_tune_reset()
+        if shapes:
+            bsp.bs_tune_set_shape(0, M, M, *shapes[0])
+            bsp.bs_tune_set_shape(1, M, M, *shapes[1])
+        pr = bsp.Parareal(p, M, cfg["N"], cfg["fine_steps"], 1, bsp.COARSE_PINN, net)
+        bsp.bs_set_divergence_growth(growth)
+        with pytest.raises(bsp.BsError) as e:
+            pr.solve(0.0)
+        assert e.value.code == bsp.BS_ERR_DIVERGED, str(e.value)
+        # the iterate that tripped the guard (FP32 network grid: 1e-6 of the oracle's)
+        assert normwise(pr.U.cpu().numpy(), ref["iterates"][k_exp]) <= 1e-6
+        bsp.bs_set_divergence_growth()
+        it, _, rc = pr.solve(0.0)
+        assert it == cfg["N"] and rc == bsp.BS_OK
+        assert normwise(pr.U.cpu().numpy(), ref["U"]) <= 1e-11
+    finally:
+        bsp.bs_set_divergence_growth()
+        bsp.bs_tune_reset()
+
+
+def test_divergence_growth_argument():
+    cuda()
+    with pytest.raises(bsp.BsError):
+        bsp.bs_set_divergence_growth(0.0)
+    assert bsp.bs_divergence_growth() == bsp.BS_DIVERGENCE_GROWTH

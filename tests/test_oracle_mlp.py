@@ -151,3 +151,51 @@ def test_empty_point_sets_contribute_zero():
     g_empty = mlp.loss_grad(th, X_f, X_e, X_b, n_in, depth, width, False, 0.2, 0.05)
     g_none = mlp.loss_grad(th, X_f, X_e[:0], X_b, n_in, depth, width, False, 0.2, 0.05)
     assert np.array_equal(g_empty, g_none)
+
+
+@pytest.mark.parametrize("n_f", [0, 40])
+def test_value_targets_vs_torch_autograd(n_f):
+    """Given value targets (y_e, y_b) replace eqs. (2)-(4): the loss and its
+    gradient against torch autograd with the same targets; n_f = 0 is the loss
+    of a network fitted to values alone (data, no residual)."""
+    n_in, depth, width = 2, 3, 16
+    th = _theta(n_in, depth, width)
+    X_f, X_e, X_b = collocation(max(n_f, 1), 25, 10, 1.0, 3.0, seed=9)
+    X_f = X_f[:n_f]
+    rng = np.random.default_rng(4)
+    y_e = rng.normal(size=X_e.shape[0])
+    y_b = rng.normal(size=X_b.shape[0])
+    net = _torch_net(th, n_in, depth, width)
+    terms = []
+    if n_f:
+        v, v_t, v_x, v_xx = _torch_streams(net, X_f)
+        x = torch.tensor(X_f[:, 1])
+        f = v_t - 0.5 * 0.2 * 0.2 * x * x * v_xx - 0.05 * x * v_x + 0.05 * v
+        terms.append((f * f).mean())
+    else:
+        terms.append(torch.zeros((), dtype=torch.float64))
+    terms.append(((net(torch.tensor(X_e))[:, 0] - torch.tensor(y_e)) ** 2).mean())
+    terms.append(((net(torch.tensor(X_b))[:, 0] - torch.tensor(y_b)) ** 2).mean())
+    sum(terms).backward()
+    ref_grad = np.concatenate([torch.cat([m.weight.grad.reshape(-1), m.bias.grad]).numpy()
+                               for m in net if isinstance(m, torch.nn.Linear)])
+    got3 = mlp.loss3(th, X_f, X_e, X_b, n_in, depth, width, False, 0.2, 0.05, y_e=y_e, y_b=y_b)
+    for g, r in zip(got3, terms):
+        assert abs(g - r.item()) <= 1e-12 * max(1.0, abs(r.item()))
+    got = mlp.loss_grad(th, X_f, X_e, X_b, n_in, depth, width, False, 0.2, 0.05, y_e=y_e, y_b=y_b)
+    assert np.max(np.abs(got - ref_grad)) <= 1e-11 * max(1.0, np.max(np.abs(ref_grad)))
+
+
+def test_value_targets_equal_to_conditions_change_nothing():
+    """Targets equal to eqs. (2)-(4) give the loss and gradient of the default."""
+    n_in, depth, width = 2, 2, 8
+    th = _theta(n_in, depth, width)
+    X_f, X_e, X_b = collocation(20, 12, 8, 1.0, 3.0, seed=10)
+    y_e = mlp.terminal_target(X_e, True)
+    y_b = mlp.boundary_target(X_b, True, 0.05)
+    a = mlp.loss3(th, X_f, X_e, X_b, n_in, depth, width, True, 0.2, 0.05)
+    b = mlp.loss3(th, X_f, X_e, X_b, n_in, depth, width, True, 0.2, 0.05, y_e=y_e, y_b=y_b)
+    assert a == b
+    ga = mlp.loss_grad(th, X_f, X_e, X_b, n_in, depth, width, True, 0.2, 0.05)
+    gb = mlp.loss_grad(th, X_f, X_e, X_b, n_in, depth, width, True, 0.2, 0.05, y_e=y_e, y_b=y_b)
+    assert np.array_equal(ga, gb)

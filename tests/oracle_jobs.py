@@ -5,9 +5,6 @@ processes when collection ends, so they run while the other GPU tests do;
 a test then waits for its result with ``oracle_result``.
 
 Each job calls the oracle only (no HIP library, no torch):
-  * ``large_put``: serial fine integration (eq. (6): N slices of the fine
-    propagator one after the other) of the 16384-node put, all 257 time
-    levels;
   * ``option_batch``: serial fine integration of each of the 512 options of
     the batched workload (process pool over the options).
 
@@ -29,13 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
-from workloads import LARGE_PUT, OPTION_BATCH, option_batch, option_params  # noqa: E402
-
-
-def large_put():
-    cfg = LARGE_PUT
-    p = oracle.params_from(option_params(cfg))
-    return oracle.serial_fine(p, cfg["M"], cfg["N"], cfg["fine_steps"], cfg["payoff_mode"])
+from workloads import OPTION_BATCH, option_batch  # noqa: E402
 
 
 def _one_option(o):
@@ -58,7 +49,7 @@ def option_batch_ref(workers: int = 8):
     return np.concatenate(out)
 
 
-JOBS = {"large_put": large_put, "option_batch": option_batch_ref}
+JOBS = {"option_batch": option_batch_ref}
 
 # Started jobs of this test session: name -> (process, output path, start time)
 _RUNNING = {}

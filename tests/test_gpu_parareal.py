@@ -397,7 +397,9 @@ def test_divergence_guard(M, shapes):
         bsp.bs_set_divergence_growth()
         it, _, rc = pr.solve(0.0)
         assert it == cfg["N"] and rc == bsp.BS_OK
-        assert normwise(pr.U.cpu().numpy(), ref["U"]) <= 1e-11
+        # the solution bar (finite termination reaches the serial fine
+        # solution, which the two sides compute with different roundings)
+        assert normwise(pr.U.cpu().numpy(), ref["U"]) <= 1e-10
     finally:
         bsp.bs_set_divergence_growth()
         bsp.bs_tune_reset()

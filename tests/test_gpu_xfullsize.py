@@ -7,8 +7,11 @@ fixed point by about the last defect or less (the iteration contracts fast
 near convergence: measured with the oracle at 0.1-0.3 x the last defect),
 so at tol 1e-8 (price units; solutions of 50..400) the gap is ~1e-11 and at
 tol 1e-10 ~1e-13, well inside the bar; rounding adds ~1e-12 (propagator
-tests).  The oracle references that take minutes of CPU time (the 16384-node
-put: 257 levels of 2048 CN steps; the 512 options) run in background
+tests).  The 16384-node put's serial fine solution takes about 20 minutes
+of one CPU core (257 levels of 2048 CN steps, each level needing the one
+before), so the oracle's values at 12 levels are stored
+(tests/golden/large_put_reference.py writes them); the 512 options' serial
+fine solutions take minutes of CPU time in all and run in background
 processes started when the tests are collected (tests/oracle_jobs.py).
 
 * The 16384-node put (256 slices, 2048 CN steps per slice, tol 1e-10) with
@@ -43,11 +46,20 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-@pytest.mark.oracle_job("large_put")
-@pytest.mark.timeout(900)
+def _large_put_reference():
+    path = os.path.join(GOLDEN, "large_put_levels.npz")
+    if not os.path.exists(path):
+        pytest.skip("fixture tests/golden/large_put_levels.npz not written yet "
+                    "(python -m tests.golden.large_put_reference)")
+    with np.load(path) as z:
+        return z["levels"], z["U"]
+
+
+@pytest.mark.timeout(300)
 @pytest.mark.parametrize("kind", [bsp.COARSE_PINN_IE, bsp.COARSE_IE])
 def test_large_put_full_size(kind):
     cuda()
+    levels, ref = _large_put_reference()
     cfg = LARGE_PUT
     M, N, Sf = cfg["M"], cfg["N"], cfg["fine_steps"]
     net = None
@@ -59,12 +71,13 @@ def test_large_put_full_size(kind):
                                            tol=cfg["tol"], net=net)
     U = U.cpu().numpy()
     say(f"large put: {iters} iterations, last defect {defects[-1]:.2e}")
-    ref = oracle_result("large_put")
-    assert ref.shape == U.shape
-    per_level = np.max(np.abs(U - ref), axis=1) / np.max(np.abs(ref))
+    assert ref.shape == (len(levels), M)
+    got = U[levels]
+    per_level = np.max(np.abs(got - ref), axis=1) / np.max(np.abs(ref))
     err = float(per_level.max())
-    say(f"large put: normwise error vs serial fine {err:.3e} (worst level {int(per_level.argmax())})")
-    assert np.array_equal(U[0], ref[0])
+    say(f"large put: normwise error vs serial fine {err:.3e} at levels {levels.tolist()} "
+        f"(worst level {int(levels[per_level.argmax()])})")
+    assert np.array_equal(got[0], ref[0])
     assert err <= 1e-10
 
 

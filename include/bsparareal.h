@@ -221,6 +221,29 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
                    int coarse_kind, double tol, const pinn_net* net, int max_iter, void* ws,
                    size_t ws_bytes, double* U, int* iters, double* defect_hist, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream or graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as parareal_solve without a caller workspace.  Its workspace and
+ * per-iteration record live in a library-owned device array of
+ * BS_NOALLOC_SCRATCH_BYTES bytes, one per GPU, created with the library's code
+ * on that GPU and held until the process ends; the call makes no hipMalloc,
+ * hipFree or other allocating call (the device address of the array is looked
+ * up once per device, on the first call there).  Iterates, defects and
+ * iteration counts are those of parareal_solve with the same block shapes:
+ * grids covered by the one-launch solve run it; other grids run the
+ * iterations one after the other on `stream` (no side streams).
+ * Limits: M <= 4096, N <= 512, and the workspace of parareal_workspace_size()
+ * plus 16 (min(max_iter, N) + 1) bytes of record must fit the array
+ * (BS_ERR_ARG otherwise, with the sizes in bs_last_error()).  The array keeps
+ * the last call's contents; every call initialises what it reads.  Calls on
+ * one GPU share the array: calls that overlap in time on one GPU (another
+ * thread, another stream) race and corrupt each other; order them.
+ * SYNCHRONOUS.  Arguments and return values as parareal_solve. */
+#define BS_NOALLOC_SCRATCH_BYTES (8u << 20)
+int parareal_solve_noalloc(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,
+                           int coarse_kind, double tol, const pinn_net* net, int max_iter,
+                           double* U, int* iters, double* defect_hist, void* stream);
+
 /* *bytes (host, out) = bytes of device workspace parareal_solve_batch needs
  * for these options (host arrays of n_opt entries).  BS_ERR_ARG if an option
  * is invalid (bs_last_error names it). */

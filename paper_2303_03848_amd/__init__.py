@@ -35,7 +35,9 @@ EXPORTS = ("bs_last_error", "bs_initial", "bs_fine_propagate_batch", "bs_coarse_
            "parareal_workspace_size", "parareal_start", "parareal_iterate", "parareal_solve",
            "parareal_batch_workspace_size", "parareal_solve_batch",
            "bs_tune_set_shape", "bs_tune_reset", "bs_profile_enable", "bs_profile_read",
-           "bs_set_divergence_growth", "bs_divergence_growth", "bs_release_resources")
+           "bs_set_divergence_growth", "bs_divergence_growth", "bs_release_resources",
+           "parareal_solve_noalloc")
+BS_NOALLOC_SCRATCH_BYTES = 8 << 20
 
 
 class BsError(RuntimeError):
@@ -89,6 +91,7 @@ def load_library(path: str = LIB_PATH):
         "parareal_start": (i, [P, G, S, i, N, vp, sz, vp, vp]),
         "parareal_iterate": (i, [P, G, S, i, N, vp, sz, vp, i, dp, ip, vp]),
         "parareal_solve": (i, [P, G, S, i, d, N, i, vp, sz, vp, ip, dp, vp]),
+        "parareal_solve_noalloc": (i, [P, G, S, i, d, N, i, vp, ip, dp, vp]),
         "parareal_batch_workspace_size": (i, [i, P, G, S, i, szp]),
         "parareal_solve_batch": (i, [i, P, G, S, i, d, N, i, vp, sz, vp,
                                      ctypes.POINTER(ctypes.c_long), ip, dp, i, vp]),
@@ -312,6 +315,28 @@ def bs_profile_read() -> dict:
     _check(load_library().bs_profile_read(out))
     return {"fine_ms": out[0], "fine_launches": int(out[1]), "fine_cells": out[2],
             "sweep_ms": out[3], "sweep_launches": int(out[4])}
+
+
+def parareal_solve_noalloc(p: dict, M: int, N: int, fine_steps: int, coarse_steps: int = 1,
+                           coarse_kind: int = COARSE_IE, tol: float = 1e-8,
+                           net: PinnNet | None = None, max_iter: int | None = None,
+                           payoff_mode: int = 1, U: torch.Tensor | None = None):
+    """parareal_solve without a workspace (the library's fixed device scratch
+    array).  U: caller's [N+1, M] float64 CUDA tensor (allocated here if
+    None).  Returns (U, iters, defects, status)."""
+    if U is None:
+        U = torch.empty((N + 1, M), dtype=torch.float64, device="cuda")
+    if U.numel() != (N + 1) * M:
+        raise ValueError("U must hold (N+1)*M values")
+    max_iter = N if max_iter is None else max_iter
+    it = ctypes.c_int()
+    hist = (ctypes.c_double * max_iter)()
+    rc = _check(load_library().parareal_solve_noalloc(
+        ctypes.byref(_params(p)), ctypes.byref(_Grid(M, payoff_mode)),
+        ctypes.byref(_Slices(N, fine_steps, coarse_steps)), coarse_kind, float(tol),
+        ctypes.byref(net.c()) if net is not None else None, int(max_iter),
+        _dev(U, torch.float64, "U"), ctypes.byref(it), hist, _stream()))
+    return U, it.value, list(hist)[: it.value], rc
 
 
 def parareal_solve(p: dict, M: int, N: int, fine_steps: int, coarse_steps: int = 1,

@@ -7,6 +7,7 @@
 #include <vector>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 #include "bsp_common.hpp"
 
@@ -322,7 +323,7 @@ static int enqueue_iteration(const bs_params* prm, const bs_grid* grid, const bs
     const double dT = prm->T / N;
     Workspace w = ws_layout(ws, M, N, kind);
     const int first = k - 1 < N - 1 ? k - 1 : N - 1;
-    const bool prof = g_prof.on;
+    const bool prof = g_prof.on && slot >= 0;
     PipeSync pk{};
     if (ps) {
         pk = *ps;
@@ -435,14 +436,22 @@ static int solve_streams() {
 // host-mapped history and leaves the final iterate in U; the host reads the
 // history once the stream has drained.  The stop flag must already be clear
 // on st.
+// rec_dev: the per-iteration record [2 (kmax+1)] the kernel writes; rec_host:
+// where the host reads it after the stream has drained (the same memory when
+// it is host-mapped; otherwise the record is copied there first).
 static int solve_persistent(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,
                             int kind, double tol, double growth, const pinn_net* net, int kmax,
                             void* ws, double* U, int* iters, double* defect_hist,
+                            double* rec_dev, double* rec_host, bool rec_mapped, bool prof,
                             hipStream_t st) {
     int rc;
     const int M = grid->M, N = sl->N;
-    SolveState& S = t_solve;
-    for (size_t i = 0; i < 2 * (size_t)(kmax + 1); ++i) S.hist[i] = -1.0;  // not reached
+    const size_t nrec = 2 * (size_t)(kmax + 1);
+    if (rec_mapped) {
+        for (size_t i = 0; i < nrec; ++i) rec_host[i] = -1.0;  // not reached
+    } else if ((rc = launch_fill_double(rec_dev, (int)nrec, -1.0, st))) {
+        return rc;
+    }
     Workspace w = ws_layout(ws, M, N, kind);
     const PipeSync ps = pipe_sync(w, N);
     if ((rc = launch_fill_int(w.flags, flag_count(N), 0, st))) return rc;
@@ -465,24 +474,26 @@ static int solve_persistent(const bs_params* prm, const bs_grid* grid, const bs_
     a.Vt = w.Vt;
     a.result = w.result;
     a.stop = reinterpret_cast<int*>(w.result + 4);
-    a.hist = S.hist_dev;
+    a.hist = rec_dev;
     a.decided = w.flags + 3 * (N + 1) + 1;
     a.exited = a.decided + (N + 1);
     a.stop_rank = a.exited + 1;
     a.ps = ps;
-    const bool prof = g_prof.on;
     if (prof) BSP_HIP(hipEventRecord(g_prof.ev[0], st));
     if ((rc = launch_parareal_persist(a, st))) return rc;
     if (prof) BSP_HIP(hipEventRecord(g_prof.ev[1], st));
     int err = 0;
     BSP_HIP(hipMemcpyAsync(&err, ps.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (!rec_mapped)
+        BSP_HIP(hipMemcpyAsync(rec_host, rec_dev, nrec * sizeof(double), hipMemcpyDeviceToHost,
+                               st));
     BSP_HIP(hipStreamSynchronize(st));
     if (err) {
         set_error("Parareal solve: a launch waited longer than its time limit");
         return BS_ERR_HIP;
     }
     // the first iteration that met the stopping rule (or kmax)
-    const volatile double* hist = S.hist;
+    const volatile double* hist = rec_host;
     int status = BS_NOT_CONVERGED, last = 0;
     for (int j = 1; j <= kmax; ++j) {
         const double d = hist[2 * j], flag = hist[2 * j + 1];
@@ -547,7 +558,7 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
     if ((rc = launch_set_int(stop, 0, st))) return rc;
     if (persist_capable(grid->M, N))
         return solve_persistent(prm, grid, sl, kind, tol, growth, net, kmax, ws, U, iters,
-                                defect_hist, st);
+                                defect_hist, S.hist_dev, S.hist, true, g_prof.on, st);
 
     // Overlapped iterations (grids the one-block sweep and the per-system
     // fine kernel cover): the fine launch of iteration k runs on a side
@@ -657,3 +668,116 @@ int bs_release_resources(void) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------ solve without allocation
+// parareal_solve_noalloc keeps its workspace and per-iteration record in a
+// file-scope device array, `scratch` (one copy per GPU the library runs on,
+// held until the process ends).  In host code the array's name stands for a
+// host-side shadow, not a device address: kernels and copies get the address
+// hipGetSymbolAddress returns, looked up once per device.
+static __device__ __align__(256) unsigned char scratch[BS_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kScratchDevices = 64;
+constexpr int kNoallocMaxM = 4096;  // beyond: coefficient tables the library allocates
+constexpr int kNoallocMaxN = 512;   // bounds the host copy of the record (on the stack)
+static std::mutex g_scratch_mu;
+static void* g_scratch[kScratchDevices] = {};
+
+// Device address of this device's scratch (looked up on the first call on
+// the device, with that device current).
+static int scratch_address(void** out) {
+    int dev = 0;
+    BSP_HIP(hipGetDevice(&dev));
+    BSP_CHECK_ARG(dev >= 0 && dev < kScratchDevices, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr) {
+            set_error("hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                      hipGetErrorString(e));
+            return BS_ERR_HIP;
+        }
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return BS_OK;
+}
+
+extern "C" int parareal_solve_noalloc(const bs_params* prm, const bs_grid* grid,
+                                      const bs_slices* sl, int kind, double tol,
+                                      const pinn_net* net, int max_iter, double* U, int* iters,
+                                      double* defect_hist, void* stream) {
+    clear_error();
+    int rc;
+    if ((rc = check_params(prm))) return rc;
+    if ((rc = check_grid(grid))) return rc;
+    if ((rc = check_slices(sl))) return rc;
+    BSP_CHECK_ARG(kind == BS_COARSE_IE || kind == BS_COARSE_PINN || kind == BS_COARSE_PINN_IE,
+                  "unknown coarse kind %d", kind);
+    if (kind != BS_COARSE_IE) {
+        if ((rc = check_net(net))) return rc;
+        BSP_CHECK_ARG(net->n_in == 2 || net->n_in == 4, "network inputs must be 2 or 4");
+    }
+    BSP_CHECK_ARG(U != nullptr, "U is NULL");
+    BSP_CHECK_ARG(iters != nullptr, "iters must be a non-NULL host pointer");
+    BSP_CHECK_ARG(max_iter >= 1, "max_iter must be >= 1");
+    BSP_CHECK_ARG(tol >= 0, "tol must be >= 0");
+    const int M = grid->M, N = sl->N;
+    BSP_CHECK_ARG(M <= kNoallocMaxM, "parareal_solve_noalloc covers grids of up to %d nodes (M = %d)",
+                  kNoallocMaxM, M);
+    BSP_CHECK_ARG(N <= kNoallocMaxN, "parareal_solve_noalloc covers up to %d slices (N = %d)",
+                  kNoallocMaxN, N);
+    const int kmax = max_iter < N ? max_iter : N;
+    const size_t wsb = ws_bytes(M, N, kind);  // a multiple of 256
+    const size_t nrec = 2 * (size_t)(kmax + 1);
+    const size_t need = wsb + align256(sizeof(double) * nrec);
+    if (need > (size_t)BS_NOALLOC_SCRATCH_BYTES) {
+        set_error("parareal_solve_noalloc: M = %d, N = %d needs %zu bytes of scratch, the maximum "
+                  "is %zu",
+                  M, N, need, (size_t)BS_NOALLOC_SCRATCH_BYTES);
+        return BS_ERR_ARG;
+    }
+    void* base = nullptr;
+    if ((rc = scratch_address(&base))) return rc;
+    void* ws = base;
+    double* rec_dev = reinterpret_cast<double*>(static_cast<char*>(base) + wsb);
+    double rec[2 * (kNoallocMaxN + 1)];
+    hipStream_t st = (hipStream_t)stream;
+    const double growth = g_growth.load();
+    *iters = 0;
+    Workspace w = ws_layout(ws, M, N, kind);
+    int* stop = reinterpret_cast<int*>(w.result + 4);
+    if ((rc = launch_set_int(stop, 0, st))) return rc;
+    if (persist_capable(M, N))
+        return solve_persistent(prm, grid, sl, kind, tol, growth, net, kmax, ws, U, iters,
+                                defect_hist, rec_dev, rec, false, false, st);
+
+    // Otherwise the iterations one after the other on the caller's stream,
+    // each decided from its 16-byte record before the next one is queued.
+    if ((rc = start_impl(prm, grid, sl, kind, net, ws, U, nullptr, st))) return rc;
+    int status = BS_NOT_CONVERGED, last = 0;
+    for (int k = 1; k <= kmax; ++k) {
+        if ((rc = enqueue_iteration(prm, grid, sl, kind, ws, U, k, stop, rec_dev, tol, growth, -1,
+                                    nullptr, st, st)))
+            return rc;
+        BSP_HIP(hipMemcpyAsync(rec + 2 * k, rec_dev + 2 * k, 2 * sizeof(double),
+                               hipMemcpyDeviceToHost, st));
+        BSP_HIP(hipStreamSynchronize(st));
+        const double d = rec[2 * k];
+        if (defect_hist) defect_hist[k - 1] = d;
+        last = k;
+        if ((status = record_status(rec[2 * k + 1])) != BS_OK) break;
+        if (d <= tol || k == N) {
+            status = BS_OK;
+            break;
+        }
+        status = BS_NOT_CONVERGED;
+    }
+    *iters = last;
+    if (status == BS_ERR_NONFINITE)
+        set_error("non-finite value in the Parareal state at iteration %d", last);
+    else if (status == BS_ERR_DIVERGED)
+        set_error("Parareal diverging: defect of iteration %d above %g x the first", last, growth);
+    return status;
+}

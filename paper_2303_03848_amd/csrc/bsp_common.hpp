@@ -274,6 +274,7 @@ bool persist_capable(int M, int N);
 int launch_parareal_persist(const PersistArgs& a, hipStream_t stream);
 int launch_set_int(int* p, int v, hipStream_t stream);  // *p = v in stream order
 int launch_fill_int(int* p, int n, int v, hipStream_t stream);  // p[0..n) = v
+int launch_fill_double(double* p, int n, double v, hipStream_t stream);  // p[0..n) = v
 bool pipe_capable(int M);  // the overlapped solve covers grids of this size
 
 int launch_initial(const OptionDev& o, int M, int payoff_mode, double* u0, hipStream_t stream);

@@ -69,6 +69,18 @@ int launch_fill_int(int* p, int n, int v, hipStream_t stream) {
     return BS_OK;
 }
 
+__global__ void k_fill_double(double* p, int n, double v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+int launch_fill_double(double* p, int n, double v, hipStream_t stream) {
+    if (n <= 0) return BS_OK;
+    hipLaunchKernelGGL(k_fill_double, dim3((n + 255) / 256), dim3(256), 0, stream, p, n, v);
+    BSP_LAUNCHED();
+    return BS_OK;
+}
+
 int launch_set_int(int* p, int v, hipStream_t stream) {
     hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, stream, p, v);
     BSP_LAUNCHED();

@@ -3,6 +3,7 @@
 #include "bsp_common.hpp"
 #include "bsp_steps.hpp"
 #include "bsp_tridiag_large.hpp"
+#include "bsp_tridiag_rc.hpp"
 
 namespace bsp {
 
@@ -405,16 +406,18 @@ int launch_parareal_persist(const PersistArgs& in, hipStream_t stream) {
 // use the streamed-coefficient solver.
 static bool is_large(TriShape sh) { return sh.T == 512 && sh.MC >= 16; }
 
-template <int T, int MC>
-__global__ __launch_bounds__(T) void k_large_theta(ThetaArgs a, const double* __restrict__ tab,
-                                                   const double* __restrict__ ptab) {
+// F / G on large grids: one block per system and compute unit; each block
+// builds its own factorisation (BlockTriR keeps the pivots in LDS and
+// recomputes everything else), so concurrent launches share nothing.
+template <int T, int MC, bool HI>
+__global__ __launch_bounds__(T) void k_rc_theta(ThetaArgs a) {
     __shared__ double lds[4 * T];
     __shared__ double ftab[2 * kForceChunk];
-    __shared__ double kst[2 * BlockTriG<T, MC>::LOGT * T];
+    __shared__ double kus[(MC - 1) * T];
     if (stopped(a.stop)) return;
     const int sys = blockIdx.x;
-    BlockTriG<T, MC> S;
-    S.load(tab, ptab, a.o.s2, a.o.r, a.theta * a.dt, (1.0 - a.theta) * a.dt, a.M, kst);
+    BlockTriR<T, MC, HI> S;
+    S.setup(a.o.s2, a.o.r, a.theta * a.dt, (1.0 - a.theta) * a.dt, a.M, kus, lds);
     const double tau0 =
         a.tau0 ? a.tau0[sys] : a.tau_start + (double)(sys + a.sys_offset) * a.tau_stride;
     double V[MC];
@@ -584,16 +587,13 @@ int launch_theta_batch(const OptionDev& o, int M, int nsys, const double* tau0, 
         return BS_ERR_ARG;
     }
     if (is_large(sh)) {
-        double *tab, *ptab;
-        int rc = large_tables(0, &tab, &ptab);
-        if (rc) return rc;
-        const double h = theta * dt, e = (1.0 - theta) * dt;
+        const bool hi = M % sh.MC != 0;
         if (sh.MC == 16) {
-            if ((rc = launch_large_setup<512, 16>(o, M, h, e, tab, ptab, stream))) return rc;
-            hipLaunchKernelGGL((k_large_theta<512, 16>), dim3(nsys), dim3(512), 0, stream, a, tab, ptab);
+            if (hi) hipLaunchKernelGGL((k_rc_theta<512, 16, true>), dim3(nsys), dim3(512), 0, stream, a);
+            else hipLaunchKernelGGL((k_rc_theta<512, 16, false>), dim3(nsys), dim3(512), 0, stream, a);
         } else {
-            if ((rc = launch_large_setup<512, 32>(o, M, h, e, tab, ptab, stream))) return rc;
-            hipLaunchKernelGGL((k_large_theta<512, 32>), dim3(nsys), dim3(512), 0, stream, a, tab, ptab);
+            if (hi) hipLaunchKernelGGL((k_rc_theta<512, 32, true>), dim3(nsys), dim3(512), 0, stream, a);
+            else hipLaunchKernelGGL((k_rc_theta<512, 32, false>), dim3(nsys), dim3(512), 0, stream, a);
         }
         BSP_LAUNCHED();
         return BS_OK;

@@ -1,8 +1,7 @@
-"""Measurements of the workloads besides the headline one (one GPU): the
-small call, one training step of the residual loss, the batch of 512
-options and the 16384-node put.  Used by ``bench.py --all-workloads``; every
-number comes from the library's kernels, timed with events on the current
-stream after a warm-up.
+"""Measurements of the workloads besides the headline ones (one GPU): the
+small call, one training step of the residual loss and the batch of 512
+options.  Used by ``bench.py --all-workloads``; every number comes from the
+library's kernels, timed after a warm-up.
 """
 from __future__ import annotations
 
@@ -12,7 +11,7 @@ import numpy as np
 import torch
 
 import paper_2303_03848_amd as bsp
-from workloads import (LARGE_PUT, OPTION_BATCH, SMALL_CALL, TRAIN_STEP, collocation, option_batch,
+from workloads import (OPTION_BATCH, SMALL_CALL, TRAIN_STEP, collocation, option_batch,
                        option_params, xavier_normal)
 
 FP32_VALU_PEAK = 157.3e12
@@ -106,40 +105,10 @@ def batch_options(n_opt: int | None = None) -> dict:
             "serial_fine_cells": serial}
 
 
-def large_put() -> dict:
-    cfg = LARGE_PUT
-    p, M, N, Sf = option_params(cfg), cfg["M"], cfg["N"], cfg["fine_steps"]
-    pr = bsp.Parareal(p, M, N, Sf, 1, bsp.COARSE_IE)
-    it = [0]
-
-    def solve():
-        it[0] = pr.solve(cfg["tol"])[0]
-
-    ms = _timed(solve, 1)
-    # the network on the whole (N+1) x M grid, BF16 MFMA, seeded weights
-    d, w = cfg["depth"], cfg["width"]
-    net = bsp.PinnNet(torch.tensor(xavier_normal(cfg["n_in"], d, w, 0), device="cuda"),
-                      cfg["n_in"], d, w, bsp.PREC_BF16)
-    from paper_2303_03848_amd.pinn import grid_values
-    grid_values(net, p, M, N)  # builds the inputs once (host side) and warms up
-    S = (np.arange(1, M + 1) * (p["s_max"] / (M + 1))) / p["K"]
-    taus = np.arange(N + 1) * (p["T"] / N)
-    T, X = np.meshgrid(taus, S, indexing="ij")
-    X = torch.tensor(np.stack([T.ravel(), X.ravel()], 1), dtype=torch.float32, device="cuda")
-    out32 = torch.empty(X.shape[0], dtype=torch.float32, device="cuda")
-    mlp_ms = _timed(lambda: bsp.pinn_forward(net, X, out32), 5)
-    mlp_flops = 2.0 * (cfg["n_in"] * w + (d - 1) * w * w + w) * X.shape[0]
-    return {"workload": cfg["name"], "coarse": "implicit_euler", "time_to_solution_ms": ms,
-            "iters": it[0], "cell_updates_per_s": parareal_cells(M, N, Sf, it[0]) / (ms / 1e3),
-            "network_grid_eval": {"network": f"{d}x{w} tanh bf16", "points": int(X.shape[0]),
-                                  "ms": mlp_ms, "tflops": mlp_flops / (mlp_ms / 1e3) / 1e12,
-                                  "mfma_frac": mlp_flops / (mlp_ms / 1e3) / BF16_MFMA_PEAK}}
-
-
 def measure_all(log=print) -> dict:
     out = {}
     for name, fn in (("small_call", small_call), ("train_step", train_step),
-                     ("option_batch", batch_options), ("large_put", large_put)):
+                     ("option_batch", batch_options)):
         t0 = time.time()
         out[name] = fn()
         log(f"[workloads] {name}: {time.time() - t0:.1f}s {out[name]}")

@@ -416,16 +416,32 @@ __global__ __launch_bounds__(T) void k_rc_theta(ThetaArgs a) {
     __shared__ double kus[(MC - 1) * T];
     if (stopped(a.stop)) return;
     const int sys = blockIdx.x;
-    BlockTriR<T, MC, HI> S;
-    S.setup(a.o.s2, a.o.r, a.theta * a.dt, (1.0 - a.theta) * a.dt, a.M, kus, lds);
+    RcFact<T, MC, HI> Fa;
+    Fa.setup(a.o.s2, a.o.r, a.theta * a.dt, (1.0 - a.theta) * a.dt, a.M, kus, lds);
     const double tau0 =
         a.tau0 ? a.tau0[sys] : a.tau_start + (double)(sys + a.sys_offset) * a.tau_stride;
     double V[MC];
     load_chunk<T, MC>(a.u_in + (long)sys * a.ld_in, a.M, V);
-    if (a.theta == 1.0)
-        theta_steps<T, MC, false>(S, a.o, V, tau0, a.dt, a.steps, 1.0, a.homog != 0, lds, ftab);
-    else
-        theta_steps<T, MC, true>(S, a.o, V, tau0, a.dt, a.steps, a.theta, a.homog != 0, lds, ftab);
+    const bool slow = Fa.nst > kRcRegStages;  // the same in every thread of the block
+    const bool hg = a.homog != 0;
+    if (a.theta == 0.5) {
+        if (slow)
+            theta_steps<T, MC, true>(BlockTriR<T, MC, HI, true, true>(Fa), a.o, V, tau0, a.dt,
+                                     a.steps, 0.5, hg, lds, ftab);
+        else
+            theta_steps<T, MC, true>(BlockTriR<T, MC, HI, true, false>(Fa), a.o, V, tau0, a.dt,
+                                     a.steps, 0.5, hg, lds, ftab);
+    } else if (a.theta == 1.0) {
+        if (slow)
+            theta_steps<T, MC, false>(BlockTriR<T, MC, HI, false, true>(Fa), a.o, V, tau0, a.dt,
+                                      a.steps, 1.0, hg, lds, ftab);
+        else
+            theta_steps<T, MC, false>(BlockTriR<T, MC, HI, false, false>(Fa), a.o, V, tau0,
+                                      a.dt, a.steps, 1.0, hg, lds, ftab);
+    } else {
+        theta_steps<T, MC, true>(BlockTriR<T, MC, HI, false, true>(Fa), a.o, V, tau0, a.dt,
+                                 a.steps, a.theta, hg, lds, ftab);
+    }
     store_chunk<T, MC>(a.u_out + (long)sys * a.ld_out, a.M, V);
 }
 

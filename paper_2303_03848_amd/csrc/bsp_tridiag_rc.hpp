@@ -44,8 +44,10 @@ constexpr double kPcrTruncationRc = 8.673617379884035e-19;  // 2^-60
 
 // Scaled closed-form row coefficients of thread p's chunk (grid index
 // j = J + q of row q, J = p MC + 1): A'(j) = j (c2 j + c1), C'(j) = j (c2 j - c1).
-// The sweeps walk j up or down by one (exact: j is an integer), so a
-// coefficient costs an add, an FMA and a multiply.
+// A sweep walks them by their differences (second differences are the
+// constant 2 c2): up the chunk from A'_0, A'_1 - A'_0, down it from
+// C'_{NI-1}, C'_{NI-1} - C'_{NI-2}, two adds per row.  The set-up takes the
+// same walks, so the pivots and the steps see bitwise the same coefficients.
 struct RcRows {
     double c2, c1, J;
     // pad: a chunk wholly outside the grid (identity rows: no couplings)
@@ -57,12 +59,31 @@ struct RcRows {
     }
     __device__ __forceinline__ double A(double j) const { return j * fma(c2, j, c1); }
     __device__ __forceinline__ double C(double j) const { return j * fma(c2, j, -c1); }
-    __device__ __forceinline__ double Aq(int q) const { return A(J + (double)q); }
-    __device__ __forceinline__ double Cq(int q) const { return C(J + (double)q); }
+    // A'_0 and A'_1 - A'_0; next row: a += da, da += 2 c2
+    __device__ __forceinline__ void startA(double& a, double& da) const {
+        a = A(J);
+        da = fma(c2, fma(2.0, J, 1.0), c1);
+    }
+    __device__ __forceinline__ void upA(double& a, double& da) const {
+        a += da;
+        da = fma(2.0, c2, da);
+    }
+    // C'_{n} and C'_{n} - C'_{n-1} for row n; next row down: c -= dc, dc -= 2 c2
+    __device__ __forceinline__ void startC(int n, double& c, double& dc) const {
+        const double jt = J + (double)n;
+        c = C(jt);
+        dc = fma(c2, fma(2.0, jt, -1.0), -c1);
+    }
+    __device__ __forceinline__ void downC(double& c, double& dc) const {
+        c -= dc;
+        dc = fma(-2.0, c2, dc);
+    }
 };
 
+// Factorisation and interface data of one block (set-up); the steps are in
+// BlockTriR below.
 template <int T, int MC, bool HI>
-struct BlockTriR {
+struct RcFact {
     static constexpr int LOGT = ilog2(T);
     static constexpr int NI = MC - 1;
     static_assert(MC >= 4, "chunks of at least four rows");
@@ -75,10 +96,6 @@ struct BlockTriR {
     double Ar, Br, Cr;  // reduced interface row after kRcRegStages stages
     int p, nst, zq;
 
-    __device__ __forceinline__ double Cz(const RcRows& rw, double j, int q) const {
-        const double c = rw.C(j);
-        return (HI && q == zq) ? 0.0 : c;
-    }
 
     // Factorisation, responses and interface reduction for one (option,
     // theta, dt); h = theta*dt > 0, e = (1-theta)*dt.  Whole block.
@@ -94,7 +111,24 @@ struct BlockTriR {
         rows.init(s2, r, h, kap, p, MC, pad);
         const bool owner = p == (M - 1) / MC;
         zq = (HI && owner) ? (M - 1) % MC : -1;
-        auto Cs = [&](int q) { return (i0 + q == M - 1) ? 0.0 : rows.Cq(q); };
+        // the sweeps' coefficients: A'_q up the chunk, C'_q down it
+        double Aw[NI], Cw[NI];
+        {
+            double a, da, c, dc;
+            rows.startA(a, da);
+            Aw[0] = a;
+            for (int q = 1; q < NI; ++q) {
+                rows.upA(a, da);
+                Aw[q] = a;
+            }
+            rows.startC(NI - 1, c, dc);
+            Cw[NI - 1] = c;
+            for (int q = NI - 2; q >= 0; --q) {
+                rows.downC(c, dc);
+                Cw[q] = c;
+            }
+        }
+        auto Cs = [&](int q) { return (i0 + q == M - 1) ? 0.0 : Cw[q]; };
         auto Bs = [&](int q) {
             const double j = (double)(i0 + q + 1);
             return (pad ? 1.0 : fma(h, fma(s2 * j, j, r), 1.0)) / kap;
@@ -104,20 +138,20 @@ struct BlockTriR {
         double kp = 1.0 / Bs(0);
         kuc[0] = kp;
         for (int q = 1; q < NI; ++q) {
-            const double l = rows.Aq(q) * kp;
+            const double l = Aw[q] * kp;
             kp = 1.0 / fma(-l, Cs(q - 1), Bs(q));
             kuc[q * T] = kp;
         }
         ku = ku_lds;
         // end values of the responses v (to the left interface value) and w
         // (to the right one), by the step's correction sweeps
-        a0s = (i0 == 0) ? 0.0 : rows.Aq(0);
+        a0s = (i0 == 0) ? 0.0 : Aw[0];
         cNI = Cs(NI - 1);
         double vlast, wlast, vfirst, wfirst;
         {
             double g[NI];
             g[0] = -a0s;
-            for (int q = 1; q < NI; ++q) g[q] = -(rows.Aq(q) * kuc[(q - 1) * T]) * g[q - 1];
+            for (int q = 1; q < NI; ++q) g[q] = -(Aw[q] * kuc[(q - 1) * T]) * g[q - 1];
             double vv = kuc[(NI - 1) * T] * g[NI - 1];
             double ww = kuc[(NI - 1) * T] * -cNI;
             vlast = vv;
@@ -132,9 +166,9 @@ struct BlockTriR {
 
         // interface row i = i0 + MC - 1 (unscaled coefficients)
         const int i = i0 + MC - 1;
-        aq = kap * rows.Aq(MC - 1);
+        aq = kap * rows.A(rows.J + (double)(MC - 1));
         const double bq = kap * Bs(MC - 1);
-        cq = (i == M - 1) ? 0.0 : kap * rows.Cq(MC - 1);
+        cq = (i == M - 1) ? 0.0 : kap * rows.C(rows.J + (double)(MC - 1));
         lds[p] = vfirst;
         lds[T + p] = wfirst;
         __syncthreads();
@@ -204,6 +238,104 @@ struct BlockTriR {
         __syncthreads();  // lds is scratch of the steps from here on
     }
 
+};
+
+// The steps.  CN: Crank-Nicolson (kappa = 2, mu = 1 as constants).  SLOW:
+// the interface reduction needs more than kRcRegStages stages (the kernel
+// picks this instance when the set-up found so).
+template <int T, int MC, bool HI, bool CN, bool SLOW>
+struct BlockTriR : RcFact<T, MC, HI> {
+    using F = RcFact<T, MC, HI>;
+    using F::NI;
+    using F::ku;
+    using F::fc;
+    using F::rows;
+    using F::aq;
+    using F::cq;
+    using F::invB;
+    using F::kap;
+    using F::mu;
+    using F::a0s;
+    using F::cNI;
+    using F::k1;
+    using F::k2;
+    using F::Ar;
+    using F::Br;
+    using F::Cr;
+    using F::p;
+    using F::nst;
+    using F::zq;
+    __device__ __forceinline__ explicit BlockTriR(const F& f) : F(f) {}
+
+    // Pivot reads kPD rows ahead of their use (a ring of registers), so the
+    // sweeps wait on LDS latency once per sweep instead of once per row pair.
+    // Reads go in pairs of adjacent rows (one two-address LDS read each, whose
+    // offsets reach every row without address arithmetic).
+    static constexpr int kPD = NI >= 8 ? 8 : (NI & ~1);
+    static_assert(NI >= 3, "paired pivot reads");
+
+    // Forward sweep over rows 1..NI-1 with l_q = A'_q kappa/u_{q-1}:
+    // body(q, l).  Returns kappa/u_{NI-1}.
+    // Pivot of row q from two column bases (rows 0..15 and 16.. of this
+    // thread's column), so every read's LDS offset fits the instruction.
+    struct Col {
+        const double* lo;
+        const double* hi;
+        __device__ __forceinline__ double operator[](int q) const {
+            return q < 16 ? lo[q * T] : hi[(q - 16) * T];
+        }
+    };
+    __device__ __forceinline__ Col col() const {
+        int a = p, b = p + 16 * T;
+        asm volatile("" : "+v"(a), "+v"(b));  // opaque: see step()
+        return Col{ku + a, ku + b};
+    }
+
+    template <class Body>
+    __device__ __forceinline__ double forward(const RcRows& rw, const Col& kuc,
+                                              Body&& body) const {
+        double kr[kPD];
+#pragma unroll
+        for (int i = 0; i < kPD; ++i) kr[i] = kuc[i];
+        double a, da;
+        rw.startA(a, da);
+#pragma unroll
+        for (int q = 1; q < NI; ++q) {
+            const double kprev = kr[(q - 1) % kPD];
+            if ((q - 1) & 1) {  // rows q-2, q-1 consumed: their slots take rows q-2+kPD, q-1+kPD
+                if (q - 2 + kPD < NI) kr[(q - 2) % kPD] = kuc[q - 2 + kPD];
+                if (q - 1 + kPD < NI) kr[(q - 1) % kPD] = kuc[q - 1 + kPD];
+            }
+            rw.upA(a, da);
+            body(q, a * kprev);
+        }
+        return kr[(NI - 1) % kPD];
+    }
+
+    // Backward sweep over rows NI-2..0: body(q, C'_q, kappa/u_q).
+    template <class Body>
+    __device__ __forceinline__ void backward(const RcRows& rw, const Col& kuc,
+                                             Body&& body) const {
+        constexpr int PB = NI - 1 >= kPD ? kPD : ((NI - 1) & ~1);
+        static_assert(PB >= 2, "paired pivot reads");
+        double kr[PB];
+#pragma unroll
+        for (int i = 0; i < PB; ++i) kr[i] = kuc[NI - 2 - i];
+        double c, dc;
+        rw.startC(NI - 1, c, dc);
+#pragma unroll
+        for (int e = 0; e < NI - 1; ++e) {  // q = NI-2-e
+            const int q = NI - 2 - e;
+            const double kq = kr[e % PB];
+            if (e & 1) {  // rows of e-1, e consumed: their slots take the rows PB further down
+                if (e - 1 + PB < NI - 1) kr[(e - 1) % PB] = kuc[q + 1 - PB];
+                if (e + PB < NI - 1) kr[e % PB] = kuc[q - PB];
+            }
+            rw.downC(c, dc);
+            body(q, (HI && q == zq) ? 0.0 : c, kq);
+        }
+    }
+
     // One step V <- A^{-1}(kappa V + f) - mu V (see BlockTri::step).  Pass 1:
     // forward and backward sweep of the interior rows with zero interface
     // values (y), interface reduction; pass 2: forward and backward sweep of
@@ -212,38 +344,26 @@ struct BlockTriR {
     template <bool EX>
     __device__ __forceinline__ void step(double (&V)[MC], double flo, double fhi,
                                          double* lds) const {
-        // Opaque per step: the row coefficients and the pivot reads are the
-        // same every step, and hoisting them out of the step loop would take
-        // 2 x 31 doubles of registers per thread (the footprint this solver
-        // avoids); recomputing and rereading them is what it is built for.
+        // Opaque per sweep: the row coefficients and the pivot reads are the
+        // same every step; hoisting them out of the step loop, or keeping
+        // them from one sweep to the next, would take 2 x 31 doubles of
+        // registers per thread (the footprint this solver avoids).
+        // Recomputing and rereading them is what it is built for.
+        const double kap_ = CN ? 2.0 : kap, mu_ = CN ? 1.0 : mu;
         RcRows rw = rows;
-        int col = p;
-        asm volatile("" : "+v"(rw.c2), "+v"(rw.c1), "+v"(rw.J), "+v"(col));
-        const double* kuc = ku + col;
+        asm volatile("" : "+v"(rw.c2), "+v"(rw.c1), "+v"(rw.J));
         double d[MC];
         fc.rhs(V, flo, fhi, d);
-        double kum = kuc[0];
-        double j = rw.J;
-#pragma unroll
-        for (int q = 1; q < NI; ++q) {
-            j += 1.0;
-            const double l = rw.A(j) * kum;
-            kum = kuc[q * T];
+        const double kum = forward(rw, col(), [&](int q, double l) {
             d[q] = fma(-l, d[q - 1], d[q]);
-        }
+        });
         double y = d[NI - 1] * kum;
         const double yl = y;
-        V[NI - 1] = EX ? fma(-mu, V[NI - 1], y) : y;
-        // the backward sweep reads the pivots again (not kept from the forward one)
-        int colb = p;
-        asm volatile("" : "+v"(colb));
-        const double* kucb = ku + colb;
-#pragma unroll
-        for (int q = NI - 2; q >= 0; --q) {
-            j -= 1.0;
-            y = kucb[q * T] * fma(-Cz(rw, j, q), y, d[q]);
-            V[q] = EX ? fma(-mu, V[q], y) : y;
-        }
+        V[NI - 1] = EX ? fma(-mu_, V[NI - 1], y) : y;
+        backward(rw, col(), [&](int q, double c, double kq) {
+            y = kq * fma(-c, y, d[q]);
+            V[q] = EX ? fma(-mu_, V[q], y) : y;
+        });
         // interface rows: y_0 of the next chunk, then the reduced system
         double* ybuf = lds;
         double* pb0 = lds + T;
@@ -252,8 +372,8 @@ struct BlockTriR {
         ybuf[p] = y;
         __syncthreads();
         const double yF = (p + 1 < T) ? ybuf[p + 1] : 0.0;
-        double D = fma(kap, V[MC - 1], fma(fc.bhiD, fhi, fma(-aq, yl, -cq * yF)));
-        const double rz = EX ? -mu * V[MC - 1] : 0.0;
+        double D = fma(kap_, V[MC - 1], fma(fc.bhiD, fhi, fma(-aq, yl, -cq * yF)));
+        const double rz = EX ? -mu_ * V[MC - 1] : 0.0;
 #pragma unroll
         for (int k = 0; k < kRcRegStages; ++k) {
             if (k < nst) {
@@ -266,7 +386,7 @@ struct BlockTriR {
                 D = fma(-k1[k], Dm, fma(-k2[k], Dp, D));
             }
         }
-        if (nst > kRcRegStages) {
+        if constexpr (SLOW) {
             // stiff steps: the reduced coefficients travel with D and the
             // multipliers are recomputed (the set-up's operations exactly)
             double A_ = Ar, B_ = Br, C_ = Cr;
@@ -308,32 +428,19 @@ struct BlockTriR {
         const double zl = (p > 0) ? zbuf[p - 1] : 0.0;
         // pass 2: the interior rows' correction for the interface values
         RcRows r2 = rows;
-        int col2 = p;
-        asm volatile("" : "+v"(r2.c2), "+v"(r2.c1), "+v"(r2.J), "+v"(col2));
-        const double* kub = ku + col2;
+        asm volatile("" : "+v"(r2.c2), "+v"(r2.c1), "+v"(r2.J));
         double t = -a0s * zl;
         d[0] = t;
-        kum = kub[0];
-        j = r2.J;
-#pragma unroll
-        for (int q = 1; q < NI; ++q) {
-            j += 1.0;
-            const double l = r2.A(j) * kum;
-            kum = kub[q * T];
+        const double kum2 = forward(r2, col(), [&](int q, double l) {
             t = -l * t;
             d[q] = t;
-        }
-        t = kum * fma(-cNI, z, d[NI - 1]);
+        });
+        t = kum2 * fma(-cNI, z, d[NI - 1]);
         V[NI - 1] += t;
-        int col2b = p;
-        asm volatile("" : "+v"(col2b));
-        const double* kubb = ku + col2b;
-#pragma unroll
-        for (int q = NI - 2; q >= 0; --q) {
-            j -= 1.0;
-            t = kubb[q * T] * fma(-Cz(r2, j, q), t, d[q]);
+        backward(r2, col(), [&](int q, double c, double kq) {
+            t = kq * fma(-c, t, d[q]);
             V[q] += t;
-        }
+        });
         V[MC - 1] = z + rz;
     }
 };

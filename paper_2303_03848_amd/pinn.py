@@ -9,9 +9,9 @@ optimiser (Adam, as in the paper) and device memory.
 
 Training recipe (Sec. 3.3): fixed sets of uniformly drawn collocation points
 (interior, terminal, boundary), reshuffled every epoch and taken in
-minibatches; Adam with a learning rate of 1e-2, then 1e-3.  The step counts
-are parameters (the paper's 5000 + 800 epochs are the defaults of
-``train``; the benchmark uses a shorter schedule).
+minibatches (an epoch is one pass over the sets: 8 minibatches of 8192 / 512 /
+256 points for the default sets); Adam with a learning rate of 1e-2, then
+1e-3, for the paper's 5000 + 800 epochs by default.
 """
 from __future__ import annotations
 
@@ -49,10 +49,11 @@ def pinn_loss(params: torch.Tensor, spec, p: dict, X_f, X_e, X_b, ws=None):
 
 def train(p: dict, n_in: int, depth: int, width: int, precision: int = bsp.PREC_FP32,
           n_f: int = 65536, n_e: int = 4096, n_b: int = 2048, batch=(8192, 512, 256),
-          steps_hi: int = 5000, steps_lo: int = 800, lr_hi: float = 1e-2, lr_lo: float = 1e-3,
+          epochs_hi: int = 5000, epochs_lo: int = 800, lr_hi: float = 1e-2, lr_lo: float = 1e-3,
           seed: int = SEED, init_seed: int = 0, coeff_box=None, log_every: int = 0):
     """Train a network on the option `p` (or, with coeff_box, on a box of
-    (sigma, r)); returns (PinnNet, info dict).  Steps count minibatches."""
+    (sigma, r)) for epochs_hi epochs at lr_hi, then epochs_lo at lr_lo;
+    returns (PinnNet, info dict)."""
     dev = torch.device("cuda")
     x_max = p["s_max"] / p["K"]
     Xf, Xe, Xb = collocation(n_f, n_e, n_b, p["T"], x_max, seed=seed, coeff_box=coeff_box)
@@ -65,9 +66,10 @@ def train(p: dict, n_in: int, depth: int, width: int, precision: int = bsp.PREC_
     opt = torch.optim.Adam([params], lr=lr_hi)
     nb_f, nb_e, nb_b = batch
     per_epoch = min(n_f // nb_f, n_e // nb_e, n_b // nb_b)
+    steps_hi = epochs_hi * per_epoch
+    total_steps = (epochs_hi + epochs_lo) * per_epoch
     t0 = time.time()
     step, epoch, hist = 0, 0, []
-    total_steps = steps_hi + steps_lo
     while step < total_steps:
         idx_f = minibatch_indices(n_f, nb_f, epoch, seed)
         idx_e = minibatch_indices(n_e, nb_e, epoch, seed + 1)
@@ -98,22 +100,12 @@ def train(p: dict, n_in: int, depth: int, width: int, precision: int = bsp.PREC_
     return bsp.PinnNet(params.data.clone(), *spec), info
 
 
-def train_call_network(cfg: dict, steps_hi: int = 6000, steps_lo: int = 4000,
+def train_call_network(cfg: dict, epochs_hi: int = 5000, epochs_lo: int = 800,
                        precision_train: int = bsp.PREC_FP32, precision_eval: int = bsp.PREC_BF16):
-    """The network coarse of the benchmark workload: trained on that call
+    """The network coarse of the 1024-node call workload: trained on that call
     (FP32 training), evaluated with `precision_eval`."""
     p = option_params(cfg)
     net, info = train(p, cfg["n_in"], cfg["depth"], cfg["width"], precision_train,
-                      steps_hi=steps_hi, steps_lo=steps_lo)
+                      epochs_hi=epochs_hi, epochs_lo=epochs_lo)
     net.precision = precision_eval
     return net, {k: v for k, v in info.items() if k != "history"}
-
-
-def grid_values(net: bsp.PinnNet, p: dict, M: int, N: int) -> torch.Tensor:
-    """The network's dimensionless prediction v(tau_n, S_j / K) on the Parareal
-    grid, shape [N+1, M] (tau_n = n T / N, S_j = j S_max / (M+1))."""
-    S = (np.arange(1, M + 1) * (p["s_max"] / (M + 1))) / p["K"]
-    taus = np.arange(N + 1) * (p["T"] / N)
-    T, X = np.meshgrid(taus, S, indexing="ij")
-    X = torch.tensor(np.stack([T.ravel(), X.ravel()], 1), dtype=torch.float32, device="cuda")
-    return bsp.pinn_forward(net, X).reshape(N + 1, M)

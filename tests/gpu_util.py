@@ -21,3 +21,13 @@ def to_dev(a, dtype=torch.float64):
 
 def say(*args):
     print(*args, flush=True)
+
+
+def network_grid(bsp, net, p, M, N):
+    """The library's network values v(tau_n, S_j / K) on the Parareal grid,
+    [N+1, M] float64 (pinn_forward on inputs built here)."""
+    S = (np.arange(1, M + 1) * (p["s_max"] / (M + 1))) / p["K"]
+    taus = np.arange(N + 1) * (p["T"] / N)
+    T, X = np.meshgrid(taus, S, indexing="ij")
+    X = torch.tensor(np.stack([T.ravel(), X.ravel()], 1), dtype=torch.float32, device="cuda")
+    return bsp.pinn_forward(net, X).double().reshape(N + 1, M).cpu().numpy()

@@ -36,7 +36,7 @@ import torch
 import oracle
 import paper_2303_03848_amd as bsp
 from oracle import mlp
-from tests.gpu_util import cuda, normwise, say, to_dev
+from tests.gpu_util import cuda, network_grid, normwise, say, to_dev
 from tests.oracle_jobs import oracle_result
 from workloads import (LARGE_PUT, OPTION_BATCH, PINN_CALL, option_batch, option_params,
                        perturbed, xavier_normal)
@@ -107,8 +107,7 @@ def test_call_trained_network(prec):
     ref = oracle.parareal(po, M, N, Sf, 1, oracle.COARSE_PINN_IE, Vt=Vt, tol=tol, nthreads=8)
     ie = oracle.parareal(po, M, N, Sf, 1, oracle.COARSE_IE, tol=tol, nthreads=8)
     # the network's own error on the Parareal grid, price units (levels n >= 1)
-    from paper_2303_03848_amd.pinn import grid_values
-    vt_gpu = grid_values(net, option_params(cfg), M, N).double().cpu().numpy() * po.K
+    vt_gpu = network_grid(bsp, net, option_params(cfg), M, N) * po.K
     err_gpu = float(np.max(np.abs(vt_gpu[1:] - ser[1:])))
     err_ora = float(np.max(np.abs(Vt[1:] - ser[1:])))
     name = "bf16" if prec == bsp.PREC_BF16 else "fp32"

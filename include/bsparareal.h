@@ -215,8 +215,12 @@ int parareal_iterate(const bs_params* prm, const bs_grid* grid, const bs_slices*
  * thread and the sweep on `stream`, which is joined with them before
  * returning.  The launches synchronise through progress counters in ws;
  * every wait also ends on the stop flag, and after about 2 s the solve
- * fails with BS_ERR_HIP.  Beyond 4096 nodes the iterations run one after
- * the other. */
+ * fails with BS_ERR_HIP.  Beyond 4096 nodes (block shapes of 512 threads)
+ * with 2 <= N <= 256: iteration 1's fine launch, then one launch in which
+ * one block runs the sweeps of all iterations and one block per slice n >= 1
+ * the fine work of iterations 2, 3, ... (when the device holds all N blocks
+ * at once; another kernel occupying compute units meanwhile makes the waits
+ * time out: BS_ERR_HIP); otherwise the iterations run one after the other. */
 int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,
                    int coarse_kind, double tol, const pinn_net* net, int max_iter, void* ws,
                    size_t ws_bytes, double* U, int* iters, double* defect_hist, void* stream);
@@ -290,12 +294,16 @@ int bs_tune_reset(void);
 /* Kernel timing of the Parareal iteration, for measurement.
  * bs_profile_enable(1) resets the counters and makes parareal_iterate /
  * parareal_solve record HIP events on their stream around each launch of the
- * fine-propagator kernel and of the sweep kernel; bs_profile_enable(0) stops
- * recording.  Timing adds no synchronisation beyond the per-iteration one.
- * bs_profile_read fills out[6] (host) with: total fine-kernel milliseconds,
- * number of fine launches, fine cell-updates launched (systems x steps x M),
- * total sweep milliseconds, number of sweep launches, 0.  Process-wide, not
- * thread-safe: for a single measuring thread. */
+ * fine-propagator kernel, of the sweep kernel and of the one-launch solve
+ * kernels; bs_profile_enable(0) stops recording.  Timing adds no
+ * synchronisation beyond the per-iteration one.
+ * bs_profile_read fills out[8] (host) with: total fine-kernel milliseconds,
+ * number of fine launches, fine cell-updates of those launches (systems x
+ * steps x M), total sweep milliseconds, number of sweep launches, total
+ * milliseconds of one-launch solve kernels (fine work and sweeps of several
+ * iterations in one launch), their number, and the fine cell-updates of the
+ * iterations they ran.  Process-wide, not thread-safe: for a single
+ * measuring thread. */
 int bs_profile_enable(int on);
 int bs_profile_read(double* out);
 

@@ -311,10 +311,11 @@ def bs_profile_enable(on: bool = True):
 
 
 def bs_profile_read() -> dict:
-    out = (ctypes.c_double * 6)()
+    out = (ctypes.c_double * 8)()
     _check(load_library().bs_profile_read(out))
     return {"fine_ms": out[0], "fine_launches": int(out[1]), "fine_cells": out[2],
-            "sweep_ms": out[3], "sweep_launches": int(out[4])}
+            "sweep_ms": out[3], "sweep_launches": int(out[4]), "solve_ms": out[5],
+            "solve_launches": int(out[6]), "solve_cells": out[7]}
 
 
 def parareal_solve_noalloc(p: dict, M: int, N: int, fine_steps: int, coarse_steps: int = 1,

@@ -160,6 +160,7 @@ struct Profile {
     bool on = false;
     std::vector<hipEvent_t> ev;
     double fine_ms = 0, fine_launches = 0, fine_cells = 0, sweep_ms = 0, sweep_launches = 0;
+    double solve_ms = 0, solve_launches = 0, solve_cells = 0;  // one-launch solve kernels
 };
 static Profile g_prof;
 
@@ -237,6 +238,7 @@ int bs_profile_enable(int on) {
     if (on) {
         g_prof.fine_ms = g_prof.fine_launches = g_prof.fine_cells = 0;
         g_prof.sweep_ms = g_prof.sweep_launches = 0;
+        g_prof.solve_ms = g_prof.solve_launches = g_prof.solve_cells = 0;
     }
     return BS_OK;
 }
@@ -259,7 +261,9 @@ int bs_profile_read(double* out) {
     out[2] = g_prof.fine_cells;
     out[3] = g_prof.sweep_ms;
     out[4] = g_prof.sweep_launches;
-    out[5] = 0;
+    out[5] = g_prof.solve_ms;
+    out[6] = g_prof.solve_launches;
+    out[7] = g_prof.solve_cells;
     return BS_OK;
 }
 
@@ -511,9 +515,104 @@ static int solve_persistent(const bs_params* prm, const bs_grid* grid, const bs_
     if (prof) {
         float ms = 0.f;
         BSP_HIP(hipEventElapsedTime(&ms, g_prof.ev[0], g_prof.ev[1]));
-        g_prof.fine_ms += ms;
+        g_prof.solve_ms += ms;
+        g_prof.solve_launches += 1;
+        for (int k = 1; k <= last; ++k) g_prof.solve_cells += iteration_cells(grid, sl, k);
+    }
+    if (status == BS_ERR_NONFINITE)
+        set_error("non-finite value in the Parareal state at iteration %d", last);
+    else if (status == BS_ERR_DIVERGED)
+        set_error("Parareal diverging: defect of iteration %d above %g x the first", last, growth);
+    return status;
+}
+
+// Overlapped solve of a grid beyond 4096 nodes (k_large_persist): initial
+// state, network grid and prediction, iteration 1's fine launch over every
+// slice, then one launch for the sweeps of all iterations beside the fine
+// work of iterations 2, 3, ...; the host reads the per-iteration record once
+// the stream has drained.  The stop flag must already be clear on st.
+static int solve_large(const bs_params* prm, const bs_grid* grid, const bs_slices* sl, int kind,
+                       double tol, double growth, const pinn_net* net, int kmax, void* ws,
+                       double* U, int* iters, double* defect_hist, hipStream_t st) {
+    int rc;
+    const int M = grid->M, N = sl->N;
+    SolveState& S = t_solve;
+    for (size_t i = 0; i < 2 * (size_t)(kmax + 1); ++i) S.hist[i] = -1.0;  // not reached
+    Workspace w = ws_layout(ws, M, N, kind);
+    const PipeSync ps = pipe_sync(w, N);
+    int* stop = reinterpret_cast<int*>(w.result + 4);
+    if ((rc = launch_fill_int(w.flags, flag_count(N), 0, st))) return rc;
+    if ((rc = start_impl(prm, grid, sl, kind, net, ws, U, nullptr, st))) return rc;
+    const OptionDev o = make_option(*prm, M);
+    const double dT = prm->T / N;
+    const bool prof = g_prof.on;
+    // iteration 1: F on every slice, one launch
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[0], st));
+    if ((rc = launch_theta_batch(o, M, N, nullptr, 0.0, dT, 0, dT / sl->fine_steps,
+                                 sl->fine_steps, 0.5, 0, U, M, w.Fv, M, st, stop, nullptr)))
+        return rc;
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[1], st));
+    // every U[n] holds iterate 0 and every Fv[n] iteration 1's result, read
+    // from U[n]: the counters as the overlapped launches would have left them
+    if ((rc = launch_fill_int(ps.ready, N + 1, 1, st))) return rc;
+    if ((rc = launch_fill_int(ps.taken, N + 1, 1, st))) return rc;
+    if ((rc = launch_fill_int(ps.fdone, N, 1, st))) return rc;
+    LargePersistArgs a{};
+    if ((rc = launch_large_sweep_tables(o, M, dT, sl->coarse_steps, &a.tab, &a.ptab, st)))
+        return rc;
+    a.o = o;
+    a.M = M;
+    a.N = N;
+    a.kmax = kmax;
+    a.fine_steps = sl->fine_steps;
+    a.coarse_steps = sl->coarse_steps;
+    a.kind = kind;
+    a.dT = dT;
+    a.tol = tol;
+    a.growth = growth;
+    a.U = U;
+    a.Fv = w.Fv;
+    a.Gold = w.Gold;
+    a.Vt = w.Vt;
+    a.result = w.result;
+    a.stop = stop;
+    a.hist = S.hist_dev;
+    a.ps = ps;
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[2], st));
+    if ((rc = launch_large_persist(a, st))) return rc;
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[3], st));
+    int err = 0;
+    BSP_HIP(hipMemcpyAsync(&err, ps.err, sizeof(int), hipMemcpyDeviceToHost, st));
+    BSP_HIP(hipStreamSynchronize(st));
+    if (err) {
+        set_error("overlapped Parareal solve: a wait exceeded its time limit");
+        return BS_ERR_HIP;
+    }
+    const volatile double* hist = S.hist;
+    int status = BS_NOT_CONVERGED, last = 0;
+    for (int j = 1; j <= kmax; ++j) {
+        const double d = hist[2 * j], flag = hist[2 * j + 1];
+        if (d < 0.0) break;  // not reached
+        if (defect_hist) defect_hist[j - 1] = d;
+        last = j;
+        if ((status = record_status(flag)) != BS_OK) break;
+        if (d <= tol || j == N) {
+            status = BS_OK;
+            break;
+        }
+        status = BS_NOT_CONVERGED;
+    }
+    *iters = last;
+    if (prof) {
+        float f_ms = 0.f, p_ms = 0.f;
+        BSP_HIP(hipEventElapsedTime(&f_ms, g_prof.ev[0], g_prof.ev[1]));
+        BSP_HIP(hipEventElapsedTime(&p_ms, g_prof.ev[2], g_prof.ev[3]));
+        g_prof.fine_ms += f_ms;
         g_prof.fine_launches += 1;
-        for (int k = 1; k <= last; ++k) g_prof.fine_cells += iteration_cells(grid, sl, k);
+        g_prof.fine_cells += iteration_cells(grid, sl, 1);
+        g_prof.solve_ms += p_ms;
+        g_prof.solve_launches += 1;
+        for (int k = 2; k <= last; ++k) g_prof.solve_cells += iteration_cells(grid, sl, k);
     }
     if (status == BS_ERR_NONFINITE)
         set_error("non-finite value in the Parareal state at iteration %d", last);
@@ -559,6 +658,11 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
     if (persist_capable(grid->M, N))
         return solve_persistent(prm, grid, sl, kind, tol, growth, net, kmax, ws, U, iters,
                                 defect_hist, S.hist_dev, S.hist, true, g_prof.on, st);
+    if (large_persist_capable(grid->M, N)) {
+        if (g_prof.on && (rc = prof_reserve(1))) return rc;
+        return solve_large(prm, grid, sl, kind, tol, growth, net, kmax, ws, U, iters,
+                           defect_hist, st);
+    }
 
     // Overlapped iterations (grids the one-block sweep and the per-system
     // fine kernel cover): the fine launch of iteration k runs on a side

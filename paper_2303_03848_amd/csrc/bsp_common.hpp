@@ -267,6 +267,30 @@ struct PersistArgs {
     PipeSync ps;
     double growth;    // divergence guard, as in SweepArgs
 };
+// Overlapped solve of a grid beyond 4096 nodes (see k_large_persist): after
+// iteration 1's fine launch, one launch runs the sweeps of every iteration in
+// one block and the fine work of iterations 2, 3, ... in one block per slice
+// n >= 1.  The sweep's coefficient tables (tab, ptab) are built beforehand.
+struct LargePersistArgs {
+    OptionDev o;
+    int M, N, kmax, fine_steps, coarse_steps, kind;
+    double dT, tol, growth;
+    double* U;
+    double* Fv;
+    double* Gold;
+    const double* Vt;
+    double* result;
+    int* stop;
+    double* hist;  // per-iteration record [2 (kmax+1)] (host-mapped or device)
+    PipeSync ps;
+    const double* tab;
+    const double* ptab;
+};
+bool large_persist_capable(int M, int N);
+int launch_large_persist(const LargePersistArgs& a, hipStream_t stream);
+int launch_large_sweep_tables(const OptionDev& o, int M, double dT, int coarse_steps,
+                              const double** tab, const double** ptab, hipStream_t stream);
+
 // The one-launch solve can cover this problem size (block shapes aside).
 constexpr int kPersistMaxN = 512, kPersistMaxM = 1024;
 inline bool persist_possible(int M, int N) { return M <= kPersistMaxM && N <= kPersistMaxN; }

@@ -351,7 +351,7 @@ bool persist_capable(int M, int N) {
 // Resident-block capacity of one kernel on the current device (blocks per
 // compute unit x compute units), queried once per device.
 static int resident_blocks(const void* fn, int threads, int slot) {
-    static int cache[16][4] = {};
+    static int cache[16][8] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 0;
     if (cache[dev][slot]) return cache[dev][slot];
@@ -502,6 +502,179 @@ static int launch_large_setup(const OptionDev& o, int M, double h, double e, dou
                        ptab);
     BSP_LAUNCHED();
     return BS_OK;
+}
+
+// ------------------------------------------ overlapped large-grid solve
+
+// One launch for iterations 1.. of a solve on a grid beyond 4096 nodes, after
+// iteration 1's fine launch (k_rc_theta over all slices).  Block N-1 sweeps:
+// iterations k = 1, 2, ... one after the other, slice by slice, each slice as
+// soon as its fine result of iteration k is written.  Blocks 0 .. N-2 are the
+// fine blocks: block b owns slice n = b + 1 and propagates it for iterations
+// k = 2 .. min(kmax, n + 1) (slice n is exact from iteration n + 1 on), each
+// as soon as the sweep of iteration k-1 has produced its initial value.  So
+// the sweep of iteration k runs beside the fine work of iteration k + 1 and
+// an iteration costs about one fine propagation instead of one plus a sweep.
+// Hand-offs go through the progress counters of PipeSync (ready: U[n] holds
+// iterate j, stored as j + 1; taken: the fine block of iteration k has read
+// U[n]; fdone: Fv[n] holds iteration k's result), exactly as in the solve
+// that overlaps launches on side streams; the iterates are those of the
+// one-iteration-at-a-time solve.  The fine blocks poll the stop flag every
+// kPollSteps steps.  Every block must be resident (N blocks, one per compute
+// unit): the host checks the device's capacity first.
+constexpr int kLargePersistMaxN = 256;
+
+template <int MC>
+constexpr int large_persist_lds() {  // doubles: the larger of the two roles
+    constexpr int T = 512;
+    constexpr int fine = (MC - 1) * T + 4 * T + 2 * kForceChunk;
+    constexpr int sweep = 2 * BlockTriG<T, MC>::LOGT * T + sweep_smem_doubles<T, MC>();
+    return fine > sweep ? fine : sweep;
+}
+
+template <int MC, bool HI>
+__device__ __forceinline__ void large_fine_role(const LargePersistArgs& a, int n, double* smem,
+                                                int* pslot) {
+    constexpr int T = 512;
+    double* kus = smem;
+    double* lds = smem + (MC - 1) * T;
+    double* ftab = lds + 4 * T;
+    const double dt = a.dT / (double)a.fine_steps;
+    RcFact<T, MC, HI> Fa;
+    Fa.setup(a.o.s2, a.o.r, 0.5 * dt, 0.5 * dt, a.M, kus, lds);
+    const bool slow = Fa.nst > kRcRegStages;  // the same in every thread
+    const double tau0 = (double)n * a.dT;
+    const int klast = min(a.kmax, n + 1);
+    const PipeSync& ps = a.ps;
+    for (int k = 2; k <= klast; ++k) {
+        if (!pipe_wait(ps, ps.ready + n, k, a.stop, pslot)) return;
+        double V[MC];
+        load_chunk<T, MC>(a.U + (long)n * a.M, a.M, V);
+        pipe_signal(ps.taken + n, k);  // the loads have completed (release fence)
+        const bool ok =
+            slow ? theta_steps<T, MC, true, BlockTriR<T, MC, HI, true, true>, true>(
+                       BlockTriR<T, MC, HI, true, true>(Fa), a.o, V, tau0, dt, a.fine_steps, 0.5,
+                       false, lds, ftab, a.stop)
+                 : theta_steps<T, MC, true, BlockTriR<T, MC, HI, true, false>, true>(
+                       BlockTriR<T, MC, HI, true, false>(Fa), a.o, V, tau0, dt, a.fine_steps,
+                       0.5, false, lds, ftab, a.stop);
+        if (!ok) return;
+        // Fv[n] of iteration k-1 has been used once the sweep of iteration k-1
+        // has written U[n+1]
+        if (!pipe_wait<false>(ps, ps.ready + n + 1, k, a.stop, pslot)) return;
+        store_chunk<T, MC>(a.Fv + (long)n * a.M, a.M, V);
+        pipe_signal(ps.fdone + n, k);
+    }
+}
+
+template <int MC>
+__device__ __forceinline__ void large_sweep_role(const LargePersistArgs& a, double* smem,
+                                                 int* pslot) {
+    constexpr int T = 512;
+    double* kst = smem;
+    double* lds = smem + 2 * BlockTriG<T, MC>::LOGT * T;
+    double* ftab = lds + 4 * T;
+    BlockTriG<T, MC> S;
+    S.load(a.tab, a.ptab, a.o.s2, a.o.r, a.dT / (double)a.coarse_steps, 0.0, a.M, kst);
+    for (int k = 1; k <= a.kmax; ++k) {
+        PipeSync ps = a.ps;
+        ps.k = k;
+        const int n0 = min(k - 1, a.N - 1);
+        double dmax = 0.0;
+        int bad = 0;
+        if (!sweep_slices<T, MC>(S, a.o, a.M, a.N, n0, a.coarse_steps, a.kind, false, a.dT, a.U,
+                                 a.U, a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad, ps, true, a.stop,
+                                 pslot))
+            return;
+        block_defect<T>(dmax, bad, lds);
+        if (threadIdx.x == 0) {
+            SweepArgs sa{};
+            sa.result = a.result;
+            sa.stop = a.stop;
+            sa.hist = a.hist;
+            sa.tol = a.tol;
+            sa.k = k;
+            sa.growth = a.growth;
+            sweep_record(sa, dmax, bad);
+        }
+        __syncthreads();
+        if (__syncthreads_or(threadIdx.x == 0 && pipe_load(a.stop) != 0)) return;
+    }
+}
+
+template <int MC, bool HI>
+__global__ __launch_bounds__(512) void k_large_persist(LargePersistArgs a) {
+    __shared__ double smem[large_persist_lds<MC>()];
+    __shared__ int pslot;
+    if ((int)blockIdx.x < (int)gridDim.x - 1)
+        large_fine_role<MC, HI>(a, (int)blockIdx.x + 1, smem, &pslot);
+    else
+        large_sweep_role<MC>(a, smem, &pslot);
+}
+
+// The kernel instance for grid M and its slot in the residency cache.
+static const void* large_persist_fn(int M, int& slot) {
+    const TriShape f = shape_for(0, M);
+    const bool hi = M % f.MC != 0;
+    if (f.MC == 16) {
+        slot = hi ? 4 : 5;
+        return hi ? (const void*)k_large_persist<16, true> : (const void*)k_large_persist<16, false>;
+    }
+    slot = hi ? 6 : 7;
+    return hi ? (const void*)k_large_persist<32, true> : (const void*)k_large_persist<32, false>;
+}
+
+// Shapes allow it, and the device holds all N blocks at once (they wait on
+// each other).
+bool large_persist_capable(int M, int N) {
+    const TriShape f = shape_for(0, M), w = shape_for(1, M);
+    if (!(is_large(f) && is_large(w) && f.MC == w.MC && N >= 2 && N <= kLargePersistMaxN))
+        return false;
+    int slot = 0;
+    const void* fn = large_persist_fn(M, slot);
+    return N <= resident_blocks(fn, 512, slot);
+}
+
+int launch_large_persist(const LargePersistArgs& a, hipStream_t stream) {
+    if (!large_persist_capable(a.M, a.N)) {
+        set_error("no overlapped large-grid solve for M = %d, N = %d", a.M, a.N);
+        return BS_ERR_ARG;
+    }
+    const TriShape f = shape_for(0, a.M);
+    const bool hi = a.M % f.MC != 0;
+    int slot = 0;
+    const void* fn = large_persist_fn(a.M, slot);
+    const int cap = resident_blocks(fn, 512, slot);
+    if (a.N > cap) {
+        set_error("overlapped large-grid solve needs %d resident blocks, the device holds %d",
+                  a.N, cap);
+        return BS_ERR_HIP;
+    }
+    const dim3 grid(a.N), block(512);
+    if (f.MC == 16) {
+        if (hi) hipLaunchKernelGGL((k_large_persist<16, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((k_large_persist<16, false>), grid, block, 0, stream, a);
+    } else {
+        if (hi) hipLaunchKernelGGL((k_large_persist<32, true>), grid, block, 0, stream, a);
+        else hipLaunchKernelGGL((k_large_persist<32, false>), grid, block, 0, stream, a);
+    }
+    BSP_LAUNCHED();
+    return BS_OK;
+}
+
+int launch_large_sweep_tables(const OptionDev& o, int M, double dT, int coarse_steps,
+                              const double** tab, const double** ptab, hipStream_t stream) {
+    double *t, *pt;
+    int rc = large_tables(1, &t, &pt);
+    if (rc) return rc;
+    const double h = dT / (double)coarse_steps;
+    if (shape_for(1, M).MC == 16)
+        rc = launch_large_setup<512, 16>(o, M, h, 0.0, t, pt, stream);
+    else
+        rc = launch_large_setup<512, 32>(o, M, h, 0.0, t, pt, stream);
+    *tab = t;
+    *ptab = pt;
+    return rc;
 }
 
 // ------------------------------------------------------------ dispatch

@@ -223,8 +223,8 @@ __device__ __forceinline__ bool piped_path(const Solver& S, int steps) {
     return false;
 }
 
-// Runs `steps` theta-steps on V.  POLL (one-wavefront solver only): stop early
-// when *stop is set, returning false.  prefilled: on the pipelined path the
+// Runs `steps` theta-steps on V.  POLL: check *stop every kPollSteps steps
+// and return false once it is set (the same decision in every thread).  prefilled: on the pipelined path the
 // first forcing table is already in ftab (fill_piped_table with m0 = 0).
 // WAVE: the calling wavefront works on this system alone (one-wavefront
 // solver, Crank-Nicolson or implicit Euler).
@@ -264,6 +264,7 @@ __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
 #undef BSP_RUN
     }
     const double h = theta * dt, e = (1.0 - theta) * dt;
+    int sv = 0;
     for (int m0 = 0; m0 < steps; m0 += kForceChunk) {
         const int nch = min(kForceChunk, steps - m0);
         if (!homog) {
@@ -281,6 +282,15 @@ __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
         double flo_n = homog ? 0.0 : ftab[0];
         double fhi_n = homog ? 0.0 : ftab[kForceChunk];
         for (int i = 0; i < nch; ++i) {
+            if constexpr (POLL) {
+                if (i % kPollSteps == 0) {  // the same decision in every thread of the system
+                    if (sv) return false;
+                    if constexpr (WAVE || T == 64)
+                        sv = __builtin_amdgcn_readfirstlane(pipe_load(stop));
+                    else
+                        sv = __syncthreads_or(pipe_load(stop) != 0);
+                }
+            }
             const double flo = flo_n, fhi = fhi_n;
             if (!homog && i + 1 < nch) {
                 flo_n = ftab[i + 1];

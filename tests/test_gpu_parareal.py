@@ -307,6 +307,54 @@ def test_overlapped_solve_multiwave(M, N, Sf, is_put, tol, max_iter):
         assert rc == bsp.BS_NOT_CONVERGED
 
 
+@pytest.mark.parametrize("M,N,Sf,is_put,kind,tol,max_iter", [
+    (5000, 6, 20, False, bsp.COARSE_IE, 1e-9, None),     # 16 nodes per thread, ragged grid
+    (8192, 5, 16, True, bsp.COARSE_IE, 0.0, None),       # grid a multiple of the chunk
+    (9000, 8, 12, False, bsp.COARSE_IE, 0.0, 3),         # 32 nodes per thread, max_iter cut
+    (6000, 7, 10, True, bsp.COARSE_PINN_IE, 0.0, None),  # network coarse
+    (4500, 64, 4, False, bsp.COARSE_IE, 1e-6, None),     # many slices, early stop
+])
+def test_overlapped_solve_large_grid(M, N, Sf, is_put, kind, tol, max_iter):
+    """Grids beyond 4096 nodes: iteration 1's fine launch, then one launch
+    with the sweeps of all iterations in one block beside the fine work of
+    iterations 2.. in one block per slice.  Bitwise the iterates, defects
+    and iteration count of the one-iteration-at-a-time path, and the
+    oracle's to the iterate tolerance."""
+    cuda()
+    say(f"overlapped large-grid solve M={M} N={N} Sf={Sf} put={is_put} kind={kind}")
+    cfg = dict(SMALL_CALL, M=M, N=N, fine_steps=Sf, is_put=is_put, n_in=2, depth=2, width=16)
+    p = option_params(cfg)
+    po = _oracle_params(cfg)
+    net, Vt = None, None
+    if kind != bsp.COARSE_IE:
+        th = _seeded_net(cfg, seed=4)
+        net = bsp.PinnNet(to_dev(th, torch.float32), 2, cfg["depth"], cfg["width"], bsp.PREC_FP32)
+        taus = np.arange(N + 1) * (po.T / N)
+        Vt = mlp.grid_values(th.astype(np.float64), 2, cfg["depth"], cfg["width"], po.K, taus,
+                             oracle.grid(po, M))
+    pr = bsp.Parareal(p, M, N, Sf, 1, kind, net)
+    for rep in range(2):  # the same workspace twice
+        iters, defects, rc = pr.solve(tol, max_iter=max_iter)
+        U = pr.U.cpu().numpy()
+        ref = bsp.Parareal(p, M, N, Sf, 1, kind, net)
+        ref.start()
+        d_ref = [ref.iterate(k) for k in range(1, iters + 1)]
+        assert np.array_equal(U, ref.U.cpu().numpy()), rep
+        assert defects == d_ref, rep
+    ora = oracle.parareal(po, M, N, Sf, 1, oracle.COARSE_IE if net is None else oracle.COARSE_PINN_IE,
+                          Vt=Vt, tol=tol, max_iter=max_iter)
+    if net is None:
+        assert iters == ora["iters"]
+    else:  # FP32 network grid against the oracle's FP64 one
+        assert abs(iters - ora["iters"]) <= 1
+    dt = p["T"] / (N * Sf)
+    bound = max(1e-11, 16 * np.finfo(float).eps * N * Sf * (1 + dt * (p["sigma"] * M) ** 2))
+    if net is None or tol == 0.0:
+        assert normwise(U, ora["U"]) <= bound
+    if max_iter is not None:
+        assert rc == bsp.BS_NOT_CONVERGED
+
+
 def _nan_net(cfg):
     th = _seeded_net(cfg, seed=9)
     th[cfg["n_in"] * cfg["width"]] = np.nan  # first bias of the first layer

@@ -52,7 +52,8 @@ static int check_slices(const bs_slices* s) {
 
 // Parareal workspace: [result 256 B | Fv N*M | Gold N*M | progress counters
 // 4(N+1)+3 ints | U2 (N+1)*M (grids the one-launch solve may cover) | Vt
-// (N+1)*M (network kinds)].  result: [0] defect, [1] status of the last
+// (N+1)*M (network kinds) | the large-grid sweep's tables (grids beyond 4096
+// nodes)].  result: [0] defect, [1] status of the last
 // iteration (0, 1 non-finite, 2 diverged), [2] defect of iteration 1, int at
 // [4]: stop flag of the asynchronous solve.
 struct Workspace {
@@ -62,6 +63,7 @@ struct Workspace {
     int* flags;  // ready[N+1], taken[N+1], fdone[N+1], err, decided[N+1], exited, stop_rank
     double* U2;
     double* Vt;
+    double* tab;  // grids beyond 4096 nodes: the sweep's implicit-Euler tables
 };
 
 static int flag_count(int N) { return 4 * (N + 1) + 3; }
@@ -75,6 +77,7 @@ static size_t ws_bytes(int M, int N, int kind) {
     b += align256(sizeof(int) * (size_t)flag_count(N));
     if (persist_possible(M, N)) b += align256(sizeof(double) * (size_t)(N + 1) * M);
     if (kind != BS_COARSE_IE) b += align256(sizeof(double) * (size_t)(N + 1) * M);
+    b += align256(sizeof(double) * large_sweep_table_doubles(M));
     return b;
 }
 
@@ -94,7 +97,12 @@ static Workspace ws_layout(void* ws, int M, int N, int kind) {
         w.U2 = (double*)p;
         p += align256(sizeof(double) * (size_t)(N + 1) * M);
     }
-    w.Vt = (kind != BS_COARSE_IE) ? (double*)p : nullptr;
+    w.Vt = nullptr;
+    if (kind != BS_COARSE_IE) {
+        w.Vt = (double*)p;
+        p += align256(sizeof(double) * (size_t)(N + 1) * M);
+    }
+    w.tab = large_sweep_table_doubles(M) ? (double*)p : nullptr;
     return w;
 }
 
@@ -204,6 +212,7 @@ static int start_impl(const bs_params* prm, const bs_grid* grid, const bs_slices
     if (!predict) return BS_OK;
     SweepArgs a{o, M, N, 0, sl->coarse_steps, kind, 1, dT, U, w.Fv, w.Gold, w.Vt, w.result};
     a.growth = INFINITY;
+    a.tab = w.tab;
     if (ps) {
         a.ps = *ps;
         a.ps.k = 0;
@@ -343,6 +352,7 @@ static int enqueue_iteration(const bs_params* prm, const bs_grid* grid, const bs
     SweepArgs a{o,      M,      N,      first,    sl->coarse_steps, kind, 0, dT, U, w.Fv,
                 w.Gold, w.Vt,   w.result, stop,   hist,             tol,  k,  pk};
     a.growth = growth;
+    a.tab = w.tab;
     if ((rc = launch_sweep(a, st))) return rc;
     if (prof) BSP_HIP(hipEventRecord(g_prof.ev[4 * slot + 3], st));
     return BS_OK;
@@ -558,8 +568,9 @@ static int solve_large(const bs_params* prm, const bs_grid* grid, const bs_slice
     if ((rc = launch_fill_int(ps.taken, N + 1, 1, st))) return rc;
     if ((rc = launch_fill_int(ps.fdone, N, 1, st))) return rc;
     LargePersistArgs a{};
-    if ((rc = launch_large_sweep_tables(o, M, dT, sl->coarse_steps, &a.tab, &a.ptab, st)))
-        return rc;
+    if ((rc = launch_large_sweep_setup(o, M, dT, sl->coarse_steps, w.tab, st))) return rc;
+    a.tab = w.tab;
+    a.ptab = large_sweep_ptab(w.tab);
     a.o = o;
     a.M = M;
     a.N = N;
@@ -766,8 +777,6 @@ int bs_release_resources(void) {
     for (hipEvent_t e : g_prof.ev) BSP_HIP(hipEventDestroy(e));
     g_prof.ev.clear();
     g_prof.on = false;
-    int rc;
-    if ((rc = release_large_tables())) return rc;
     return release_batch_resources();
 }
 

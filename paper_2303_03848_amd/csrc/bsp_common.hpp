@@ -244,7 +244,15 @@ struct SweepArgs {
     int k;
     PipeSync ps;  // overlapped solve (ps.ready null: not overlapped)
     double growth = __builtin_inf();  // divergence guard (infinite: none)
+    // grids beyond 4096 nodes: workspace space for the implicit-Euler tables
+    // (large_sweep_table_doubles(M) doubles; ptab is set by launch_sweep)
+    double* tab = nullptr;
+    const double* ptab = nullptr;
 };
+size_t large_sweep_table_doubles(int M);  // 0 for grids the sweep solves in registers
+const double* large_sweep_ptab(const double* tab);  // the per-thread part of the tables
+int launch_large_sweep_setup(const OptionDev& o, int M, double dT, int coarse_steps, double* tab,
+                             hipStream_t stream);
 int launch_sweep(const SweepArgs& a, hipStream_t stream);
 
 // Whole overlapped solve in one launch (see k_parareal_persist).  Iterate k
@@ -270,7 +278,7 @@ struct PersistArgs {
 // Overlapped solve of a grid beyond 4096 nodes (see k_large_persist): after
 // iteration 1's fine launch, one launch runs the sweeps of every iteration in
 // one block and the fine work of iterations 2, 3, ... in one block per slice
-// n >= 1.  The sweep's coefficient tables (tab, ptab) are built beforehand.
+// n >= 1.
 struct LargePersistArgs {
     OptionDev o;
     int M, N, kmax, fine_steps, coarse_steps, kind;
@@ -283,13 +291,11 @@ struct LargePersistArgs {
     int* stop;
     double* hist;  // per-iteration record [2 (kmax+1)] (host-mapped or device)
     PipeSync ps;
-    const double* tab;
+    const double* tab;  // the sweep's implicit-Euler tables (launch_large_sweep_setup)
     const double* ptab;
 };
 bool large_persist_capable(int M, int N);
 int launch_large_persist(const LargePersistArgs& a, hipStream_t stream);
-int launch_large_sweep_tables(const OptionDev& o, int M, double dT, int coarse_steps,
-                              const double** tab, const double** ptab, hipStream_t stream);
 
 // The one-launch solve can cover this problem size (block shapes aside).
 constexpr int kPersistMaxN = 512, kPersistMaxM = 1024;
@@ -327,7 +333,6 @@ struct BatchTile {
 };
 
 int check_net(const pinn_net* net);
-int release_large_tables();     // coefficient tables of the large-grid solver, this device
 int release_batch_resources();  // class streams and events of this thread
 long net_param_count(const pinn_net& net);
 

@@ -445,16 +445,19 @@ __global__ __launch_bounds__(T) void k_rc_theta(ThetaArgs a) {
     store_chunk<T, MC>(a.u_out + (long)sys * a.ld_out, a.M, V);
 }
 
+// The serial sweep on large grids: one block; the implicit-Euler solves
+// stream their factors from the tables a.tab / a.ptab (built by
+// k_large_setup in the caller's workspace), which keeps LDS free for the
+// staged correction's 4096-node passes.
 template <int T, int MC>
-__global__ __launch_bounds__(T) void k_large_sweep(SweepArgs a, const double* __restrict__ tab,
-                                                   const double* __restrict__ ptab) {
+__global__ __launch_bounds__(T) void k_large_sweep(SweepArgs a) {
     __shared__ double smem[sweep_smem_doubles<T, MC>()];
     __shared__ double kst[2 * BlockTriG<T, MC>::LOGT * T];
     double* lds = smem;
     double* ftab = smem + 4 * T;
     if (stopped(a.stop)) return;
     BlockTriG<T, MC> S;
-    S.load(tab, ptab, a.o.s2, a.o.r, a.dT / (double)a.coarse_steps, 0.0, a.M, kst);
+    S.load(a.tab, a.ptab, a.o.s2, a.o.r, a.dT / (double)a.coarse_steps, 0.0, a.M, kst);
     double dmax = 0.0;
     int bad = 0;
     sweep_slices<T, MC>(S, a.o, a.M, a.N, a.n0, a.coarse_steps, a.kind, a.predict != 0, a.dT, a.U,
@@ -465,36 +468,6 @@ __global__ __launch_bounds__(T) void k_large_sweep(SweepArgs a, const double* __
     }
 }
 
-// Coefficient tables of the large-grid solver: one slot per kernel kind
-// (0: F / G batch, 1: sweep), owned by the library for each device and kept
-// until the process ends.  Calls with M > 4096 on one device therefore must
-// not overlap in time (they are ordered on one stream in normal use).
-constexpr long kLargeTab = 5L * 32 * 512, kLargePtab = (long)kLgP * 512;
-static double* g_large[16] = {nullptr};
-
-int release_large_tables() {
-    int dev = 0;
-    BSP_HIP(hipGetDevice(&dev));
-    if (dev >= 0 && dev < 16 && g_large[dev]) {
-        BSP_HIP(hipFree(g_large[dev]));
-        g_large[dev] = nullptr;
-    }
-    return BS_OK;
-}
-
-static int large_tables(int slot, double** tab, double** ptab) {
-    int dev = 0;
-    BSP_HIP(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 16) {
-        set_error("device index %d out of range", dev);
-        return BS_ERR_ARG;
-    }
-    if (!g_large[dev]) BSP_HIP(hipMalloc(&g_large[dev], sizeof(double) * 2 * (kLargeTab + kLargePtab)));
-    *tab = g_large[dev] + (long)slot * (kLargeTab + kLargePtab);
-    *ptab = *tab + kLargeTab;
-    return BS_OK;
-}
-
 template <int T, int MC>
 static int launch_large_setup(const OptionDev& o, int M, double h, double e, double* tab,
                               double* ptab, hipStream_t st) {
@@ -503,6 +476,24 @@ static int launch_large_setup(const OptionDev& o, int M, double h, double e, dou
     BSP_LAUNCHED();
     return BS_OK;
 }
+
+size_t large_sweep_table_doubles(int M) {
+    return is_large(shape_for(1, M)) ? (size_t)kLgFields * 32 * 512 + (size_t)kLgP * 512 : 0;
+}
+
+const double* large_sweep_ptab(const double* tab) { return tab + (size_t)kLgFields * 32 * 512; }
+
+// Tables of the large-grid sweep's implicit-Euler solves, in tab (of
+// large_sweep_table_doubles(M) doubles).
+int launch_large_sweep_setup(const OptionDev& o, int M, double dT, int coarse_steps, double* tab,
+                             hipStream_t stream) {
+    const TriShape sh = shape_for(1, M);
+    double* ptab = tab + (size_t)kLgFields * 32 * 512;
+    const double h = dT / (double)coarse_steps;
+    if (sh.MC == 16) return launch_large_setup<512, 16>(o, M, h, 0.0, tab, ptab, stream);
+    return launch_large_setup<512, 32>(o, M, h, 0.0, tab, ptab, stream);
+}
+
 
 // ------------------------------------------ overlapped large-grid solve
 
@@ -523,6 +514,10 @@ static int launch_large_setup(const OptionDev& o, int M, double h, double e, dou
 // kPollSteps steps.  Every block must be resident (N blocks, one per compute
 // unit): the host checks the device's capacity first.
 constexpr int kLargePersistMaxN = 256;
+// Slices per hand-off batch of the sweep block (one acquire and one release
+// per batch: agent-scope fences write back / drop the compute unit's cached
+// lines, which the sweep's solver re-reads every slice).
+constexpr int kLargeSweepBatch = 8;
 
 template <int MC>
 constexpr int large_persist_lds() {  // doubles: the larger of the two roles
@@ -582,10 +577,10 @@ __device__ __forceinline__ void large_sweep_role(const LargePersistArgs& a, doub
         const int n0 = min(k - 1, a.N - 1);
         double dmax = 0.0;
         int bad = 0;
-        if (!sweep_slices<T, MC>(S, a.o, a.M, a.N, n0, a.coarse_steps, a.kind, false, a.dT, a.U,
-                                 a.U, a.Fv, a.Gold, a.Vt, lds, ftab, dmax, bad, ps, true, a.stop,
-                                 pslot))
-            return;
+        const bool ok = sweep_slices<T, MC>(S, a.o, a.M, a.N, n0, a.coarse_steps, a.kind, false,
+                                            a.dT, a.U, a.U, a.Fv, a.Gold, a.Vt, lds, ftab, dmax,
+                                            bad, ps, true, a.stop, pslot, 0, kLargeSweepBatch);
+        if (!ok) return;
         block_defect<T>(dmax, bad, lds);
         if (threadIdx.x == 0) {
             SweepArgs sa{};
@@ -662,20 +657,6 @@ int launch_large_persist(const LargePersistArgs& a, hipStream_t stream) {
     return BS_OK;
 }
 
-int launch_large_sweep_tables(const OptionDev& o, int M, double dT, int coarse_steps,
-                              const double** tab, const double** ptab, hipStream_t stream) {
-    double *t, *pt;
-    int rc = large_tables(1, &t, &pt);
-    if (rc) return rc;
-    const double h = dT / (double)coarse_steps;
-    if (shape_for(1, M).MC == 16)
-        rc = launch_large_setup<512, 16>(o, M, h, 0.0, t, pt, stream);
-    else
-        rc = launch_large_setup<512, 32>(o, M, h, 0.0, t, pt, stream);
-    *tab = t;
-    *ptab = pt;
-    return rc;
-}
 
 // ------------------------------------------------------------ dispatch
 
@@ -802,17 +783,18 @@ int launch_theta_batch(const OptionDev& o, int M, int nsys, const double* tau0, 
 int launch_sweep(const SweepArgs& a, hipStream_t stream) {
     const TriShape sh = shape_for(1, a.M);
     if (is_large(sh)) {
-        double *tab, *ptab;
-        int rc = large_tables(1, &tab, &ptab);
-        if (rc) return rc;
-        const double h = a.dT / (double)a.coarse_steps;
-        if (sh.MC == 16) {
-            if ((rc = launch_large_setup<512, 16>(a.o, a.M, h, 0.0, tab, ptab, stream))) return rc;
-            hipLaunchKernelGGL((k_large_sweep<512, 16>), dim3(1), dim3(512), 0, stream, a, tab, ptab);
-        } else {
-            if ((rc = launch_large_setup<512, 32>(a.o, a.M, h, 0.0, tab, ptab, stream))) return rc;
-            hipLaunchKernelGGL((k_large_sweep<512, 32>), dim3(1), dim3(512), 0, stream, a, tab, ptab);
+        if (!a.tab) {
+            set_error("the large-grid sweep needs its coefficient tables");
+            return BS_ERR_ARG;
         }
+        int rc = launch_large_sweep_setup(a.o, a.M, a.dT, a.coarse_steps, a.tab, stream);
+        if (rc) return rc;
+        SweepArgs b = a;
+        b.ptab = a.tab + (size_t)kLgFields * 32 * 512;
+        if (sh.MC == 16)
+            hipLaunchKernelGGL((k_large_sweep<512, 16>), dim3(1), dim3(512), 0, stream, b);
+        else
+            hipLaunchKernelGGL((k_large_sweep<512, 32>), dim3(1), dim3(512), 0, stream, b);
         BSP_LAUNCHED();
         return BS_OK;
     }

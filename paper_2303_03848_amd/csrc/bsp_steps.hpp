@@ -331,12 +331,20 @@ constexpr int sweep_smem_doubles() {
            (2 * kForceChunk > staged_doubles<T, MC>() ? 2 * kForceChunk : staged_doubles<T, MC>());
 }
 
-template <int T, int MC>
+// The coarse value of slice n at node i, by coarse kind:
+//   kCoarseSolve:  G = g (the solve's result);
+//   kCoarseNet:    G = Vt_{n+1} (the network alone; g is not used);
+//   kCoarseNetDev: G = Vt_{n+1} + g (g: the solved deviation from the network),
+//                  and the state carried to the next slice is the new
+//                  iterate's deviation U[n+1] - Vt_{n+1}.
+enum { kCoarseSolve = 0, kCoarseNet = 1, kCoarseNetDev = 2 };
+
+template <int T, int MC, int MODE = kCoarseSolve>
 __device__ __forceinline__ void correct_staged(double (&g)[MC], int M, bool predict,
                                                const double* __restrict__ fv,
                                                double* __restrict__ go, const double* uo1,
-                                               double* un1, double* stage, double& dmax,
-                                               int& bad) {
+                                               double* un1, const double* __restrict__ vt1,
+                                               double* stage, double& dmax, int& bad) {
     constexpr int CH = staged_chunks<T, MC>();
     constexpr int J = CH * MC / T;  // nodes per thread and pass
     static_assert(CH * MC % T == 0 && T % CH == 0, "whole passes");
@@ -346,7 +354,7 @@ __device__ __forceinline__ void correct_staged(double (&g)[MC], int M, bool pred
         const int pl = p - c0;
         const bool mine = pl >= 0 && pl < CH;
         __syncthreads();  // earlier readers of this shared memory are done
-        if (mine) {
+        if (mine && MODE != kCoarseNet) {
 #pragma unroll
             for (int q = 0; q < MC; ++q) stage[pl * (MC + 1) + q] = g[q];
         }
@@ -357,38 +365,46 @@ __device__ __forceinline__ void correct_staged(double (&g)[MC], int M, bool pred
             for (int j = 0; j < J; ++j) {
                 const int t = j * T + p, i = base + t;
                 if (i < M) {
-                    const double gg = stage[t + t / MC];
+                    const double v = MODE != kCoarseSolve ? vt1[i] : 0.0;
+                    const double gg = MODE == kCoarseSolve ? stage[t + t / MC]
+                                      : MODE == kCoarseNet ? v
+                                                           : v + stage[t + t / MC];
                     un1[i] = gg;
                     go[i] = gg;
+                    if (MODE == kCoarseNetDev) stage[t + t / MC] = gg - v;
                 }
             }
-            continue;
-        }
-        // groups of G nodes per thread: the loads of a group are issued
-        // together, with few registers held beside the chunk
-        constexpr int G = J < 4 ? J : 4;
-        static_assert(J % G == 0, "whole groups");
+            if (MODE != kCoarseNetDev) continue;
+        } else {
+            // groups of G nodes per thread: the loads of a group are issued
+            // together, with few registers held beside the chunk
+            constexpr int G = J < 4 ? J : 4;
+            static_assert(J % G == 0, "whole groups");
 #pragma unroll
-        for (int j0 = 0; j0 < J; j0 += G) {
-            double f[G], gl[G], uo[G];
+            for (int j0 = 0; j0 < J; j0 += G) {
+                double f[G], gl[G], uo[G], v[G];
 #pragma unroll
-            for (int j = 0; j < G; ++j) {
-                const int i = base + (j0 + j) * T + p;
-                f[j] = (i < M) ? fv[i] : 0.0;
-                gl[j] = (i < M) ? go[i] : 0.0;
-                uo[j] = (i < M) ? uo1[i] : 0.0;
-            }
+                for (int j = 0; j < G; ++j) {
+                    const int i = base + (j0 + j) * T + p;
+                    f[j] = (i < M) ? fv[i] : 0.0;
+                    gl[j] = (i < M) ? go[i] : 0.0;
+                    uo[j] = (i < M) ? uo1[i] : 0.0;
+                    v[j] = (MODE != kCoarseSolve && i < M) ? vt1[i] : 0.0;
+                }
 #pragma unroll
-            for (int j = 0; j < G; ++j) {
-                const int t = (j0 + j) * T + p, i = base + t;
-                if (i < M) {
-                    const double gg = stage[t + t / MC];
-                    const double unew = f[j] + (gg - gl[j]);
-                    go[i] = gg;
-                    un1[i] = unew;
-                    dmax = fmax(dmax, fabs(unew - uo[j]));
-                    bad |= !isfinite(unew);
-                    stage[t + t / MC] = unew;
+                for (int j = 0; j < G; ++j) {
+                    const int t = (j0 + j) * T + p, i = base + t;
+                    if (i < M) {
+                        const double gg = MODE == kCoarseSolve ? stage[t + t / MC]
+                                          : MODE == kCoarseNet ? v[j]
+                                                               : v[j] + stage[t + t / MC];
+                        const double unew = f[j] + (gg - gl[j]);
+                        go[i] = gg;
+                        un1[i] = unew;
+                        dmax = fmax(dmax, fabs(unew - uo[j]));
+                        bad |= !isfinite(unew);
+                        stage[t + t / MC] = MODE == kCoarseNetDev ? unew - v[j] : unew;
+                    }
                 }
             }
         }
@@ -402,12 +418,41 @@ __device__ __forceinline__ void correct_staged(double (&g)[MC], int M, bool pred
     __syncthreads();  // the next coarse solve may overwrite the staging area
 }
 
+// g[q] = op(g[q], src[p*MC + q]) for this thread's chunk (0 past the grid),
+// with src read in node order through the staging area (passes as in
+// correct_staged; chunks of 8 or more nodes per thread).
+template <int T, int MC, class Op>
+__device__ __forceinline__ void combine_staged(const double* __restrict__ src, int M,
+                                               double (&g)[MC], double* stage, Op op) {
+    constexpr int CH = staged_chunks<T, MC>();
+    constexpr int J = CH * MC / T;
+    static_assert(CH * MC % T == 0 && T % CH == 0, "whole passes");
+    const int p = threadIdx.x;
+#pragma unroll 1
+    for (int c0 = 0; c0 < T; c0 += CH) {
+        const int base = c0 * MC;
+        __syncthreads();  // earlier readers of this shared memory are done
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+            const int t = j * T + p, i = base + t;
+            stage[t + t / MC] = (i < M) ? src[i] : 0.0;
+        }
+        __syncthreads();
+        const int pl = p - c0;
+        if (pl >= 0 && pl < CH) {
+#pragma unroll
+            for (int q = 0; q < MC; ++q) g[q] = op(g[q], stage[pl * (MC + 1) + q]);
+        }
+    }
+    __syncthreads();  // the coarse solve may overwrite the staging area
+}
+
 // One option's serial Parareal sweep over slices n = n0..N-1 in one block:
 //   g = G(U[n])                       (state carried in registers)
 //   predict: U[n+1] = g, Gold[n] = g
 //   else:    U[n+1] = Fv[n] + (g - Gold[n]), Gold[n] = g,
 //            dmax = max |U_new[n+1] - U_old[n+1]|, bad |= non-finite.
-// S (BlockTri, BlockTriH or BlockTriG) must be set up for implicit Euler with
+// S (BlockTri, BlockTriH or BlockTriR) must be set up for implicit Euler with
 // dt = dT / coarse_steps.  For MC >= 8, lds must hold sweep_smem_doubles<T,
 // MC>() doubles with ftab = lds + 4T (the staged correction uses the space
 // after the solver's 4T doubles).
@@ -430,11 +475,15 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
                                              double* ftab, double& dmax, int& bad,
                                              const PipeSync& ps = PipeSync{}, bool pipe = false,
                                              const int* stop = nullptr, int* pslot = nullptr,
-                                             int taken_lag = 0) {
+                                             int taken_lag = 0, int pbatch = 1) {
     const double dtc = dT / (double)coarse_steps;
     const int i0 = threadIdx.x * MC;
     const bool net = kind != BS_COARSE_IE;
     if (pipe && predict && n0 == 0) pipe_signal(ps.ready, 1);  // U[0], written before the launch
+    // Loads that do not depend on the coarse solve go first, so their latency
+    // overlaps it (when registers allow: small chunks); larger chunks move
+    // the slice's global traffic through the staged, node-order correction.
+    constexpr bool kPrefetch = MC <= 4;
     double V[MC];
     load_chunk<T, MC>(Uin + (long)n0 * M, M, V);
     if (Uout != Uin) {
@@ -444,13 +493,16 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
             return false;
         store_chunk<T, MC>(Uout + (long)n0 * M, M, V);
     }
+    if (!kPrefetch && kind == BS_COARSE_PINN_IE) {
+        // staged path: the state carried from slice to slice is the
+        // deviation from the network, U[n] - Vt_n
+        combine_staged<T, MC>(Vt + (long)n0 * M, M, V, lds + 4 * T,
+                              [](double a, double v) { return a - v; });
+    }
     for (int n = n0; n < N; ++n) {
         const double* uo1 = Uin + (long)(n + 1) * M;
         double* un1 = Uout + (long)(n + 1) * M;
         double* go = Gold + (long)n * M;
-        // Loads that do not depend on the coarse solve go first, so their
-        // latency overlaps it (when registers allow: small chunks).
-        constexpr bool kPrefetch = MC <= 4;
         double fv[MC], gold[MC], uold[MC], vt0[MC], vt1[MC];
         if constexpr (kPrefetch) {
             if (!predict && !pipe) {
@@ -470,23 +522,26 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
             theta_steps<T, MC, false>(S, o, g, (double)n * dT, dtc, coarse_steps, 1.0, false, lds,
                                       ftab);
         } else if (kind == BS_COARSE_PINN) {
-            const double* vn1 = Vt + (long)(n + 1) * M;
+            if constexpr (kPrefetch) {
 #pragma unroll
-            for (int q = 0; q < MC; ++q)
-                g[q] = kPrefetch ? vt1[q] : ((i0 + q < M) ? vn1[i0 + q] : 0.0);
+                for (int q = 0; q < MC; ++q) g[q] = vt1[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < MC; ++q) g[q] = 0.0;  // the correction takes Vt_{n+1}
+            }
         } else {
-            const double* vn0 = Vt + (long)n * M;
-            const double* vn1 = Vt + (long)(n + 1) * M;
+            // G = Vt_{n+1} + E(U[n] - Vt_n); the staged path carries the
+            // deviation in V and adds Vt_{n+1} in the correction
 #pragma unroll
-            for (int q = 0; q < MC; ++q)
-                g[q] = V[q] - (kPrefetch ? vt0[q] : ((i0 + q < M) ? vn0[i0 + q] : 0.0));
+            for (int q = 0; q < MC; ++q) g[q] = kPrefetch ? V[q] - vt0[q] : V[q];
             theta_steps<T, MC, false>(S, o, g, (double)n * dT, dtc, coarse_steps, 1.0, true, lds,
                                       ftab);
+            if constexpr (kPrefetch) {
 #pragma unroll
-            for (int q = 0; q < MC; ++q)
-                g[q] = (kPrefetch ? vt1[q] : ((i0 + q < M) ? vn1[i0 + q] : 0.0)) + g[q];
+                for (int q = 0; q < MC; ++q) g[q] = vt1[q] + g[q];
+            }
         }
-        if (pipe && !predict) {
+        if (pipe && !predict && pbatch == 1) {
             // this iteration's fine result of slice n, then U[n+1] free to overwrite
             if (!pipe_wait(ps, ps.fdone + n, ps.k, stop, pslot)) return false;
             // Fv[n], and (written by the previous iteration's sweep, which has
@@ -499,12 +554,31 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
             if (n + 1 < N &&
                 !pipe_wait<false>(ps, ps.taken + n + 1, ps.k - taken_lag, stop, pslot))
                 return false;
+        } else if (pipe && !predict && (n - n0) % pbatch == 0) {
+            // batched hand-offs: the fine results of slices n .. n+pbatch-1,
+            // then one acquire for all of them (each acquire also drops this
+            // compute unit's cached lines, among them the solver's tables)
+            const int nb = min(n + pbatch, N);
+            for (int m = n; m < nb; ++m)
+                if (!pipe_wait<false>(ps, ps.fdone + m, ps.k, stop, pslot)) return false;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            for (int m = n; m < nb && m + 1 < N; ++m)
+                if (!pipe_wait<false>(ps, ps.taken + m + 1, ps.k - taken_lag, stop, pslot))
+                    return false;
         }
         if constexpr (!kPrefetch) {
             // chunks of 8 or more nodes: the slice's global traffic goes
             // through the staged, node-order correction
-            correct_staged<T, MC>(g, M, predict, Fv + (long)n * M, go, uo1, un1, lds + 4 * T,
-                                  dmax, bad);
+            const double* vn1 = net ? Vt + (long)(n + 1) * M : nullptr;
+            if (kind == BS_COARSE_IE)
+                correct_staged<T, MC, kCoarseSolve>(g, M, predict, Fv + (long)n * M, go, uo1,
+                                                    un1, vn1, lds + 4 * T, dmax, bad);
+            else if (kind == BS_COARSE_PINN)
+                correct_staged<T, MC, kCoarseNet>(g, M, predict, Fv + (long)n * M, go, uo1, un1,
+                                                  vn1, lds + 4 * T, dmax, bad);
+            else
+                correct_staged<T, MC, kCoarseNetDev>(g, M, predict, Fv + (long)n * M, go, uo1,
+                                                     un1, vn1, lds + 4 * T, dmax, bad);
 #pragma unroll
             for (int q = 0; q < MC; ++q) V[q] = g[q];
         } else if (predict) {
@@ -531,7 +605,17 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
                 }
             }
         }
-        if (pipe) pipe_signal(ps.ready + n + 1, predict ? 1 : ps.k + 1);
+        if (pipe && (predict || pbatch == 1)) {
+            pipe_signal(ps.ready + n + 1, predict ? 1 : ps.k + 1);
+        } else if (pipe && ((n - n0) % pbatch == pbatch - 1 || n == N - 1)) {
+            // one release for the batch's new iterates
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (threadIdx.x == 0)
+                for (int m = n - (n - n0) % pbatch; m <= n; ++m)
+                    __hip_atomic_store(ps.ready + m + 1, ps.k + 1, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
     return true;
 }

@@ -1,11 +1,12 @@
 // Tridiagonal block solver for large grids (up to 16384 nodes on 512 threads)
 // that keeps one coefficient field per node on chip and recomputes the rest.
 //
-// Same partition and implicit step form as BlockTriG (each thread owns MC
+// Same partition and implicit step form as BlockTri (each thread owns MC
 // consecutive rows: MC-1 interior rows eliminated locally and one interface
 // row; the interface system is reduced by truncated parallel cyclic
-// reduction through LDS), but nothing is read from global memory after the
-// set-up:
+// reduction, here through LDS with one barrier per stage), but with 512
+// threads of 16 or 32 rows nothing per row fits in registers beside the
+// state, and nothing is read from global memory after the set-up:
 //  * kappa/u_q, the scaled reciprocal pivot of interior row q, is the one
 //    field kept per node, in LDS (NI x T doubles, read twice per step);
 //  * the row coefficients are closed forms in the grid index j (centred

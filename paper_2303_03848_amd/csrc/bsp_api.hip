@@ -156,7 +156,7 @@ static int propagate_checked(const bs_params* prm, const bs_grid* grid, int nsys
     if (nsys == 0) return BS_OK;
     BSP_CHECK_ARG(tau0 && u_in && u_out, "tau0, u_in and u_out must be non-NULL");
     const OptionDev o = make_option(*prm, grid->M);
-    return launch_theta_batch(o, grid->M, nsys, tau0, 0.0, 0.0, 0, dtau / steps, steps, theta, 0,
+    return launch_theta_batch(o, grid->M, nsys, tau0, 0.0, 0.0, 0, dtau / steps, steps, theta,
                               u_in, grid->M, u_out, grid->M, (hipStream_t)stream);
 }
 
@@ -344,7 +344,7 @@ static int enqueue_iteration(const bs_params* prm, const bs_grid* grid, const bs
     }
     if (prof) BSP_HIP(hipEventRecord(g_prof.ev[4 * slot], fst));
     int rc = launch_theta_batch(o, M, N - first, nullptr, 0.0, dT, first, dT / sl->fine_steps,
-                                sl->fine_steps, 0.5, 0, U + (long)first * M, M,
+                                sl->fine_steps, 0.5, U + (long)first * M, M,
                                 w.Fv + (long)first * M, M, fst, stop, ps ? &pk : nullptr);
     if (rc) return rc;
     if (prof) BSP_HIP(hipEventRecord(g_prof.ev[4 * slot + 1], fst));
@@ -559,7 +559,7 @@ static int solve_large(const bs_params* prm, const bs_grid* grid, const bs_slice
     // iteration 1: F on every slice, one launch
     if (prof) BSP_HIP(hipEventRecord(g_prof.ev[0], st));
     if ((rc = launch_theta_batch(o, M, N, nullptr, 0.0, dT, 0, dT / sl->fine_steps,
-                                 sl->fine_steps, 0.5, 0, U, M, w.Fv, M, st, stop, nullptr)))
+                                 sl->fine_steps, 0.5, U, M, w.Fv, M, st, stop, nullptr)))
         return rc;
     if (prof) BSP_HIP(hipEventRecord(g_prof.ev[1], st));
     // every U[n] holds iterate 0 and every Fv[n] iteration 1's result, read

@@ -216,10 +216,9 @@ __device__ inline void pipe_signal(int* f, int v) {
 
 // theta-method on nsys independent systems: tau of system s = tau0[s] if
 // tau0 != nullptr else tau_start + (s + sys_offset) * tau_stride.
-// homog: zero boundary data.
 int launch_theta_batch(const OptionDev& o, int M, int nsys, const double* tau0, double tau_start,
                        double tau_stride, int sys_offset, double dt, int steps, double theta,
-                       int homog, const double* u_in, long ld_in, double* u_out, long ld_out,
+                       const double* u_in, long ld_in, double* u_out, long ld_out,
                        hipStream_t stream, const int* stop = nullptr,
                        const PipeSync* ps = nullptr);
 

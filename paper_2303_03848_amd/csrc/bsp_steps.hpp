@@ -281,22 +281,25 @@ __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
         }
         double flo_n = homog ? 0.0 : ftab[0];
         double fhi_n = homog ? 0.0 : ftab[kForceChunk];
-        for (int i = 0; i < nch; ++i) {
-            if constexpr (POLL) {
-                if (i % kPollSteps == 0) {  // the same decision in every thread of the system
-                    if (sv) return false;
-                    if constexpr (WAVE || T == 64)
-                        sv = __builtin_amdgcn_readfirstlane(pipe_load(stop));
-                    else
-                        sv = __syncthreads_or(pipe_load(stop) != 0);
+        // POLL: runs of kPollSteps steps with the check between them, so the
+        // step loop itself carries no test
+        for (int i0 = 0; i0 < nch; i0 += kPollSteps) {
+            if constexpr (POLL) {  // the same decision in every thread of the system
+                if (sv) return false;
+                if constexpr (WAVE || T == 64)
+                    sv = __builtin_amdgcn_readfirstlane(pipe_load(stop));
+                else
+                    sv = __syncthreads_or(pipe_load(stop) != 0);
+            }
+            const int i1 = min(nch, i0 + kPollSteps);
+            for (int i = i0; i < i1; ++i) {
+                const double flo = flo_n, fhi = fhi_n;
+                if (!homog && i + 1 < nch) {
+                    flo_n = ftab[i + 1];
+                    fhi_n = ftab[kForceChunk + i + 1];
                 }
+                S.template step<EX>(V, flo, fhi, lds);
             }
-            const double flo = flo_n, fhi = fhi_n;
-            if (!homog && i + 1 < nch) {
-                flo_n = ftab[i + 1];
-                fhi_n = ftab[kForceChunk + i + 1];
-            }
-            S.template step<EX>(V, flo, fhi, lds);
         }
     }
     return true;
@@ -376,9 +379,11 @@ __device__ __forceinline__ void correct_staged(double (&g)[MC], int M, bool pred
             }
             if (MODE != kCoarseNetDev) continue;
         } else {
-            // groups of G nodes per thread: the loads of a group are issued
-            // together, with few registers held beside the chunk
-            constexpr int G = J < 4 ? J : 4;
+            // the loads of the whole pass are issued together: one memory
+            // round trip per pass (the stores of a group may alias the next
+            // group's loads as far as the compiler knows, which would
+            // serialise groups)
+            constexpr int G = J;
             static_assert(J % G == 0, "whole groups");
 #pragma unroll
             for (int j0 = 0; j0 < J; j0 += G) {

@@ -41,6 +41,24 @@ class PinnResidualLoss(torch.autograd.Function):
         return g * grad, None, None, None, None, None, None
 
 
+class DataLoss(torch.autograd.Function):
+    """Mean squared error between the network and value targets (the
+    residual kernel's value-matching set alone); loss and gradient in one
+    pass of the kernel."""
+
+    @staticmethod
+    def forward(ctx, params, spec, p, X, y, empty, ws):
+        net = bsp.PinnNet(params.detach(), *spec)
+        loss3, grad = bsp.pinn_residual_fwd_bwd(net, p, empty, X, empty, ws=ws, y_e=y)
+        ctx.save_for_backward(grad)
+        return loss3[1].clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        (grad,) = ctx.saved_tensors
+        return g * grad, None, None, None, None, None, None
+
+
 def pinn_loss(params: torch.Tensor, spec, p: dict, X_f, X_e, X_b, ws=None):
     """(total loss [differentiable w.r.t. params], loss3 [detached])."""
     total = PinnResidualLoss.apply(params, spec, p, X_f, X_e, X_b, ws)
@@ -109,3 +127,51 @@ def train_call_network(cfg: dict, epochs_hi: int = 5000, epochs_lo: int = 800,
                       epochs_hi=epochs_hi, epochs_lo=epochs_lo)
     net.precision = precision_eval
     return net, {k: v for k, v in info.items() if k != "history"}
+
+
+def train_on_data(p: dict, X, y, n_in: int, depth: int, width: int,
+                  precision: int = bsp.PREC_FP32, batch: int = 8192, epochs_hi: int = 5000,
+                  epochs_lo: int = 800, lr_hi: float = 1e-2, lr_lo: float = 1e-3,
+                  seed: int = SEED, init_seed: int = 0):
+    """A network fitted to data alone (no PDE terms): the same MLP and Adam
+    schedule as train(), with the loss the mean squared error between the
+    network and the targets y at the points X (float32 [n, n_in], v = V/K
+    targets [n]).  The gradient comes from the residual kernel with only its
+    value-matching set (n_f = n_b = 0).  Returns (PinnNet, info dict)."""
+    dev = torch.device("cuda")
+    X = torch.as_tensor(X, dtype=torch.float32, device=dev).contiguous()
+    y = torch.as_tensor(y, dtype=torch.float32, device=dev).contiguous()
+    n = X.shape[0]
+    if y.numel() != n or X.shape[1] != n_in:
+        raise ValueError("X must be [n, n_in] and y [n]")
+    batch = min(batch, n)
+    params = torch.nn.Parameter(torch.tensor(xavier_normal(n_in, depth, width, init_seed),
+                                             device=dev))
+    spec = (n_in, depth, width, precision)
+    net = bsp.PinnNet(params.data, *spec)
+    ws = torch.empty(bsp.pinn_residual_workspace_size(net, 0, batch, 0), dtype=torch.uint8,
+                     device=dev)
+    empty = torch.empty((0, n_in), dtype=torch.float32, device=dev)
+    opt = torch.optim.Adam([params], lr=lr_hi)
+    per_epoch = n // batch
+    t0 = time.time()
+    step = 0
+    for epoch in range(epochs_hi + epochs_lo):
+        if epoch == epochs_hi:
+            for gopt in opt.param_groups:
+                gopt["lr"] = lr_lo
+        for idx in minibatch_indices(n, batch, epoch, seed):
+            i = torch.as_tensor(idx, device=dev)
+            opt.zero_grad(set_to_none=True)
+            loss = DataLoss.apply(params, spec, p, X[i].contiguous(), y[i].contiguous(), empty,
+                                  ws)
+            loss.backward()
+            opt.step()
+            step += 1
+    torch.cuda.synchronize()
+    m = min(n, batch)
+    final = bsp.pinn_residual_fwd_bwd(bsp.PinnNet(params.data, *spec), p, empty, X[:m].contiguous(),
+                                      empty, y_e=y[:m].contiguous())[0]
+    info = {"steps": step, "epochs": epochs_hi + epochs_lo, "per_epoch": per_epoch,
+            "seconds": time.time() - t0, "final_data_mse": float(final[1])}
+    return bsp.PinnNet(params.data.clone(), *spec), info

@@ -313,6 +313,7 @@ def test_overlapped_solve_multiwave(M, N, Sf, is_put, tol, max_iter):
     (9000, 8, 12, False, bsp.COARSE_IE, 0.0, 3),         # 32 nodes per thread, max_iter cut
     (6000, 7, 10, True, bsp.COARSE_PINN_IE, 0.0, None),  # network coarse
     (4500, 64, 4, False, bsp.COARSE_IE, 1e-6, None),     # many slices, early stop
+    (16384, 2, 24, True, bsp.COARSE_IE, 0.0, None),      # two slices: one fine block
 ])
 def test_overlapped_solve_large_grid(M, N, Sf, is_put, kind, tol, max_iter):
     """Grids beyond 4096 nodes: iteration 1's fine launch, then one launch

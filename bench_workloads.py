@@ -80,29 +80,64 @@ def train_step() -> dict:
     return out
 
 
-def batch_options(n_opt: int | None = None) -> dict:
-    """The batch of options, numerical coarse, one launch per phase and block
-    shape with hipGraph replay."""
+def train_batch_network(epochs=(1000, 200), precision: int = bsp.PREC_BF16):
+    """The parametric network of the batch: (tau, S/K, sigma, r) -> V/K of a
+    call, trained over the batch's box of maturities, S/K, sigma and r (puts
+    take put-call parity on the device).  FP32 training, evaluated in
+    `precision`."""
+    from paper_2303_03848_amd.pinn import train
+    cfg = OPTION_BATCH
+    box = dict(K=1.0, r=0.0, sigma=0.2, T=cfg["T_range"][1], s_max=cfg["s_max_over_K"],
+               is_put=False)
+    net, info = train(box, cfg["n_in"], cfg["depth"], cfg["width"], bsp.PREC_FP32,
+                      epochs_hi=epochs[0], epochs_lo=epochs[1],
+                      coeff_box=(cfg["sigma_range"], cfg["r_range"]))
+    net.precision = precision
+    return net, {k: v for k, v in info.items() if k != "history"}
+
+
+def batch_options(n_opt: int | None = None, train_epochs=(1000, 200)) -> dict:
+    """The batch of options: numerical coarse, and the network coarse with
+    the parametric network in BF16 (one launch per phase and block shape,
+    iterations queued ahead of the host's convergence check)."""
     cfg = OPTION_BATCH
     opts = option_batch(cfg, n_opt=n_opt)
     for o in opts:
         o["fine_steps"] = cfg["fine_steps"]
         o["coarse_steps"] = cfg["coarse_steps"]
-    res = {}
-
-    def solve():
-        _, _, iters, _, _ = bsp.parareal_solve_batch(opts, bsp.COARSE_IE, cfg["tol"])
-        res["iters"] = iters
-
-    ms = _timed(solve, 2)
-    iters = np.array(res["iters"])
-    cells = sum(parareal_cells(o["M"], o["N"], o["fine_steps"], int(k))
-                for o, k in zip(opts, iters))
     serial = sum(float(o["N"] * o["fine_steps"] * o["M"]) for o in opts)
-    return {"workload": cfg["name"], "options": len(opts), "coarse": "implicit_euler",
-            "time_ms": ms, "iters_mean": float(iters.mean()), "iters_min": int(iters.min()),
-            "iters_max": int(iters.max()), "cell_updates_per_s": cells / (ms / 1e3),
-            "serial_fine_cells": serial}
+
+    def run(kind, net):
+        res = {}
+
+        def solve():
+            _, _, iters, _, _ = bsp.parareal_solve_batch(opts, kind, cfg["tol"], net=net)
+            res["iters"] = iters
+
+        ms = _timed(solve, 2)
+        iters = np.array(res["iters"])
+        cells = sum(parareal_cells(o["M"], o["N"], o["fine_steps"], int(k))
+                    for o, k in zip(opts, iters))
+        return {"time_ms": ms, "iters_mean": float(iters.mean()), "iters_min": int(iters.min()),
+                "iters_max": int(iters.max()), "cell_updates_per_s": cells / (ms / 1e3)}
+
+    out = {"workload": cfg["name"], "options": len(opts), "serial_fine_cells": serial,
+           "numeric_coarse_default_shapes": run(bsp.COARSE_IE, None)}
+    # block shapes per grid size picked by the autotuner on this batch
+    from paper_2303_03848_amd.autotune import tune_batch
+    t0 = time.time()
+    shapes = tune_batch(cfg["name"], opts, use_cache=False)
+    out["tuned_shapes"] = {M: {"fine": e["fine"], "sweep": e["sweep"]} for M, e in shapes.items()}
+    out["tuning_s"] = time.time() - t0
+    out["numeric_coarse"] = run(bsp.COARSE_IE, None)
+    if train_epochs:
+        t0 = time.time()
+        net, info = train_batch_network(train_epochs)
+        out["network_training"] = dict(info, wall_s=time.time() - t0)
+        out["network_coarse_bf16"] = run(bsp.COARSE_PINN_IE, net)
+        out["network"] = f"{cfg['depth']}x{cfg['width']} tanh, inputs (tau, S/K, sigma, r), bf16"
+    bsp.bs_tune_reset()
+    return out
 
 
 def measure_all(log=print) -> dict:

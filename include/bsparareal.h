@@ -258,9 +258,13 @@ int parareal_batch_workspace_size(int n_opt, const bs_params* prm, const bs_grid
  * uneven grids and slice counts).  Every phase of an iteration is one launch
  * per block-shape class covering all options of the class; options that have
  * converged, and slices that already hold the serial fine solution, are
- * skipped on the device, so with use_graph != 0 one iteration is captured
- * once as a hipGraph and replayed.  Stopping rule per option as in
- * parareal_solve (defect <= tol, k == N, or k == max_iter).
+ * skipped on the device, so iterations are queued ahead of their results:
+ * `lookahead` iterations (1..16; 0 selects 4) stay in flight, each followed by
+ * an asynchronous copy of the count of active options to pinned host memory,
+ * and the host waits only for the oldest (no per-iteration round trip; at
+ * most lookahead - 1 empty iterations run after the last option converges).
+ * Stopping rule per option as in parareal_solve (defect <= tol, k == N, or
+ * k == max_iter).
  * prm, grids, sl: host arrays [n_opt]; all options share payoff_mode; each
  *    grid has 1 <= M <= 4096 nodes (BS_ERR_ARG otherwise).
  * U: device FP64; option o's state [N_o+1][M_o] starts at element offsets[o]
@@ -277,7 +281,7 @@ int parareal_batch_workspace_size(int n_opt, const bs_params* prm, const bs_grid
 int parareal_solve_batch(int n_opt, const bs_params* prm, const bs_grid* grids,
                          const bs_slices* sl, int coarse_kind, double tol, const pinn_net* net,
                          int max_iter, void* ws, size_t ws_bytes, double* U, const long* offsets,
-                         int* iters, double* defects, int use_graph, void* stream);
+                         int* iters, double* defects, int lookahead, void* stream);
 
 /* Block shape of the tridiagonal kernels (for the autotuner).  Each system is
  * solved by one thread block of `threads` threads holding `nodes_per_thread`

@@ -351,7 +351,7 @@ def parareal_solve(p: dict, M: int, N: int, fine_steps: int, coarse_steps: int =
 
 def parareal_solve_batch(options, coarse_kind: int = COARSE_IE, tol: float = 1e-8,
                          net: PinnNet | None = None, max_iter: int | None = None,
-                         payoff_mode: int = 1, use_graph: bool = True):
+                         payoff_mode: int = 1, lookahead: int = 0):
     """Solve many options together.  `options`: dicts with K, r, sigma, T, s_max,
     is_put, M, N, fine_steps, coarse_steps.  Returns (U_packed [cuda float64],
     offsets, iters, defects, status); option o's state is
@@ -378,6 +378,6 @@ def parareal_solve_batch(options, coarse_kind: int = COARSE_IE, tol: float = 1e-
         max_iter = max(o["N"] for o in options)
     rc = _check(lib.parareal_solve_batch(
         n, Pa, Ga, Sa, coarse_kind, float(tol), ctypes.byref(net.c()) if net is not None else None,
-        int(max_iter), ws.data_ptr(), wsb, U.data_ptr(), Oa, it, de, int(bool(use_graph)),
+        int(max_iter), ws.data_ptr(), wsb, U.data_ptr(), Oa, it, de, int(lookahead),
         _stream()))
     return U, offs, list(it), list(de), rc

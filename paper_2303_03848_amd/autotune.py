@@ -123,3 +123,42 @@ def tune_workload(name: str, p: dict, M: int, N: int, fine_steps: int, use_cache
     if verbose:
         print(f"[autotune] {name}: fine {ent['fine']} sweep {ent['sweep']}", flush=True)
     return ent
+
+
+def tune_batch(name: str, options, use_cache: bool = True, path: str = CACHE,
+               verbose: bool = False):
+    """Pick and install the fine and sweep shapes of every grid size of a
+    batch of options (the batch solve launches one class per shape): per
+    distinct M, the fine shape is timed on as many systems as the batch has
+    slices of that M (a representative option's coefficients) and the sweep
+    shape on one representative option.  Returns {M: entry}."""
+    cache = load_cache(path) if use_cache else {}
+    key = _key(name)
+    ent = cache.get(key)
+    if ent is None:
+        ent = {}
+        for M in sorted({o["M"] for o in options}):
+            group = [o for o in options if o["M"] == M]
+            rep = group[len(group) // 2]
+            p = {k: rep[k] for k in ("K", "r", "sigma", "T", "s_max", "is_put")}
+            nsys = sum(o["N"] for o in group)
+            dT = rep["T"] / rep["N"]
+            bsp.bs_tune_reset()
+            bf, tf = tune_fine(p, M, nsys, rep["fine_steps"], dT)
+            bs, ts = tune_sweep(p, M, rep["N"], rep["fine_steps"])
+            ent[str(M)] = {"fine": list(bf), "sweep": list(bs), "systems": nsys,
+                           "fine_ms": {f"{a}x{b}": v for (a, b), v in tf.items()},
+                           "sweep_ms": {f"{a}x{b}": v for (a, b), v in ts.items()}}
+        cache[key] = ent
+        try:
+            with open(path, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+        except OSError:
+            pass
+    bsp.bs_tune_reset()
+    for M, e in ent.items():
+        bsp.bs_tune_set_shape(FINE, int(M), int(M), *e["fine"])
+        bsp.bs_tune_set_shape(SWEEP, int(M), int(M), *e["sweep"])
+        if verbose:
+            print(f"[autotune] {name} M={M}: fine {e['fine']} sweep {e['sweep']}", flush=True)
+    return ent

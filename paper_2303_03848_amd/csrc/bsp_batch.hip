@@ -7,9 +7,12 @@
 // per class the list of (option, slice) fine-propagator items and the list of
 // options for the sweep.  Blocks of converged options, and fine items of
 // slices that already hold the serial fine solution (n < k - 1), return at
-// once, so the launch configuration never changes between iterations: one
-// iteration is captured once in a hipGraph and replayed, and the host reads
-// back a single counter of still-active options per iteration.
+// once, so the launch configuration never changes between iterations and the
+// host can queue iterations ahead of their results: it keeps `lookahead`
+// iterations in flight, each followed by an asynchronous copy of the count of
+// still-active options into pinned host memory, and waits only for the
+// oldest of them (the device never idles on a host round trip; at most
+// lookahead - 1 empty iterations run after the last option converges).
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -228,19 +231,52 @@ static int make_plan(int n_opt, const bs_params* prm, const bs_grid* grids, cons
 
 // Streams for the shape classes of one phase.  The launches of a phase touch
 // disjoint items (fine) or options (sweep), so they run side by side: fork
-// from the caller's stream, one stream per class, join back on it (the same
-// calls build parallel branches when the iteration is captured in a graph).
+// from the caller's stream, one stream per class, join back on it.
 // Created once per thread and device, kept until the process ends.
 constexpr int kMaxClasses = 16;
 struct ClassStreams {
     int dev = -1;
     hipStream_t s[kMaxClasses] = {};
-    hipStream_t own = nullptr;  // stands in for the legacy default stream under capture
     hipEvent_t fork[2] = {}, join[2][kMaxClasses] = {};
 };
 static thread_local ClassStreams t_cls;
 
+// Pinned slots for the active counts of the iterations in flight and their
+// events; created once per thread and device, kept until released.
+constexpr int kDefaultLookahead = 4, kMaxLookahead = 16;
+struct LookaheadSlots {
+    int dev = -1;
+    int* active = nullptr;  // pinned host [kMaxLookahead]
+    hipEvent_t ev[kMaxLookahead] = {};
+};
+static thread_local LookaheadSlots t_look;
+
+static int release_lookahead() {
+    LookaheadSlots& L = t_look;
+    if (L.dev < 0) return BS_OK;
+    for (int i = 0; i < kMaxLookahead; ++i) BSP_HIP(hipEventDestroy(L.ev[i]));
+    BSP_HIP(hipHostFree(L.active));
+    L = LookaheadSlots{};
+    return BS_OK;
+}
+
+static int lookahead_slots() {
+    LookaheadSlots& L = t_look;
+    int dev = 0;
+    BSP_HIP(hipGetDevice(&dev));
+    if (L.dev == dev) return BS_OK;
+    int rc = release_lookahead();
+    if (rc) return rc;
+    BSP_HIP(hipHostMalloc((void**)&L.active, sizeof(int) * kMaxLookahead, hipHostMallocDefault));
+    for (int i = 0; i < kMaxLookahead; ++i)
+        BSP_HIP(hipEventCreateWithFlags(&L.ev[i], hipEventDisableTiming));
+    L.dev = dev;
+    return BS_OK;
+}
+
 int release_batch_resources() {
+    int rc = release_lookahead();
+    if (rc) return rc;
     ClassStreams& C = t_cls;
     if (C.dev < 0) return BS_OK;
     for (int i = 0; i < kMaxClasses; ++i) {
@@ -248,7 +284,6 @@ int release_batch_resources() {
         for (int ph = 0; ph < 2; ++ph) BSP_HIP(hipEventDestroy(C.join[ph][i]));
     }
     for (int ph = 0; ph < 2; ++ph) BSP_HIP(hipEventDestroy(C.fork[ph]));
-    BSP_HIP(hipStreamDestroy(C.own));
     C = ClassStreams{};
     return BS_OK;
 }
@@ -268,7 +303,6 @@ static int class_streams() {
             BSP_HIP(hipEventCreateWithFlags(&C.join[ph][i], hipEventDisableTiming));
     }
     for (int ph = 0; ph < 2; ++ph) BSP_HIP(hipEventCreateWithFlags(&C.fork[ph], hipEventDisableTiming));
-    BSP_HIP(hipStreamCreateWithFlags(&C.own, hipStreamNonBlocking));
     C.dev = dev;
     return BS_OK;
 }
@@ -367,12 +401,14 @@ extern "C" int parareal_solve_batch(int n_opt, const bs_params* prm, const bs_gr
                                     const bs_slices* sl, int kind, double tol,
                                     const pinn_net* net, int max_iter, void* ws, size_t ws_bytes,
                                     double* U, const long* offsets, int* iters, double* defects,
-                                    int use_graph, void* stream) {
+                                    int lookahead, void* stream) {
     clear_error();
     int rc = batch_checks(n_opt, prm, grids, sl, kind, net);
     if (rc) return rc;
     BSP_CHECK_ARG(U && offsets && iters, "U, offsets and iters must be non-NULL");
     BSP_CHECK_ARG(max_iter >= 1 && tol >= 0, "max_iter >= 1 and tol >= 0 required");
+    BSP_CHECK_ARG(lookahead >= 0 && lookahead <= kMaxLookahead, "lookahead must be 0..%d",
+                  kMaxLookahead);
     const bool is_net = kind != BS_COARSE_IE;
     BatchPlan P;
     if ((rc = make_plan(n_opt, prm, grids, sl, offsets, is_net, P))) return rc;
@@ -385,13 +421,6 @@ extern "C" int parareal_solve_batch(int n_opt, const bs_params* prm, const bs_gr
     }
     hipStream_t st = (hipStream_t)stream;
     const double growth = bs_divergence_growth();
-    // The legacy default stream cannot be captured: a graph run on it uses a
-    // library stream of this thread instead (the call is synchronous either way).
-    if (use_graph && st == nullptr) {
-        BSP_HIP(hipDeviceSynchronize());
-        if ((rc = class_streams())) return rc;
-        st = t_cls.own;
-    }
 
     // tables -> device (one staging copy)
     std::vector<FItem> items_flat;
@@ -452,43 +481,27 @@ extern "C" int parareal_solve_batch(int n_opt, const bs_params* prm, const bs_gr
         return BS_OK;
     };
 
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-    if (use_graph) {
-        BSP_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        rc = iteration();
-        hipGraph_t g2 = nullptr;
-        hipError_t e = hipStreamEndCapture(st, &g2);
-        if (rc) return rc;
-        if (e != hipSuccess) {
-            set_error("graph capture failed: %s", hipGetErrorString(e));
-            return BS_ERR_HIP;
+    // iterations queued ahead: after each one an asynchronous copy of the
+    // active count to a pinned slot and an event; the host waits for the
+    // oldest iteration in flight only, and stops queueing once a copied count
+    // is zero (iterations already queued then return at once on the device)
+    if ((rc = lookahead_slots())) return rc;
+    const int L = lookahead == 0 ? kDefaultLookahead : lookahead;
+    LookaheadSlots& LS = t_look;
+    int queued = 0, checked = 0;
+    bool finished = false;
+    while (!finished && checked < kmax) {
+        while (queued < kmax && queued - checked < L) {
+            if ((rc = iteration())) return rc;
+            BSP_HIP(hipMemcpyAsync(LS.active + queued % L, w.counters + 1, sizeof(int),
+                                   hipMemcpyDeviceToHost, st));
+            BSP_HIP(hipEventRecord(LS.ev[queued % L], st));
+            ++queued;
         }
-        graph = g2;
-        BSP_HIP(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        BSP_HIP(hipEventSynchronize(LS.ev[checked % L]));
+        finished = LS.active[checked % L] == 0;
+        ++checked;
     }
-    int active = n_opt;
-    for (int k = 1; k <= kmax && active > 0; ++k) {
-        if (use_graph) {
-            if (hipGraphLaunch(gexec, st) != hipSuccess) {
-                set_error("graph launch failed");
-                rc = BS_ERR_HIP;
-                break;
-            }
-        } else if ((rc = iteration())) {
-            break;
-        }
-        if (hipMemcpyAsync(&active, w.counters + 1, sizeof(int), hipMemcpyDeviceToHost, st) !=
-                hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess) {
-            set_error("read-back of the active count failed");
-            rc = BS_ERR_HIP;
-            break;
-        }
-    }
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (rc) return rc;
 
     std::vector<BatchState> out(n_opt);
     BSP_HIP(hipMemcpyAsync(out.data(), w.state, sizeof(BatchState) * n_opt, hipMemcpyDeviceToHost, st));

@@ -68,7 +68,7 @@ def cpu_model() -> str:
 # Sources of the large-grid F kernel; a traffic figure taken from counters is
 # reported only while they are unchanged since the counters were taken.
 F_SOURCES = ["bsp_propagate.hip", "bsp_steps.hpp", "bsp_tridiag.hpp", "bsp_tridiag_rc.hpp",
-             "bsp_common.hpp"]
+             "bsp_tridiag_large.hpp", "bsp_common.hpp"]
 
 
 def f_kernel_hash() -> str:
@@ -350,6 +350,8 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain elementwise copy of MIB MiB (float64) so a "
                          "counter profile of this command has a copy kernel of known size")
+    ap.add_argument("--calibrate-only", action="store_true",
+                    help="exit after the calibration copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (the "
@@ -372,6 +374,8 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] calibration copy: {n} doubles ({8 * n} bytes read, {8 * n} written)")
         del src, dst
+        if args.calibrate_only:
+            return
 
     if args.workload == "large_put":
         out = bench_large_put(args, bsp, torch)

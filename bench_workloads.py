@@ -148,3 +148,35 @@ def measure_all(log=print) -> dict:
         out[name] = fn()
         log(f"[workloads] {name}: {time.time() - t0:.1f}s {out[name]}")
     return out
+
+
+def main():
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="measure the non-headline workloads (one GPU)")
+    ap.add_argument("--only", choices=["small_call", "train_step", "option_batch"], action="append",
+                    help="run only these (repeatable); default: all")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first run one plain elementwise copy of MIB MiB (float64) so a counter "
+                         "profile of this command has a copy kernel of known size")
+    args = ap.parse_args()
+    torch.cuda.init()
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.rand(n + 1, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src[1:], out=dst[1:])
+        torch.cuda.synchronize()
+        del src, dst
+    fns = {"small_call": small_call, "train_step": train_step, "option_batch": batch_options}
+    out = {}
+    for name in args.only or list(fns):
+        t0 = time.time()
+        out[name] = fns[name]()
+        print(f"[workloads] {name}: {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -428,7 +428,7 @@ __global__ __launch_bounds__(T) void k_rc_theta(ThetaArgs a) {
     load_chunk<T, MC>(a.u_in + (long)sys * a.ld_in, a.M, V);
     const bool slow = Fa.nst > kRcRegStages;  // the same in every thread of the block
     // The steps run in polled runs (the stop flag is checked between runs of
-    // kPollSteps steps): besides ending a cancelled launch early, the check
+    // kRunSteps steps): besides ending a cancelled launch early, the check
     // points let the register allocator keep the step loop free of spills
     // (measured: 40 scratch accesses per step without them, none with them).
     const int* stop = a.stop ? a.stop : &g_no_stop;
@@ -514,7 +514,7 @@ int launch_large_sweep_setup(const OptionDev& o, int M, double dT, int coarse_st
 // U[n]; fdone: Fv[n] holds iteration k's result), exactly as in the solve
 // that overlaps launches on side streams; the iterates are those of the
 // one-iteration-at-a-time solve.  The fine blocks poll the stop flag every
-// kPollSteps steps.  Every block must be resident (N blocks, one per compute
+// kRunSteps steps.  Every block must be resident (N blocks, one per compute
 // unit): the host checks the device's capacity first.
 constexpr int kLargePersistMaxN = 256;
 // Slices per hand-off batch of the sweep block (one acquire and one release

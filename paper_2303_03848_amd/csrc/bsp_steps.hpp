@@ -131,6 +131,11 @@ struct HasPipe<BlockTriH<W, MC>> : std::true_type {};
 // period before it is tested, so the load is never waited for) and returns
 // false when it is set; the state is then left half-propagated.
 constexpr int kPollSteps = 64;
+// The plain step loop (large grids) runs kRunSteps steps between checks: the
+// compiler spills part of the state around each check point (scratch
+// traffic), so the runs are longer there (a check costs at most kRunSteps
+// steps of latency once the flag is set).
+constexpr int kRunSteps = 256;
 
 // Forcing table of the pipelined steps for steps m0+1 .. m0+n+1 (entries
 // past the last step are zero), built by the block's T threads.
@@ -281,9 +286,9 @@ __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
         }
         double flo_n = homog ? 0.0 : ftab[0];
         double fhi_n = homog ? 0.0 : ftab[kForceChunk];
-        // POLL: runs of kPollSteps steps with the check between them, so the
+        // POLL: runs of kRunSteps steps with the check between them, so the
         // step loop itself carries no test
-        for (int i0 = 0; i0 < nch; i0 += kPollSteps) {
+        for (int i0 = 0; i0 < nch; i0 += kRunSteps) {
             if constexpr (POLL) {  // the same decision in every thread of the system
                 if (sv) return false;
                 if constexpr (WAVE || T == 64)
@@ -291,7 +296,7 @@ __device__ __forceinline__ bool theta_steps(const Solver& S, const OptionDev& o,
                 else
                     sv = __syncthreads_or(pipe_load(stop) != 0);
             }
-            const int i1 = min(nch, i0 + kPollSteps);
+            const int i1 = min(nch, i0 + kRunSteps);
             for (int i = i0; i < i1; ++i) {
                 const double flo = flo_n, fhi = fhi_n;
                 if (!homog && i + 1 < nch) {

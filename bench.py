@@ -260,21 +260,30 @@ def cpu_baseline_fine(p, M, N, Sf, name):
     def one(n):
         return oracle.fine(po, M, n * dT, dT, Sf, u0)
 
-    reps, t_all = 0, 0.0
+    reps, t_all, rounds = 0, 0.0, []
     with ThreadPoolExecutor(threads) as ex:
         while t_all < 10.0 and reps < 50:
             t0 = time.perf_counter()
             list(ex.map(one, range(threads)))
-            t_all += time.perf_counter() - t0
+            rounds.append(time.perf_counter() - t0)
+            t_all += rounds[-1]
             reps += 1
+    # one slice on one core (serial fine integration is N of these in a row)
+    t0 = time.perf_counter()
+    one(0)
+    t_one = time.perf_counter() - t0
     cells = reps * threads * Sf * M
-    log(f"[bench] cpu oracle: {reps} rounds of {threads} slices in {t_all:.2f}s")
+    log(f"[bench] cpu oracle: {reps} rounds of {threads} slices in {t_all:.2f}s; "
+        f"one slice on one core {t_one:.3f}s")
     return {"value": cells / t_all, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": (f"oracle fine propagator ({Sf} Crank-Nicolson steps on {M} nodes, the "
                        f"{name} slice) on {threads} slices at once, one per thread, {reps} "
                        f"rounds: {t_all:.2f} s; {1e3 * t_all / reps:.1f} ms per round"),
             "cpu_model": cpu_model(),
             "seconds_per_slice_round": t_all / reps,
+            "seconds_per_round_std": float(np.std(rounds)),
+            "one_core_seconds_per_slice": t_one,
+            "one_core_serial_fine_seconds_estimate": N * t_one,
             "note": "built -O2 -ffp-contract=off (the parity build); a whole oracle Parareal "
                     "solve of this workload would take minutes"}
 

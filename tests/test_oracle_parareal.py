@@ -12,6 +12,11 @@
   prediction equal to the serial fine solution, so the first defect is 0.
 * The numerical coarse propagator converges to tol before k = N on the
   network workload's grid.
+* With the anchor set to the numerical coarse trajectory itself, the
+  network-anchored coarse (anchor + implicit Euler with zero boundary data
+  on the deviation) equals the numerical coarse, by linearity of the
+  implicit-Euler map, for any number of coarse steps per slice: this pins
+  the deviation solve's step size and step count.
 """
 import numpy as np
 import pytest
@@ -111,3 +116,31 @@ def test_threads_do_not_change_result():
     b = oracle.parareal(p, cfg["M"], cfg["N"], cfg["fine_steps"], 1, oracle.COARSE_IE, tol=1e-8,
                         nthreads=4)
     assert np.array_equal(a["U"], b["U"]) and a["iters"] == b["iters"]
+
+
+@pytest.mark.parametrize("coarse_steps", [1, 3])
+def test_network_anchor_on_coarse_trajectory_equals_numeric_coarse(coarse_steps):
+    cfg = dict(SMALL_CALL, N=6, fine_steps=16)
+    p = _p(cfg)
+    M, N = cfg["M"], cfg["N"]
+    dT = p.T / N
+    Vt = np.empty((N + 1, M))
+    Vt[0] = oracle.initial(p, M)
+    for n in range(N):
+        Vt[n + 1] = oracle.coarse_ie(p, M, n * dT, dT, coarse_steps, Vt[n])
+    a = oracle.parareal(p, M, N, cfg["fine_steps"], coarse_steps, oracle.COARSE_PINN_IE, Vt=Vt,
+                        tol=0.0, keep_iterates=True)
+    b = oracle.parareal(p, M, N, cfg["fine_steps"], coarse_steps, oracle.COARSE_IE, tol=0.0,
+                        keep_iterates=True)
+    scale = np.abs(b["iterates"]).max()
+    assert np.abs(a["iterates"] - b["iterates"]).max() <= 1e-12 * scale
+    # a wrong step (the whole slice in each of the coarse steps) breaks it
+    if coarse_steps > 1:
+        wrong = np.empty_like(Vt)
+        wrong[0] = Vt[0]
+        for n in range(N):
+            wrong[n + 1] = oracle.coarse_ie(p, M, n * dT, coarse_steps * dT, coarse_steps,
+                                            wrong[n])
+        c = oracle.parareal(p, M, N, cfg["fine_steps"], coarse_steps, oracle.COARSE_PINN_IE,
+                            Vt=wrong, tol=0.0, keep_iterates=True)
+        assert np.abs(c["iterates"][0] - b["iterates"][0]).max() > 1e-6 * scale

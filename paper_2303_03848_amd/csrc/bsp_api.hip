@@ -64,7 +64,19 @@ struct Workspace {
     double* U2;
     double* Vt;
     double* tab;  // grids beyond 4096 nodes: the sweep's implicit-Euler tables
+    // grids beyond 4096 nodes: chunk-major copies of U, Fv, Gold and Vt for
+    // the overlapped solve (large_cm_level(M) doubles per level)
+    double* cm_U;
+    double* cm_Fv;
+    double* cm_Gold;
+    double* cm_Vt;
 };
+
+// Doubles of the chunk-major region: U and Vt (N+1 levels), Fv and Gold (N).
+static size_t cm_doubles(int M, int N, int kind) {
+    const size_t L = (size_t)large_cm_level(M);
+    return L * ((size_t)(N + 1) + 2 * (size_t)N + (kind != BS_COARSE_IE ? (size_t)(N + 1) : 0));
+}
 
 static int flag_count(int N) { return 4 * (N + 1) + 3; }
 
@@ -78,6 +90,7 @@ static size_t ws_bytes(int M, int N, int kind) {
     if (persist_possible(M, N)) b += align256(sizeof(double) * (size_t)(N + 1) * M);
     if (kind != BS_COARSE_IE) b += align256(sizeof(double) * (size_t)(N + 1) * M);
     b += align256(sizeof(double) * large_sweep_table_doubles(M));
+    b += align256(sizeof(double) * cm_doubles(M, N, kind));
     return b;
 }
 
@@ -103,6 +116,14 @@ static Workspace ws_layout(void* ws, int M, int N, int kind) {
         p += align256(sizeof(double) * (size_t)(N + 1) * M);
     }
     w.tab = large_sweep_table_doubles(M) ? (double*)p : nullptr;
+    p += align256(sizeof(double) * large_sweep_table_doubles(M));
+    w.cm_U = w.cm_Fv = w.cm_Gold = w.cm_Vt = nullptr;
+    if (const long L = large_cm_level(M)) {
+        w.cm_U = (double*)p;
+        w.cm_Fv = w.cm_U + (size_t)(N + 1) * L;
+        w.cm_Gold = w.cm_Fv + (size_t)N * L;
+        if (kind != BS_COARSE_IE) w.cm_Vt = w.cm_Gold + (size_t)N * L;
+    }
     return w;
 }
 
@@ -581,10 +602,15 @@ static int solve_large(const bs_params* prm, const bs_grid* grid, const bs_slice
     a.dT = dT;
     a.tol = tol;
     a.growth = growth;
-    a.U = U;
-    a.Fv = w.Fv;
-    a.Gold = w.Gold;
-    a.Vt = w.Vt;
+    // the launch works on chunk-major copies of U, Fv, Gold and Vt
+    if ((rc = launch_cm_convert(U, w.cm_U, N + 1, M, true, st))) return rc;
+    if ((rc = launch_cm_convert(w.Fv, w.cm_Fv, N, M, true, st))) return rc;
+    if ((rc = launch_cm_convert(w.Gold, w.cm_Gold, N, M, true, st))) return rc;
+    if (w.Vt && (rc = launch_cm_convert(w.Vt, w.cm_Vt, N + 1, M, true, st))) return rc;
+    a.U = w.cm_U;
+    a.Fv = w.cm_Fv;
+    a.Gold = w.cm_Gold;
+    a.Vt = w.cm_Vt;
     a.result = w.result;
     a.stop = stop;
     a.hist = S.hist_dev;
@@ -592,6 +618,10 @@ static int solve_large(const bs_params* prm, const bs_grid* grid, const bs_slice
     if (prof) BSP_HIP(hipEventRecord(g_prof.ev[2], st));
     if ((rc = launch_large_persist(a, st))) return rc;
     if (prof) BSP_HIP(hipEventRecord(g_prof.ev[3], st));
+    // the iterate, the fine results and the coarse values back in node order
+    if ((rc = launch_cm_convert(w.cm_U, U, N + 1, M, false, st))) return rc;
+    if ((rc = launch_cm_convert(w.cm_Fv, w.Fv, N, M, false, st))) return rc;
+    if ((rc = launch_cm_convert(w.cm_Gold, w.Gold, N, M, false, st))) return rc;
     int err = 0;
     BSP_HIP(hipMemcpyAsync(&err, ps.err, sizeof(int), hipMemcpyDeviceToHost, st));
     BSP_HIP(hipStreamSynchronize(st));

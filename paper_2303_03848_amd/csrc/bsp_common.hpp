@@ -282,6 +282,7 @@ struct LargePersistArgs {
     OptionDev o;
     int M, N, kmax, fine_steps, coarse_steps, kind;
     double dT, tol, growth;
+    // U, Fv, Gold, Vt: chunk-major levels (large_cm_level(M) doubles apart)
     double* U;
     double* Fv;
     double* Gold;
@@ -294,6 +295,12 @@ struct LargePersistArgs {
     const double* ptab;
 };
 bool large_persist_capable(int M, int N);
+// Grids beyond 4096 nodes: doubles per chunk-major level (T * MC of the
+// fine shape), 0 for smaller grids; conversion of `levels` levels between
+// node order [levels][M] and chunk-major [levels][T*MC].
+long large_cm_level(int M);
+int launch_cm_convert(const double* src, double* dst, int levels, int M, bool to_cm,
+                      hipStream_t stream);
 int launch_large_persist(const LargePersistArgs& a, hipStream_t stream);
 
 // The one-launch solve can cover this problem size (block shapes aside).

@@ -547,7 +547,7 @@ __device__ __forceinline__ void large_fine_role(const LargePersistArgs& a, int n
     for (int k = 2; k <= klast; ++k) {
         if (!pipe_wait(ps, ps.ready + n, k, a.stop, pslot)) return;
         double V[MC];
-        load_chunk<T, MC>(a.U + (long)n * a.M, a.M, V);
+        load_cm<T, MC>(a.U + (long)n * (T * MC), V);
         pipe_signal(ps.taken + n, k);  // the loads have completed (release fence)
         const bool ok =
             slow ? theta_steps<T, MC, true, BlockTriR<T, MC, HI, true, true>, true>(
@@ -560,7 +560,7 @@ __device__ __forceinline__ void large_fine_role(const LargePersistArgs& a, int n
         // Fv[n] of iteration k-1 has been used once the sweep of iteration k-1
         // has written U[n+1]
         if (!pipe_wait<false>(ps, ps.ready + n + 1, k, a.stop, pslot)) return;
-        store_chunk<T, MC>(a.Fv + (long)n * a.M, a.M, V);
+        store_cm<T, MC>(a.Fv + (long)n * (T * MC), a.M, V);
         pipe_signal(ps.fdone + n, k);
     }
 }
@@ -580,9 +580,9 @@ __device__ __forceinline__ void large_sweep_role(const LargePersistArgs& a, doub
         const int n0 = min(k - 1, a.N - 1);
         double dmax = 0.0;
         int bad = 0;
-        const bool ok = sweep_slices<T, MC>(S, a.o, a.M, a.N, n0, a.coarse_steps, a.kind, false,
-                                            a.dT, a.U, a.U, a.Fv, a.Gold, a.Vt, lds, ftab, dmax,
-                                            bad, ps, true, a.stop, pslot, 0, kLargeSweepBatch);
+        const bool ok = sweep_slices<T, MC, BlockTriG<T, MC>, true>(
+            S, a.o, a.M, a.N, n0, a.coarse_steps, a.kind, false, a.dT, a.U, a.U, a.Fv, a.Gold,
+            a.Vt, lds, ftab, dmax, bad, ps, true, a.stop, pslot, 0, kLargeSweepBatch);
         if (!ok) return;
         block_defect<T>(dmax, bad, lds);
         if (threadIdx.x == 0) {
@@ -608,6 +608,50 @@ __global__ __launch_bounds__(512) void k_large_persist(LargePersistArgs a) {
         large_fine_role<MC, HI>(a, (int)blockIdx.x + 1, smem, &pslot);
     else
         large_sweep_role<MC>(a, smem, &pslot);
+}
+
+// Levels [levels][M] (node order) to and from the chunk-major layout
+// [levels][T*MC] of the overlapped solve (zero past the grid).  One thread
+// per chunk-major entry: the chunk-major side is coalesced, the node-order
+// side reads or writes with stride MC (whole lines end up used through L2).
+__global__ void k_to_cm(const double* __restrict__ src, double* __restrict__ dst, int M, int T,
+                        int MC) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= T * MC) return;
+    const long lev = blockIdx.y;
+    const int node = (e % T) * MC + e / T;
+    dst[lev * T * MC + e] = node < M ? src[lev * M + node] : 0.0;
+}
+
+__global__ void k_from_cm(const double* __restrict__ src, double* __restrict__ dst, int M, int T,
+                          int MC) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= T * MC) return;
+    const long lev = blockIdx.y;
+    const int node = (e % T) * MC + e / T;
+    if (node < M) dst[lev * M + node] = src[lev * T * MC + e];
+}
+
+long large_cm_level(int M) {
+    const TriShape f = shape_for(0, M);
+    return is_large(f) ? (long)f.T * f.MC : 0;
+}
+
+int launch_cm_convert(const double* src, double* dst, int levels, int M, bool to_cm,
+                      hipStream_t stream) {
+    const TriShape f = shape_for(0, M);
+    if (!is_large(f) || levels < 0 || levels > 65535) {
+        set_error("chunk-major levels: M = %d, %d levels", M, levels);
+        return BS_ERR_ARG;
+    }
+    if (levels == 0) return BS_OK;
+    const dim3 grid((f.T * f.MC + 255) / 256, levels), block(256);
+    if (to_cm)
+        hipLaunchKernelGGL(k_to_cm, grid, block, 0, stream, src, dst, M, f.T, f.MC);
+    else
+        hipLaunchKernelGGL(k_from_cm, grid, block, 0, stream, src, dst, M, f.T, f.MC);
+    BSP_LAUNCHED();
+    return BS_OK;
 }
 
 // The kernel instance for grid M and its slot in the residency cache.

@@ -43,6 +43,25 @@ __device__ __forceinline__ void store_chunk(double* __restrict__ dst, int M, con
         if (i0 + q < M) dst[i0 + q] = V[q];
 }
 
+// Chunk-major layout of a level of T * MC nodes (the overlapped solve on
+// large grids keeps its internal copies of U, Fv, Gold and Vt this way):
+// node p*MC + q sits at q*T + p, so that thread p's chunk is read and
+// written by whole-wavefront accesses of 64 consecutive doubles; entries past
+// the grid hold zero (written by the conversion, never stored to again).
+template <int T, int MC>
+__device__ __forceinline__ void load_cm(const double* __restrict__ src, double (&V)[MC]) {
+#pragma unroll
+    for (int q = 0; q < MC; ++q) V[q] = src[q * T + threadIdx.x];
+}
+
+template <int T, int MC>
+__device__ __forceinline__ void store_cm(double* __restrict__ dst, int M, const double (&V)[MC]) {
+    const int i0 = threadIdx.x * MC;
+#pragma unroll
+    for (int q = 0; q < MC; ++q)
+        if (i0 + q < M) dst[q * T + threadIdx.x] = V[q];
+}
+
 // Steps per boundary-forcing table (two tables of this many doubles in LDS).
 constexpr int kForceChunk = 1024;
 
@@ -457,6 +476,55 @@ __device__ __forceinline__ void combine_staged(const double* __restrict__ src, i
     __syncthreads();  // the coarse solve may overwrite the staging area
 }
 
+// The correction of correct_staged on chunk-major levels (no staging: every
+// access is coalesced in chunk order).  Same operations per node, so the
+// same results.  uo1 and un1 may be the same level (each entry is read
+// before it is written); rows are taken in groups of G, a group's loads
+// issued together (a second buffer to overlap the next group's loads made
+// the sweep block spill).  Not for the prediction (no predict form).
+template <int T, int MC, int MODE>
+__device__ __forceinline__ void correct_cm(double (&g)[MC], int M,
+                                           const double* __restrict__ fv,
+                                           double* __restrict__ go, const double* uo1,
+                                           double* un1, const double* __restrict__ vt1,
+                                           double& dmax, int& bad) {
+    constexpr int G = 8;
+    static_assert(MC % G == 0, "whole groups");
+    const int p = threadIdx.x, i0 = p * MC;
+    double f[G], gl[G], uo[G], v[G];
+    auto load = [&](int q0) {
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const int c = (q0 + j) * T + p;
+            f[j] = fv[c];
+            gl[j] = go[c];
+            uo[j] = uo1[c];
+            v[j] = MODE != kCoarseSolve ? vt1[c] : 0.0;
+        }
+    };
+#pragma unroll
+    for (int q0 = 0; q0 < MC; q0 += G) {
+        load(q0);
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const int q = q0 + j, c = q * T + p;
+            if (i0 + q < M) {
+                const double gg = MODE == kCoarseSolve ? g[q]
+                                  : MODE == kCoarseNet ? v[j]
+                                                       : v[j] + g[q];
+                const double unew = f[j] + (gg - gl[j]);
+                go[c] = gg;
+                un1[c] = unew;
+                dmax = fmax(dmax, fabs(unew - uo[j]));
+                bad |= !isfinite(unew);
+                g[q] = MODE == kCoarseNetDev ? unew - v[j] : unew;
+            } else {
+                g[q] = 0.0;
+            }
+        }
+    }
+}
+
 // One option's serial Parareal sweep over slices n = n0..N-1 in one block:
 //   g = G(U[n])                       (state carried in registers)
 //   predict: U[n+1] = g, Gold[n] = g
@@ -475,7 +543,7 @@ __device__ __forceinline__ void combine_staged(const double* __restrict__ src, i
 // array except in the one-launch solve, which alternates two buffers by
 // iteration parity (there the first state is also copied to Uout, so that
 // Uout holds a whole iterate, and taken_lag is 1: Uout held iterate k-2).
-template <int T, int MC, class Solver>
+template <int T, int MC, class Solver, bool CM = false>
 __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o, int M,
                                              int N, int n0, int coarse_steps, int kind, bool predict,
                                              double dT, const double* Uin, double* Uout,
@@ -494,25 +562,42 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
     // overlaps it (when registers allow: small chunks); larger chunks move
     // the slice's global traffic through the staged, node-order correction.
     constexpr bool kPrefetch = MC <= 4;
+    static_assert(!CM || !kPrefetch, "chunk-major levels are for chunks of 8 or more nodes");
+    // CM: the levels of Uin, Uout, Fv, Gold and Vt are chunk-major, T * MC
+    // doubles apart
+    const long ld = CM ? (long)T * MC : (long)M;
     double V[MC];
-    load_chunk<T, MC>(Uin + (long)n0 * M, M, V);
+    if constexpr (CM)
+        load_cm<T, MC>(Uin + n0 * ld, V);
+    else
+        load_chunk<T, MC>(Uin + (long)n0 * M, M, V);
     if (Uout != Uin) {
         // Uout[n0] still holds the iterate the fine launch of iteration
         // k - taken_lag reads
         if (pipe && !pipe_wait<false>(ps, ps.taken + n0, ps.k - taken_lag, stop, pslot))
             return false;
-        store_chunk<T, MC>(Uout + (long)n0 * M, M, V);
+        if constexpr (CM)
+            store_cm<T, MC>(Uout + n0 * ld, M, V);
+        else
+            store_chunk<T, MC>(Uout + (long)n0 * M, M, V);
     }
     if (!kPrefetch && kind == BS_COARSE_PINN_IE) {
         // staged path: the state carried from slice to slice is the
         // deviation from the network, U[n] - Vt_n
-        combine_staged<T, MC>(Vt + (long)n0 * M, M, V, lds + 4 * T,
-                              [](double a, double v) { return a - v; });
+        if constexpr (CM) {
+            double v0[MC];
+            load_cm<T, MC>(Vt + n0 * ld, v0);
+#pragma unroll
+            for (int q = 0; q < MC; ++q) V[q] = V[q] - v0[q];
+        } else {
+            combine_staged<T, MC>(Vt + (long)n0 * M, M, V, lds + 4 * T,
+                                  [](double a, double v) { return a - v; });
+        }
     }
     for (int n = n0; n < N; ++n) {
-        const double* uo1 = Uin + (long)(n + 1) * M;
-        double* un1 = Uout + (long)(n + 1) * M;
-        double* go = Gold + (long)n * M;
+        const double* uo1 = Uin + (n + 1) * ld;
+        double* un1 = Uout + (n + 1) * ld;
+        double* go = Gold + n * ld;
         double fv[MC], gold[MC], uold[MC], vt0[MC], vt1[MC];
         if constexpr (kPrefetch) {
             if (!predict && !pipe) {
@@ -576,7 +661,18 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
                 if (!pipe_wait<false>(ps, ps.taken + m + 1, ps.k - taken_lag, stop, pslot))
                     return false;
         }
-        if constexpr (!kPrefetch) {
+        if constexpr (CM) {
+            const double* vn1 = net ? Vt + (n + 1) * ld : nullptr;
+            if (kind == BS_COARSE_IE)
+                correct_cm<T, MC, kCoarseSolve>(g, M, Fv + n * ld, go, uo1, un1, vn1, dmax, bad);
+            else if (kind == BS_COARSE_PINN)
+                correct_cm<T, MC, kCoarseNet>(g, M, Fv + n * ld, go, uo1, un1, vn1, dmax, bad);
+            else
+                correct_cm<T, MC, kCoarseNetDev>(g, M, Fv + n * ld, go, uo1, un1, vn1, dmax,
+                                                 bad);
+#pragma unroll
+            for (int q = 0; q < MC; ++q) V[q] = g[q];
+        } else if constexpr (!kPrefetch) {
             // chunks of 8 or more nodes: the slice's global traffic goes
             // through the staged, node-order correction
             const double* vn1 = net ? Vt + (long)(n + 1) * M : nullptr;

@@ -12,12 +12,15 @@
   data_coarse     the same network trained on fine-propagator data alone
                   (no PDE terms) against the physics-informed one and the
                   numerical coarse propagator (Sec. 4, Fig. 3).
+  flowmap         a flow-map network coarse (Sec. 3.3's interface: slice
+                  start and end, the state, the asset price) fitted to
+                  fine-propagator data, against the numerical coarse.
 
 Every number comes from the library's kernels; training runs through the
 hand-written loss-and-gradient kernel.  The fine reference is serial fine
 integration on the same GPU (one system, all steps in one launch).
 
-Usage: python bench_studies.py nsweep|generalization|data_coarse [options]
+Usage: python bench_studies.py nsweep|generalization|data_coarse|flowmap [options]
 """
 from __future__ import annotations
 
@@ -259,6 +262,62 @@ def study_data_coarse(args, bsp, torch):
             "training_data_only": info_d, "training_physics": info_p, "slices": out_n}
 
 
+# ------------------------------------------------------------------ flowmap
+
+def study_flowmap(args, bsp, torch):
+    """A flow-map network coarse: w(tau_s, tau_e, V_s/K, S/K) -> V_e/K fitted
+    to fine-propagator data (the paper gives no loss for this interface):
+    states from the serial fine trajectory and from the first iterates of
+    Parareal with the numerical coarse, each propagated over its slice by the
+    fine propagator; then Parareal with it against the numerical coarse."""
+    from workloads import PINN_CALL, option_params
+    from paper_2303_03848_amd.pinn import train_on_data
+    cfg = PINN_CALL
+    p = option_params(cfg)
+    M, N, Sf, tol = cfg["M"], cfg["N"], cfg["fine_steps"], cfg["tol"]
+    dT = p["T"] / N
+    states = [_fine_levels(bsp, torch, p, M, N, Sf)[:N]]
+    pr = bsp.Parareal(p, M, N, Sf, 1, bsp.COARSE_IE)
+    states.append(pr.start()[:N].clone())
+    for k in range(1, args.iterate_states + 1):
+        pr.iterate(k)
+        states.append(pr.U[:N].clone())
+    S = torch.arange(1, M + 1, dtype=torch.float64, device="cuda") * (p["s_max"] / (M + 1))
+    tau0 = torch.arange(N, dtype=torch.float64, device="cuda") * dT
+    Xs, ys = [], []
+    for U in states:
+        Fv = bsp.bs_fine_propagate_batch(p, M, tau0, dT, Sf, U.contiguous())
+        X = torch.stack([tau0[:, None].expand(-1, M), (tau0 + dT)[:, None].expand(-1, M),
+                         U / p["K"], (S / p["K"])[None, :].expand(N, -1)], 2).reshape(-1, 4)
+        Xs.append(X.float())
+        ys.append((Fv / p["K"]).reshape(-1).float())
+    X, y = torch.cat(Xs), torch.cat(ys)
+    t0 = time.time()
+    net, info = train_on_data(p, X, y, 4, cfg["depth"], cfg["width"],
+                              epochs_hi=args.epochs[0], epochs_lo=args.epochs[1])
+    log(f"[flowmap] 4-input network fitted to {X.shape[0]} fine-propagator pairs in "
+        f"{time.time() - t0:.1f}s: {info}")
+    U_ref = _fine_levels(bsp, torch, p, M, N, Sf)
+    res = {}
+    for name, kind, prec in (("ie", bsp.COARSE_IE, None),
+                             ("flowmap_fp32", bsp.COARSE_FLOWMAP, bsp.PREC_FP32),
+                             ("flowmap_bf16", bsp.COARSE_FLOWMAP, bsp.PREC_BF16)):
+        nn = None if prec is None else bsp.PinnNet(net.params, 4, net.depth, net.width, prec)
+        q = bsp.Parareal(p, M, N, Sf, 1, kind, nn)
+        it, d, ms = _solve_timed(bsp, torch, q, tol, 3)
+        q.start()
+        coarse_err = [float((q.U[n] - U_ref[n]).norm() / U_ref[n].norm()) for n in range(1, N + 1)]
+        res[name] = {"iters": it, "time_to_solution_ms": ms, "first_defect": d[0],
+                     "defects": d, "coarse_nl2_error_by_level": coarse_err}
+        log(f"[flowmap] {name}: K={it} {ms:.3f} ms, first defect {d[0]:.3e}, coarse error at T "
+            f"{coarse_err[-1]:.2e}")
+    return {"study": "flowmap", "workload": cfg["name"], "M": M, "N": N, "fine_steps": Sf,
+            "tol": tol, "training": dict(info, pairs=int(X.shape[0]),
+                                         state_sets=len(states)),
+            "network": f"{cfg['depth']}x{cfg['width']} tanh, inputs (tau_s, tau_e, V_s/K, S/K)",
+            "coarse": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="study", required=True)
@@ -275,13 +334,17 @@ def main():
     d.add_argument("--epochs", type=int, nargs=2, default=(5000, 800))
     d.add_argument("--data-levels", type=int, default=128)
     d.add_argument("--slices", type=int, nargs="+", default=[16, 32])
+    f = sub.add_parser("flowmap")
+    f.add_argument("--epochs", type=int, nargs=2, default=(1500, 300))
+    f.add_argument("--iterate-states", type=int, default=2,
+                   help="iterates of the numerical-coarse Parareal added to the training states")
     args = ap.parse_args()
 
     import torch
     import paper_2303_03848_amd as bsp
     torch.cuda.init()
     fn = {"nsweep": study_nsweep, "generalization": study_generalization,
-          "data_coarse": study_data_coarse}[args.study]
+          "data_coarse": study_data_coarse, "flowmap": study_flowmap}[args.study]
     print(json.dumps(fn(args, bsp, torch)), flush=True)
 
 

@@ -94,8 +94,16 @@ typedef struct bs_slices {
  *                       implicit-Euler steps with zero boundary data: the
  *                       network anchors the state, one cheap solve carries
  *                       the deviation.
+ *   BS_COARSE_FLOWMAP : G(U_n)(S_j) = K * w(tau_n, tau_{n+1}, U_n(S_j) / K, S_j / K)
+ *                       with w a network of 4 inputs: the coarse interface
+ *                       of Sec. 3.3 (slice start and end, the state at the
+ *                       start, the asset price) applied node by node to the
+ *                       state.  Evaluated inside the sweep, slice after
+ *                       slice; parareal_start, parareal_iterate and
+ *                       parareal_solve only (iterations one after the other;
+ *                       coarse_steps unused).
  * Vt_n(S_j) = K * v(tau_n, S_j / K) with v the network of `pinn_net`. */
-enum { BS_COARSE_IE = 0, BS_COARSE_PINN = 1, BS_COARSE_PINN_IE = 2 };
+enum { BS_COARSE_IE = 0, BS_COARSE_PINN = 1, BS_COARSE_PINN_IE = 2, BS_COARSE_FLOWMAP = 3 };
 
 /* Network arithmetic. */
 enum { BS_PREC_FP32 = 0, BS_PREC_BF16 = 1 };

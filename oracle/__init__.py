@@ -9,6 +9,8 @@ calls it, and it never calls the HIP library; the two share no code.
   serial fine integration, Parareal and the closed-form price.
 * ``mlp.py`` holds the network, its input-derivative streams, the PINN loss
   and its hand-written gradient, in numpy float64.
+* ``flowmap.py`` holds Parareal with a flow-map network coarse (the network
+  sees the state), in plain Python loops over the C oracle's fine propagator.
 
 Parity status of each function is recorded in the module docstrings and in
 the tests that pin it (``tests/test_oracle_*.py``).

@@ -27,7 +27,7 @@ LIB_PATH = os.path.join(_HERE, "libbsparareal.so")
 BS_OK, BS_NOT_CONVERGED = 0, 1
 BS_ERR_ARG, BS_ERR_HIP, BS_ERR_NONFINITE, BS_ERR_DIVERGED, BS_ERR_WORKSPACE = -1, -2, -3, -4, -5
 BS_DIVERGENCE_GROWTH = 1.0e3
-COARSE_IE, COARSE_PINN, COARSE_PINN_IE = 0, 1, 2
+COARSE_IE, COARSE_PINN, COARSE_PINN_IE, COARSE_FLOWMAP = 0, 1, 2, 3
 PREC_FP32, PREC_BF16 = 0, 1
 
 EXPORTS = ("bs_last_error", "bs_initial", "bs_fine_propagate_batch", "bs_coarse_numeric",

@@ -149,11 +149,14 @@ static int check_parareal(const bs_params* prm, const bs_grid* grid, const bs_sl
     if ((rc = check_params(prm))) return rc;
     if ((rc = check_grid(grid))) return rc;
     if ((rc = check_slices(sl))) return rc;
-    BSP_CHECK_ARG(kind == BS_COARSE_IE || kind == BS_COARSE_PINN || kind == BS_COARSE_PINN_IE,
+    BSP_CHECK_ARG(kind == BS_COARSE_IE || kind == BS_COARSE_PINN || kind == BS_COARSE_PINN_IE ||
+                      kind == BS_COARSE_FLOWMAP,
                   "unknown coarse kind %d", kind);
     if (kind != BS_COARSE_IE) {
         if ((rc = check_net(net))) return rc;
         BSP_CHECK_ARG(net->n_in == 2 || net->n_in == 4, "network inputs must be 2 or 4");
+        BSP_CHECK_ARG(kind != BS_COARSE_FLOWMAP || net->n_in == 4,
+                      "the flow-map coarse takes a network of 4 inputs");
     }
     BSP_CHECK_ARG(U != nullptr, "U is NULL");
     if (ws == nullptr || ws_size < ws_bytes(grid->M, sl->N, kind)) {
@@ -227,6 +230,19 @@ static int start_impl(const bs_params* prm, const bs_grid* grid, const bs_slices
     const double dT = prm->T / N;
     Workspace w = ws_layout(ws, M, N, kind);
     if ((rc = launch_initial(o, M, grid->payoff_mode, U, st))) return rc;
+    if (kind == BS_COARSE_FLOWMAP) {
+        // the network sees the state: the prediction runs slice after slice
+        // (g in the first M doubles of the network-grid area)
+        for (int n = 0; n < N && predict; ++n) {
+            if ((rc = launch_flowmap(*net, o, M, n * dT, (n + 1) * dT, U + (long)n * M, w.Vt,
+                                     st)))
+                return rc;
+            if ((rc = launch_flow_correct(M, true, false, w.Vt, nullptr, w.Gold + (long)n * M,
+                                          U + (long)(n + 1) * M, w.result, st)))
+                return rc;
+        }
+        return BS_OK;
+    }
     if (kind != BS_COARSE_IE) {
         if ((rc = launch_pinn_grid(*net, o, M, N, dT, w.Vt, st))) return rc;
     }
@@ -327,7 +343,7 @@ int parareal_workspace_size(const bs_grid* grid, const bs_slices* sl, int coarse
     if ((rc = check_grid(grid))) return rc;
     if ((rc = check_slices(sl))) return rc;
     BSP_CHECK_ARG(coarse_kind == BS_COARSE_IE || coarse_kind == BS_COARSE_PINN ||
-                      coarse_kind == BS_COARSE_PINN_IE,
+                      coarse_kind == BS_COARSE_PINN_IE || coarse_kind == BS_COARSE_FLOWMAP,
                   "unknown coarse kind %d", coarse_kind);
     *bytes = ws_bytes(grid->M, sl->N, coarse_kind);
     return BS_OK;
@@ -349,7 +365,8 @@ int parareal_start(const bs_params* prm, const bs_grid* grid, const bs_slices* s
 // the overlapped solve (null: fst == st and the launches follow each other).
 // slot: profiling slot.  growth: divergence guard (INFINITY: none).
 static int enqueue_iteration(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,
-                             int kind, void* ws, double* U, int k, int* stop, double* hist,
+                             int kind, const pinn_net* net, void* ws, double* U, int k,
+                             int* stop, double* hist,
                              double tol, double growth, int slot, const PipeSync* ps,
                              hipStream_t fst, hipStream_t st) {
     const int M = grid->M, N = sl->N;
@@ -370,6 +387,20 @@ static int enqueue_iteration(const bs_params* prm, const bs_grid* grid, const bs
     if (rc) return rc;
     if (prof) BSP_HIP(hipEventRecord(g_prof.ev[4 * slot + 1], fst));
     if (prof) BSP_HIP(hipEventRecord(g_prof.ev[4 * slot + 2], st));
+    if (kind == BS_COARSE_FLOWMAP) {
+        // sweep: the network on U[n], then the correction, slice after slice
+        for (int n = first; n < N; ++n) {
+            if ((rc = launch_flowmap(*net, o, M, n * dT, (n + 1) * dT, U + (long)n * M, w.Vt,
+                                     st)))
+                return rc;
+            if ((rc = launch_flow_correct(M, false, n == first, w.Vt, w.Fv + (long)n * M,
+                                          w.Gold + (long)n * M, U + (long)(n + 1) * M, w.result,
+                                          st)))
+                return rc;
+        }
+        if (prof) BSP_HIP(hipEventRecord(g_prof.ev[4 * slot + 3], st));
+        return BS_OK;
+    }
     SweepArgs a{o,      M,      N,      first,    sl->coarse_steps, kind, 0, dT, U, w.Fv,
                 w.Gold, w.Vt,   w.result, stop,   hist,             tol,  k,  pk};
     a.growth = growth;
@@ -386,10 +417,10 @@ static double iteration_cells(const bs_grid* grid, const bs_slices* sl, int k) {
 }
 
 static int iterate_impl(const bs_params* prm, const bs_grid* grid, const bs_slices* sl, int kind,
-                        void* ws, double* U, int k, double* defect, int* nonfinite,
-                        hipStream_t st) {
+                        const pinn_net* net, void* ws, double* U, int k, double* defect,
+                        int* nonfinite, hipStream_t st) {
     Workspace w = ws_layout(ws, grid->M, sl->N, kind);
-    int rc = enqueue_iteration(prm, grid, sl, kind, ws, U, k, nullptr, nullptr, 0.0, INFINITY, 0,
+    int rc = enqueue_iteration(prm, grid, sl, kind, net, ws, U, k, nullptr, nullptr, 0.0, INFINITY, 0,
                                nullptr, st, st);
     if (rc) return rc;
     double res[2];
@@ -672,7 +703,8 @@ int parareal_iterate(const bs_params* prm, const bs_grid* grid, const bs_slices*
     if (rc) return rc;
     BSP_CHECK_ARG(k >= 1, "iteration index k must be >= 1");
     BSP_CHECK_ARG(defect && nonfinite, "defect and nonfinite must be non-NULL host pointers");
-    return iterate_impl(prm, grid, sl, kind, ws, U, k, defect, nonfinite, (hipStream_t)stream);
+    return iterate_impl(prm, grid, sl, kind, net, ws, U, k, defect, nonfinite,
+                        (hipStream_t)stream);
 }
 
 int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* sl, int kind,
@@ -696,6 +728,28 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
     Workspace w = ws_layout(ws, grid->M, N, kind);
     int* stop = reinterpret_cast<int*>(w.result + 4);
     if ((rc = launch_set_int(stop, 0, st))) return rc;
+    if (kind == BS_COARSE_FLOWMAP) {
+        // the coarse network sees the state: iterations one after the other,
+        // the stopping rule and the divergence guard decided on the host
+        if ((rc = start_impl(prm, grid, sl, kind, net, ws, U, nullptr, st))) return rc;
+        double first = 0.0;
+        for (int k = 1; k <= kmax; ++k) {
+            double d = 0.0;
+            int bad = 0;
+            rc = iterate_impl(prm, grid, sl, kind, net, ws, U, k, &d, &bad, st);
+            *iters = k;
+            if (defect_hist) defect_hist[k - 1] = d;
+            if (rc) return rc;
+            if (k == 1) first = d;
+            if (d <= tol || k == N) return BS_OK;
+            if (k >= 2 && d > growth * first) {
+                set_error("Parareal diverging: defect of iteration %d above %g x the first", k,
+                          growth);
+                return BS_ERR_DIVERGED;
+            }
+        }
+        return BS_NOT_CONVERGED;
+    }
     if (persist_capable(grid->M, N))
         return solve_persistent(prm, grid, sl, kind, tol, growth, net, kmax, ws, U, iters,
                                 defect_hist, S.hist_dev, S.hist, true, g_prof.on, st);
@@ -745,7 +799,7 @@ int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* s
     };
     bool decided = false;
     for (int k = 1; k <= kmax && !decided; ++k) {
-        if ((rc = enqueue_iteration(prm, grid, sl, kind, ws, U, k, stop, S.hist_dev, tol, growth,
+        if ((rc = enqueue_iteration(prm, grid, sl, kind, net, ws, U, k, stop, S.hist_dev, tol, growth,
                                     k - 1, pipe ? &ps : nullptr, pipe ? S.side[k & 1] : st, st)))
             return rc;
         BSP_HIP(hipEventRecord(S.done[k], st));
@@ -901,7 +955,7 @@ extern "C" int parareal_solve_noalloc(const bs_params* prm, const bs_grid* grid,
     if ((rc = start_impl(prm, grid, sl, kind, net, ws, U, nullptr, st))) return rc;
     int status = BS_NOT_CONVERGED, last = 0;
     for (int k = 1; k <= kmax; ++k) {
-        if ((rc = enqueue_iteration(prm, grid, sl, kind, ws, U, k, stop, rec_dev, tol, growth, -1,
+        if ((rc = enqueue_iteration(prm, grid, sl, kind, net, ws, U, k, stop, rec_dev, tol, growth, -1,
                                     nullptr, st, st)))
             return rc;
         BSP_HIP(hipMemcpyAsync(rec + 2 * k, rec_dev + 2 * k, 2 * sizeof(double),

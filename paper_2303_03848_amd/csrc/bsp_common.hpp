@@ -316,6 +316,15 @@ bool pipe_capable(int M);  // the overlapped solve covers grids of this size
 int launch_initial(const OptionDev& o, int M, int payoff_mode, double* u0, hipStream_t stream);
 
 // Network evaluated on the Parareal grid: Vt[n][j] = K v(n dT, (j+1) dS / K).
+// Flow-map coarse of one slice: g[j] = K w(tau_s, tau_e, Us[j] / K, S_j / K).
+int launch_flowmap(const pinn_net& net, const OptionDev& o, int M, double tau_s, double tau_e,
+                   const double* Us, double* g, hipStream_t stream);
+// The correction of one slice with the flow-map coarse (g = G(U[n]) given):
+// predict: U[n+1] = Gold[n] = g; else U[n+1] = Fv[n] + (g - Gold[n]),
+// Gold[n] = g, result[0] = max over the slices since `first` of
+// max |U_new - U_old|, result[1] = 1 if a value is not finite.
+int launch_flow_correct(int M, bool predict, bool first, const double* g, const double* fv,
+                        double* gold, double* un1, double* result, hipStream_t stream);
 int launch_pinn_grid(const pinn_net& net, const OptionDev& o, int M, int N, double dT, double* Vt,
                      hipStream_t stream);
 

@@ -104,6 +104,16 @@ int launch_pinn_grid(const pinn_net& net, const OptionDev& o, int M, int N, doub
     return launch_mlp(net, (long)(N + 1) * M, in, nullptr, Vt, o.K, stream);
 }
 
+int launch_flowmap(const pinn_net& net, const OptionDev& o, int M, double tau_s, double tau_e,
+                   const double* Us, double* g, hipStream_t stream) {
+    NetInput in{nullptr, net.n_in, M, 0.0, o.dS / o.K, 0.0, 0.0, nullptr, nullptr};
+    in.Us = Us;
+    in.tau_s = tau_s;
+    in.tau_e = tau_e;
+    in.inv_K = 1.0 / o.K;
+    return launch_mlp(net, M, in, nullptr, g, o.K, stream);
+}
+
 int launch_pinn_batch_grid(const pinn_net& net, const BatchOpt* opts, const BatchTile* tiles,
                            long npts, double* Vt, hipStream_t stream) {
     NetInput in{nullptr, net.n_in, 1, 0.0, 0.0, 0.0, 0.0, opts, tiles};

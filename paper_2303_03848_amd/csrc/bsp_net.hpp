@@ -41,6 +41,8 @@ __device__ __forceinline__ bf16x8 lds_frag(const __bf16* p) {
 // Parareal grid (tau_n = n dT, x_j = (j+1) dS / K, i = n*M + j).
 // Batch mode (tiles != nullptr): point i lies in tile i / 32, which names its
 // option; the option's grid is packed from tiles[i/32].base on.
+// Flow-map mode (Us != nullptr): point i is node i of the state Us of one
+// slice, inputs (tau_s, tau_e, Us[i] / K, (i+1) dS / K).
 struct NetInput {
     const float* X;
     int n_in;
@@ -48,10 +50,19 @@ struct NetInput {
     double dT, dS_over_K, sigma, r;
     const BatchOpt* bopts;
     const BatchTile* tiles;
+    const double* Us = nullptr;
+    double tau_s = 0.0, tau_e = 0.0, inv_K = 0.0;
 };
 
 // Inputs of point i; false for the padding points of batch mode.
 __device__ __forceinline__ bool net_input(const NetInput& in, long i, float (&x)[4]) {
+    if (in.Us) {
+        x[0] = (float)in.tau_s;
+        x[1] = (float)in.tau_e;
+        x[2] = (float)(in.Us[i] * in.inv_K);
+        x[3] = (float)((double)(i + 1) * in.dS_over_K);
+        return true;
+    }
     if (in.X) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) x[c] = (c < in.n_in) ? in.X[i * in.n_in + c] : 0.0f;

@@ -827,6 +827,56 @@ int launch_theta_batch(const OptionDev& o, int M, int nsys, const double* tau0, 
     return BS_ERR_ARG;
 }
 
+// One slice of the sweep with the flow-map coarse (one block): see
+// launch_flow_correct.  Same arithmetic per node as sweep_slices.
+__global__ __launch_bounds__(1024) void k_flow_correct(int M, int predict, int first,
+                                                       const double* __restrict__ g,
+                                                       const double* __restrict__ fv,
+                                                       double* __restrict__ gold, double* un1,
+                                                       double* __restrict__ result) {
+    __shared__ double red[1024];
+    __shared__ int rbad[1024];
+    double dmax = 0.0;
+    int bad = 0;
+    for (int j = threadIdx.x; j < M; j += blockDim.x) {
+        const double gg = g[j];
+        if (predict) {
+            un1[j] = gg;
+            gold[j] = gg;
+        } else {
+            const double uo = un1[j];
+            const double unew = fv[j] + (gg - gold[j]);
+            gold[j] = gg;
+            un1[j] = unew;
+            dmax = fmax(dmax, fabs(unew - uo));
+            bad |= !isfinite(unew);
+        }
+    }
+    if (predict) return;
+    red[threadIdx.x] = dmax;
+    rbad[threadIdx.x] = bad;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+            rbad[threadIdx.x] |= rbad[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        result[0] = first ? red[0] : fmax(result[0], red[0]);
+        result[1] = (rbad[0] || (!first && result[1] != 0.0)) ? 1.0 : 0.0;
+    }
+}
+
+int launch_flow_correct(int M, bool predict, bool first, const double* g, const double* fv,
+                        double* gold, double* un1, double* result, hipStream_t stream) {
+    hipLaunchKernelGGL(k_flow_correct, dim3(1), dim3(1024), 0, stream, M, predict ? 1 : 0,
+                       first ? 1 : 0, g, fv, gold, un1, result);
+    BSP_LAUNCHED();
+    return BS_OK;
+}
+
 int launch_sweep(const SweepArgs& a, hipStream_t stream) {
     const TriShape sh = shape_for(1, a.M);
     if (is_large(sh)) {

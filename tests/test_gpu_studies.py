@@ -9,6 +9,11 @@
   alone (n_f = n_b = 0, targets at arbitrary tau) and its gradient match the
   oracle's hand-written reverse mode (1e-4 relative, as for the residual
   loss); a short data-only training lowers the data misfit.
+* Flow-map coarse (Sec. 3.3's interface read node by node): the coarse
+  prediction against the oracle's FP64 flow-map Parareal (oracle/flowmap.py)
+  within float32 rounding compounded over the slices (1e-4 normwise),
+  iteration N equal to the serial fine solution (1e-12), the solve equal to
+  the iteration path bitwise; a 2-input network is refused.
 Weights and data are seeded draws; no GPU result feeds the oracle.
 """
 import numpy as np
@@ -93,3 +98,44 @@ def test_train_on_data_lowers_misfit():
     say(f"data-only training: mse {mse0:.3e} -> {mse:.3e} ({info['steps']} steps)")
     assert info["steps"] == 50 * 4
     assert mse < 0.1 * mse0
+
+
+@pytest.mark.parametrize("is_put", [False, True])
+def test_flowmap_coarse_against_oracle(is_put):
+    """The flow-map coarse (a 4-input network applied to the state node by
+    node): the coarse prediction against the oracle's FP64 network within
+    float32 rounding compounded over the slices, every later iterate ending
+    in the serial fine solution (finite termination), and the solve's
+    iterate equal to the iteration path's."""
+    from oracle import flowmap
+    cuda()
+    cfg = dict(SMALL_CALL, is_put=is_put)
+    p = option_params(cfg)
+    M, N, Sf = cfg["M"], cfg["N"], cfg["fine_steps"]
+    say(f"flow-map coarse put={is_put}")
+    th = perturbed(xavier_normal(4, 3, 32, seed=9), 0.05, 10)
+    net = bsp.PinnNet(to_dev(th, torch.float32), 4, 3, 32, bsp.PREC_FP32)
+    po = oracle.params_from(p)
+    ref = flowmap.parareal(po, M, N, Sf, th.astype(np.float32).astype(np.float64), 3, 32, tol=0.0)
+    pr = bsp.Parareal(p, M, N, Sf, 1, bsp.COARSE_FLOWMAP, net)
+    U0 = pr.start().cpu().numpy()
+    assert normwise(U0, ref["iterates"][0]) <= 1e-4
+    d = [pr.iterate(k) for k in range(1, N + 1)]
+    U = pr.U.cpu().numpy()
+    assert normwise(U, oracle.serial_fine(po, M, N, Sf)) <= 1e-12
+    assert np.all(np.isfinite(d)) and d[-1] < d[0]
+    pr2 = bsp.Parareal(p, M, N, Sf, 1, bsp.COARSE_FLOWMAP, net)
+    it, d2, rc = pr2.solve(0.0)
+    assert it == N and rc == bsp.BS_OK
+    assert np.array_equal(pr2.U.cpu().numpy(), U)
+    assert d2 == d
+
+
+def test_flowmap_needs_four_inputs():
+    cuda()
+    p = option_params(SMALL_CALL)
+    th = xavier_normal(2, 2, 16, seed=1)
+    net = bsp.PinnNet(to_dev(th, torch.float32), 2, 2, 16, bsp.PREC_FP32)
+    pr = bsp.Parareal(p, 64, 4, 8, 1, bsp.COARSE_FLOWMAP, net)
+    with pytest.raises(bsp.BsError):
+        pr.start()

@@ -181,14 +181,17 @@ struct Forcing {
         bhiD = (owner && r_hi == MC - 1) ? gammaM : 0.0;
         bhi = gammaM / kappa;
     }
-    // Right-hand side of the interior rows: V (+ forcing / kappa).
-    template <int MC>
+    // Right-hand side of the interior rows: V (+ forcing / kappa).  HI false:
+    // the grid is a multiple of the chunk, so row M-1 is an interface row
+    // and no interior row takes forcing (hi_in is false; saying so at compile
+    // time drops the per-step select over the rows).
+    template <int MC, bool HI = true>
     __device__ __forceinline__ void rhs(const double (&V)[MC], double flo, double fhi,
                                         double (&d)[MC]) const {
 #pragma unroll
         for (int q = 0; q < MC; ++q) d[q] = V[q];
         d[0] = fma(blo, flo, d[0]);
-        if (hi_in) {
+        if (HI && hi_in) {
 #pragma unroll
             for (int q = 0; q < MC - 1; ++q)
                 if (q == r_hi) d[q] = fma(bhi, fhi, d[q]);

@@ -354,7 +354,7 @@ struct BlockTriR : RcFact<T, MC, HI> {
         RcRows rw = rows;
         asm volatile("" : "+v"(rw.c2), "+v"(rw.c1), "+v"(rw.J));
         double d[MC];
-        fc.rhs(V, flo, fhi, d);
+        fc.template rhs<MC, HI>(V, flo, fhi, d);
         const double kum = forward(rw, col(), [&](int q, double l) {
             d[q] = fma(-l, d[q - 1], d[q]);
         });

@@ -64,13 +64,16 @@ def tune_fine(p: dict, M: int, nsys: int, steps: int, dtau: float, reps: int = 3
 
 
 def tune_sweep(p: dict, M: int, N: int, fine_steps: int, kind: int = bsp.COARSE_IE, net=None,
-               reps: int = 3):
+               reps: int = 3, fine_shape=None):
     """Time one Parareal iteration's sweep for every candidate sweep shape
-    (the fine kernel keeps its current shape).  Returns (best, {shape: ms})."""
+    (the fine kernel takes fine_shape, or its default).  Returns (best,
+    {shape: ms})."""
     times = {}
     pr = bsp.Parareal(p, M, N, fine_steps, 1, kind, net)
     for T, MC in candidates(M):
         bsp.bs_tune_reset()
+        if fine_shape is not None:
+            bsp.bs_tune_set_shape(FINE, M, M, *fine_shape)
         bsp.bs_tune_set_shape(SWEEP, M, M, T, MC)
         pr.start()
         bsp.bs_profile_enable(True)
@@ -106,8 +109,7 @@ def tune_workload(name: str, p: dict, M: int, N: int, fine_steps: int, use_cache
     else:
         dT = p["T"] / N
         bf, tf = tune_fine(p, M, N, fine_steps, dT)
-        bsp.bs_tune_set_shape(FINE, M, M, *bf)
-        bs, ts = tune_sweep(p, M, N, fine_steps)
+        bs, ts = tune_sweep(p, M, N, fine_steps, fine_shape=bf)
         ent = {"fine": list(bf), "sweep": list(bs),
                "fine_ms": {f"{a}x{b}": v for (a, b), v in tf.items()},
                "sweep_ms": {f"{a}x{b}": v for (a, b), v in ts.items()}}
@@ -145,7 +147,7 @@ def tune_batch(name: str, options, use_cache: bool = True, path: str = CACHE,
             dT = rep["T"] / rep["N"]
             bsp.bs_tune_reset()
             bf, tf = tune_fine(p, M, nsys, rep["fine_steps"], dT)
-            bs, ts = tune_sweep(p, M, rep["N"], rep["fine_steps"])
+            bs, ts = tune_sweep(p, M, rep["N"], rep["fine_steps"], fine_shape=bf)
             ent[str(M)] = {"fine": list(bf), "sweep": list(bs), "systems": nsys,
                            "fine_ms": {f"{a}x{b}": v for (a, b), v in tf.items()},
                            "sweep_ms": {f"{a}x{b}": v for (a, b), v in ts.items()}}

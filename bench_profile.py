@@ -21,6 +21,9 @@ profiled GPU run; reads rocprofv3's files, runs nothing on the GPU).
   mfma CSV --kernel NAME ...
       BF16 MFMA flops and MFMA-busy fraction from a counter run of
       SQ_INSTS_VALU_MFMA_MOPS_BF16, SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE.
+  valu CSV --kernel NAME ...
+      VALU and LDS busy fractions and the FP64 share of the VALU
+      instructions from one counter run (see valu_table).
 """
 from __future__ import annotations
 
@@ -168,6 +171,34 @@ def mfma_table(path: str, kernels, simds: int = 1024, xcds: int = 8) -> str:
     return "\n".join(out) + "\n"
 
 
+def valu_table(path: str, kernels, cus: int = 256, xcds: int = 8) -> str:
+    """Per kernel, from SQ_ACTIVE_INST_VALU, SQ_INSTS_VALU, SQ_INSTS_VALU_{FMA,
+    MUL,ADD}_F64, SQ_INSTS_LDS, SQ_LDS_IDX_ACTIVE, SQ_WAVE_CYCLES and
+    GRBM_GUI_ACTIVE: VALU busy (rocprof's VALUBusy: active VALU cycles per CU
+    over the GPU-active cycles; GRBM_GUI_ACTIVE comes summed over the XCDs),
+    LDS busy (LdsUtil, likewise), FP64 share of the VALU instructions, and
+    VALU instructions per wave-cycle."""
+    rows = _dispatches(path)
+    tot = defaultdict(lambda: defaultdict(float))
+    for k, c, dur in rows:
+        for want in kernels:
+            if want in k:
+                t = tot[want]
+                t["n"] += 1
+                for name, v in c.items():
+                    t[name] += v
+    out = ["| kernel | launches | VALU busy | LDS busy | FP64 share of VALU instructions | "
+           "VALU instructions per wave quad-cycle |", "|---|---|---|---|---|---|"]
+    for k, t in tot.items():
+        act = t["GRBM_GUI_ACTIVE"] / xcds
+        f64 = t["SQ_INSTS_VALU_FMA_F64"] + t["SQ_INSTS_VALU_MUL_F64"] + t["SQ_INSTS_VALU_ADD_F64"]
+        out.append(f"| `{k}` | {int(t['n'])} | {t['SQ_ACTIVE_INST_VALU'] / cus / act:.3f} | "
+                   f"{t['SQ_LDS_IDX_ACTIVE'] / cus / act:.3f} | "
+                   f"{f64 / max(t['SQ_INSTS_VALU'], 1):.3f} | "
+                   f"{t['SQ_INSTS_VALU'] / max(t['SQ_WAVE_CYCLES'], 1):.3f} |")
+    return "\n".join(out) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -190,7 +221,13 @@ def main():
     m = sub.add_parser("mfma")
     m.add_argument("csv")
     m.add_argument("--kernel", action="append", required=True)
+    v = sub.add_parser("valu")
+    v.add_argument("csv")
+    v.add_argument("--kernel", action="append", required=True)
     a = ap.parse_args()
+    if a.cmd == "valu":
+        sys.stdout.write(valu_table(a.csv, a.kernel))
+        return
     if a.cmd == "trace":
         sys.stdout.write(trace_summary(a.db, a.kernel, a.command))
     elif a.cmd == "hbm":

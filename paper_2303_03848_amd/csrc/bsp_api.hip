@@ -910,6 +910,8 @@ extern "C" int parareal_solve_noalloc(const bs_params* prm, const bs_grid* grid,
     if ((rc = check_params(prm))) return rc;
     if ((rc = check_grid(grid))) return rc;
     if ((rc = check_slices(sl))) return rc;
+    BSP_CHECK_ARG(kind != BS_COARSE_FLOWMAP,
+                  "parareal_solve_noalloc does not take the flow-map coarse");
     BSP_CHECK_ARG(kind == BS_COARSE_IE || kind == BS_COARSE_PINN || kind == BS_COARSE_PINN_IE,
                   "unknown coarse kind %d", kind);
     if (kind != BS_COARSE_IE) {

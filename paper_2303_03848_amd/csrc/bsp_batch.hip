@@ -367,6 +367,7 @@ static int batch_checks(int n_opt, const bs_params* prm, const bs_grid* grids,
                         const bs_slices* sl, int kind, const pinn_net* net) {
     BSP_CHECK_ARG(n_opt >= 1, "n_opt must be >= 1");
     BSP_CHECK_ARG(prm && grids && sl, "host option arrays must be non-NULL");
+    BSP_CHECK_ARG(kind != BS_COARSE_FLOWMAP, "the batched solve does not take the flow-map coarse");
     BSP_CHECK_ARG(kind == BS_COARSE_IE || kind == BS_COARSE_PINN || kind == BS_COARSE_PINN_IE,
                   "unknown coarse kind %d", kind);
     if (kind != BS_COARSE_IE) {

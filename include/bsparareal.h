@@ -299,7 +299,8 @@ int parareal_solve_batch(int n_opt, const bs_params* prm, const bs_grid* grids,
  * bs_tune_reset().  Only built shapes are accepted (BS_ERR_ARG otherwise):
  * (64,2) (64,4) (64,8) (64,16) (128,4) (128,8) (256,4) (256,8) (512,8), and
  * threads * nodes_per_thread must cover M_hi.  Results do not depend on the
- * shape beyond rounding.  Process-wide; not thread-safe. */
+ * shape beyond rounding.  Process-wide (guarded by a lock: calls from several
+ * threads are safe; a launch uses the setting current when it starts). */
 int bs_tune_set_shape(int kernel, int M_lo, int M_hi, int threads, int nodes_per_thread);
 int bs_tune_reset(void);
 

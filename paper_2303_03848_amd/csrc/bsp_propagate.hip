@@ -1,5 +1,8 @@
 // Propagator kernels: expiry payoff, the batched theta-method (Crank-Nicolson
 // fine F, implicit-Euler coarse G) and the serial Parareal correction sweep.
+#include <mutex>
+#include <shared_mutex>
+
 #include "bsp_common.hpp"
 #include "bsp_steps.hpp"
 #include "bsp_tridiag_large.hpp"
@@ -741,7 +744,10 @@ static bool shape_built(int T, int MC) {
     return false;
 }
 
-// Overrides installed by the autotuner: per kernel, M ranges -> shape.
+// Overrides installed by the autotuner: per kernel, M ranges -> shape.  The
+// table is process-wide; a reader-writer lock makes concurrent lookups and
+// updates from several host threads safe (a launch takes the shape current
+// when it looks it up).
 struct ShapeOverride {
     int M_lo, M_hi;
     TriShape sh;
@@ -749,8 +755,10 @@ struct ShapeOverride {
 constexpr int kMaxOverrides = 16;
 static ShapeOverride g_over[2][kMaxOverrides];
 static int g_nover[2] = {0, 0};
+static std::shared_mutex g_over_mutex;
 
 TriShape shape_for(int kernel, int M) {
+    std::shared_lock<std::shared_mutex> lock(g_over_mutex);
     for (int i = g_nover[kernel] - 1; i >= 0; --i) {
         const ShapeOverride& o = g_over[kernel][i];
         if (M >= o.M_lo && M <= o.M_hi) return o.sh;
@@ -769,12 +777,16 @@ int set_shape_override(int kernel, int M_lo, int M_hi, int T, int MC) {
     BSP_CHECK_ARG(shape_built(T, MC), "block shape (%d threads, %d nodes/thread) is not built", T,
                   MC);
     BSP_CHECK_ARG((long)T * MC >= M_hi, "shape covers %d nodes, range needs %d", T * MC, M_hi);
+    std::unique_lock<std::shared_mutex> lock(g_over_mutex);
     BSP_CHECK_ARG(g_nover[kernel] < kMaxOverrides, "too many shape overrides");
     g_over[kernel][g_nover[kernel]++] = {M_lo, M_hi, {T, MC}};
     return BS_OK;
 }
 
-void reset_shape_overrides() { g_nover[0] = g_nover[1] = 0; }
+void reset_shape_overrides() {
+    std::unique_lock<std::shared_mutex> lock(g_over_mutex);
+    g_nover[0] = g_nover[1] = 0;
+}
 
 bool pipe_capable(int M) { return !is_large(shape_for(0, M)) && !is_large(shape_for(1, M)); }
 

@@ -224,9 +224,11 @@ int parareal_iterate(const bs_params* prm, const bs_grid* grid, const bs_slices*
  * returning.  The launches synchronise through progress counters in ws;
  * every wait also ends on the stop flag, and after about 2 s the solve
  * fails with BS_ERR_HIP.  Beyond 4096 nodes (block shapes of 512 threads)
- * with 2 <= N <= 256: iteration 1's fine launch, then one launch in which
- * one block runs the sweeps of all iterations and one block per slice n >= 1
- * the fine work of iterations 2, 3, ... (when the device holds all N blocks
+ * with 2 <= N <= 256: slice 0's first fine propagation, then one launch in
+ * which one block runs the prediction and the sweeps of all iterations and
+ * one block per slice n >= 1 the fine work of iterations 1, 2, ... (network
+ * grid and slice 0's propagation run side by side before it; when the
+ * device holds all N blocks
  * at once; another kernel occupying compute units meanwhile makes the waits
  * time out: BS_ERR_HIP); otherwise the iterations run one after the other. */
 int parareal_solve(const bs_params* prm, const bs_grid* grid, const bs_slices* sl,

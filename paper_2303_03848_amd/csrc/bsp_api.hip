@@ -589,10 +589,11 @@ static int solve_persistent(const bs_params* prm, const bs_grid* grid, const bs_
 }
 
 // Overlapped solve of a grid beyond 4096 nodes (k_large_persist): initial
-// state, network grid and prediction, iteration 1's fine launch over every
-// slice, then one launch for the sweeps of all iterations beside the fine
-// work of iterations 2, 3, ...; the host reads the per-iteration record once
-// the stream has drained.  The stop flag must already be clear on st.
+// state and network grid, slice 0's first fine propagation (on a side
+// stream, beside the network grid), then one launch for the prediction and
+// the sweeps of all iterations beside the fine work of iterations 1, 2, ...;
+// the host reads the per-iteration record once the stream has drained.  The
+// stop flag must already be clear on st.
 static int solve_large(const bs_params* prm, const bs_grid* grid, const bs_slices* sl, int kind,
                        double tol, double growth, const pinn_net* net, int kmax, void* ws,
                        double* U, int* iters, double* defect_hist, hipStream_t st) {
@@ -604,21 +605,27 @@ static int solve_large(const bs_params* prm, const bs_grid* grid, const bs_slice
     const PipeSync ps = pipe_sync(w, N);
     int* stop = reinterpret_cast<int*>(w.result + 4);
     if ((rc = launch_fill_int(w.flags, flag_count(N), 0, st))) return rc;
-    if ((rc = start_impl(prm, grid, sl, kind, net, ws, U, nullptr, st))) return rc;
+    if ((rc = solve_streams())) return rc;
     const OptionDev o = make_option(*prm, M);
     const double dT = prm->T / N;
     const bool prof = g_prof.on;
-    // iteration 1: F on every slice, one launch
-    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[0], st));
-    if ((rc = launch_theta_batch(o, M, N, nullptr, 0.0, dT, 0, dT / sl->fine_steps,
-                                 sl->fine_steps, 0.5, U, M, w.Fv, M, st, stop, nullptr)))
+    // U[0] = payoff; then slice 0's first fine propagation (iteration 1's
+    // F of slice 0, the only one no fine block of the launch computes) on a
+    // side stream beside the network grid
+    if ((rc = launch_initial(o, M, grid->payoff_mode, U, st))) return rc;
+    BSP_HIP(hipEventRecord(S.go, st));
+    BSP_HIP(hipStreamWaitEvent(S.side[0], S.go, 0));
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[0], S.side[0]));
+    if ((rc = launch_theta_batch(o, M, 1, nullptr, 0.0, dT, 0, dT / sl->fine_steps,
+                                 sl->fine_steps, 0.5, U, M, w.Fv, M, S.side[0], stop, nullptr)))
         return rc;
-    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[1], st));
-    // every U[n] holds iterate 0 and every Fv[n] iteration 1's result, read
-    // from U[n]: the counters as the overlapped launches would have left them
-    if ((rc = launch_fill_int(ps.ready, N + 1, 1, st))) return rc;
-    if ((rc = launch_fill_int(ps.taken, N + 1, 1, st))) return rc;
-    if ((rc = launch_fill_int(ps.fdone, N, 1, st))) return rc;
+    if (prof) BSP_HIP(hipEventRecord(g_prof.ev[1], S.side[0]));
+    if (kind != BS_COARSE_IE && (rc = launch_pinn_grid(*net, o, M, N, dT, w.Vt, st))) return rc;
+    BSP_HIP(hipEventRecord(S.side_done[0], S.side[0]));
+    BSP_HIP(hipStreamWaitEvent(st, S.side_done[0], 0));
+    // counters: nothing produced yet except Fv[0] (the prediction publishes
+    // U[0] and every U[n+1] as it goes)
+    if ((rc = launch_fill_int(ps.fdone, 1, 1, st))) return rc;
     LargePersistArgs a{};
     if ((rc = launch_large_sweep_setup(o, M, dT, sl->coarse_steps, w.tab, st))) return rc;
     a.tab = w.tab;
@@ -633,10 +640,10 @@ static int solve_large(const bs_params* prm, const bs_grid* grid, const bs_slice
     a.dT = dT;
     a.tol = tol;
     a.growth = growth;
-    // the launch works on chunk-major copies of U, Fv, Gold and Vt
-    if ((rc = launch_cm_convert(U, w.cm_U, N + 1, M, true, st))) return rc;
-    if ((rc = launch_cm_convert(w.Fv, w.cm_Fv, N, M, true, st))) return rc;
-    if ((rc = launch_cm_convert(w.Gold, w.cm_Gold, N, M, true, st))) return rc;
+    // the launch works on chunk-major copies of U, Fv, Gold and Vt (of which
+    // U[0], Fv[0] and Vt hold values so far)
+    if ((rc = launch_cm_convert(U, w.cm_U, 1, M, true, st))) return rc;
+    if ((rc = launch_cm_convert(w.Fv, w.cm_Fv, 1, M, true, st))) return rc;
     if (w.Vt && (rc = launch_cm_convert(w.Vt, w.cm_Vt, N + 1, M, true, st))) return rc;
     a.U = w.cm_U;
     a.Fv = w.cm_Fv;
@@ -681,10 +688,11 @@ static int solve_large(const bs_params* prm, const bs_grid* grid, const bs_slice
         BSP_HIP(hipEventElapsedTime(&p_ms, g_prof.ev[2], g_prof.ev[3]));
         g_prof.fine_ms += f_ms;
         g_prof.fine_launches += 1;
-        g_prof.fine_cells += iteration_cells(grid, sl, 1);
+        g_prof.fine_cells += (double)sl->fine_steps * M;  // slice 0, iteration 1
         g_prof.solve_ms += p_ms;
         g_prof.solve_launches += 1;
-        for (int k = 2; k <= last; ++k) g_prof.solve_cells += iteration_cells(grid, sl, k);
+        for (int k = 1; k <= last; ++k) g_prof.solve_cells += iteration_cells(grid, sl, k);
+        if (last >= 1) g_prof.solve_cells -= (double)sl->fine_steps * M;
     }
     if (status == BS_ERR_NONFINITE)
         set_error("non-finite value in the Parareal state at iteration %d", last);

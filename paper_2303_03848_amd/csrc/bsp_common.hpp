@@ -275,9 +275,9 @@ struct PersistArgs {
     double growth;    // divergence guard, as in SweepArgs
 };
 // Overlapped solve of a grid beyond 4096 nodes (see k_large_persist): after
-// iteration 1's fine launch, one launch runs the sweeps of every iteration in
-// one block and the fine work of iterations 2, 3, ... in one block per slice
-// n >= 1.
+// slice 0's iteration-1 fine propagation, one launch runs the prediction and
+// the sweeps of every iteration in one block and the fine work of iterations
+// 1, 2, ... in one block per slice n >= 1.
 struct LargePersistArgs {
     OptionDev o;
     int M, N, kmax, fine_steps, coarse_steps, kind;

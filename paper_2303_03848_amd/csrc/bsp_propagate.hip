@@ -503,13 +503,16 @@ int launch_large_sweep_setup(const OptionDev& o, int M, double dT, int coarse_st
 
 // ------------------------------------------ overlapped large-grid solve
 
-// One launch for iterations 1.. of a solve on a grid beyond 4096 nodes, after
-// iteration 1's fine launch (k_rc_theta over all slices).  Block N-1 sweeps:
+// One launch for the prediction and iterations 1.. of a solve on a grid
+// beyond 4096 nodes, after the fine propagation of slice 0's initial value
+// (its iteration-1 result).  Block N-1 sweeps:
 // iterations k = 1, 2, ... one after the other, slice by slice, each slice as
-// soon as its fine result of iteration k is written.  Blocks 0 .. N-2 are the
-// fine blocks: block b owns slice n = b + 1 and propagates it for iterations
-// k = 2 .. min(kmax, n + 1) (slice n is exact from iteration n + 1 on), each
-// as soon as the sweep of iteration k-1 has produced its initial value.  So
+// soon as its fine result of iteration k is written; before them the coarse
+// prediction (k = 0).  Blocks 0 .. N-2 are the fine blocks: block b owns
+// slice n = b + 1 and propagates it for iterations k = 1 .. min(kmax, n + 1)
+// (slice n is exact from iteration n + 1 on), each as soon as the sweep of
+// iteration k-1 (the prediction for k = 1) has produced its initial value;
+// slice 0's fine result of iteration 1 is computed before the launch.  So
 // the sweep of iteration k runs beside the fine work of iteration k + 1 and
 // an iteration costs about one fine propagation instead of one plus a sweep.
 // Hand-offs go through the progress counters of PipeSync (ready: U[n] holds
@@ -547,7 +550,7 @@ __device__ __forceinline__ void large_fine_role(const LargePersistArgs& a, int n
     const double tau0 = (double)n * a.dT;
     const int klast = min(a.kmax, n + 1);
     const PipeSync& ps = a.ps;
-    for (int k = 2; k <= klast; ++k) {
+    for (int k = 1; k <= klast; ++k) {
         if (!pipe_wait(ps, ps.ready + n, k, a.stop, pslot)) return;
         double V[MC];
         load_cm<T, MC>(a.U + (long)n * (T * MC), V);
@@ -577,16 +580,19 @@ __device__ __forceinline__ void large_sweep_role(const LargePersistArgs& a, doub
     double* ftab = lds + 4 * T;
     BlockTriG<T, MC> S;
     S.load(a.tab, a.ptab, a.o.s2, a.o.r, a.dT / (double)a.coarse_steps, 0.0, a.M, kst);
-    for (int k = 1; k <= a.kmax; ++k) {
+    for (int k = 0; k <= a.kmax; ++k) {
+        // k = 0: the coarse prediction, which the fine blocks' first
+        // iteration follows slice by slice
         PipeSync ps = a.ps;
         ps.k = k;
-        const int n0 = min(k - 1, a.N - 1);
+        const int n0 = k == 0 ? 0 : min(k - 1, a.N - 1);
         double dmax = 0.0;
         int bad = 0;
         const bool ok = sweep_slices<T, MC, BlockTriG<T, MC>, true>(
-            S, a.o, a.M, a.N, n0, a.coarse_steps, a.kind, false, a.dT, a.U, a.U, a.Fv, a.Gold,
+            S, a.o, a.M, a.N, n0, a.coarse_steps, a.kind, k == 0, a.dT, a.U, a.U, a.Fv, a.Gold,
             a.Vt, lds, ftab, dmax, bad, ps, true, a.stop, pslot, 0, kLargeSweepBatch);
         if (!ok) return;
+        if (k == 0) continue;
         block_defect<T>(dmax, bad, lds);
         if (threadIdx.x == 0) {
             SweepArgs sa{};

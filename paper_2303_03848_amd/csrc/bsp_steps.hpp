@@ -481,9 +481,9 @@ __device__ __forceinline__ void combine_staged(const double* __restrict__ src, i
 // same results.  uo1 and un1 may be the same level (each entry is read
 // before it is written); rows are taken in groups of G, a group's loads
 // issued together (a second buffer to overlap the next group's loads made
-// the sweep block spill).  Not for the prediction (no predict form).
+// the sweep block spill).  predict: U[n+1] = Gold[n] = the coarse value.
 template <int T, int MC, int MODE>
-__device__ __forceinline__ void correct_cm(double (&g)[MC], int M,
+__device__ __forceinline__ void correct_cm(double (&g)[MC], int M, bool predict,
                                            const double* __restrict__ fv,
                                            double* __restrict__ go, const double* uo1,
                                            double* un1, const double* __restrict__ vt1,
@@ -491,6 +491,24 @@ __device__ __forceinline__ void correct_cm(double (&g)[MC], int M,
     constexpr int G = 8;
     static_assert(MC % G == 0, "whole groups");
     const int p = threadIdx.x, i0 = p * MC;
+    if (predict) {
+#pragma unroll
+        for (int q = 0; q < MC; ++q) {
+            const int c = q * T + p;
+            if (i0 + q < M) {
+                const double v = MODE != kCoarseSolve ? vt1[c] : 0.0;
+                const double gg = MODE == kCoarseSolve ? g[q]
+                                  : MODE == kCoarseNet ? v
+                                                       : v + g[q];
+                un1[c] = gg;
+                go[c] = gg;
+                g[q] = MODE == kCoarseNetDev ? gg - v : gg;
+            } else {
+                g[q] = 0.0;
+            }
+        }
+        return;
+    }
     double f[G], gl[G], uo[G], v[G];
     auto load = [&](int q0) {
 #pragma unroll
@@ -664,12 +682,14 @@ __device__ __forceinline__ bool sweep_slices(const Solver& S, const OptionDev& o
         if constexpr (CM) {
             const double* vn1 = net ? Vt + (n + 1) * ld : nullptr;
             if (kind == BS_COARSE_IE)
-                correct_cm<T, MC, kCoarseSolve>(g, M, Fv + n * ld, go, uo1, un1, vn1, dmax, bad);
+                correct_cm<T, MC, kCoarseSolve>(g, M, predict, Fv + n * ld, go, uo1, un1, vn1,
+                                                dmax, bad);
             else if (kind == BS_COARSE_PINN)
-                correct_cm<T, MC, kCoarseNet>(g, M, Fv + n * ld, go, uo1, un1, vn1, dmax, bad);
+                correct_cm<T, MC, kCoarseNet>(g, M, predict, Fv + n * ld, go, uo1, un1, vn1,
+                                              dmax, bad);
             else
-                correct_cm<T, MC, kCoarseNetDev>(g, M, Fv + n * ld, go, uo1, un1, vn1, dmax,
-                                                 bad);
+                correct_cm<T, MC, kCoarseNetDev>(g, M, predict, Fv + n * ld, go, uo1, un1, vn1,
+                                                 dmax, bad);
 #pragma unroll
             for (int q = 0; q < MC; ++q) V[q] = g[q];
         } else if constexpr (!kPrefetch) {

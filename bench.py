@@ -176,10 +176,12 @@ def bench_large_put(args, bsp, torch):
     cells = (prof["fine_cells"] + prof["solve_cells"]) / args.steps
     value = cells / (ms / 1e3)
     # The dominant kernel: the one-launch part of each timed solve
-    # (k_large_persist: the fine work of iterations 2.. beside every sweep),
+    # (k_large_persist: the coarse prediction and every sweep on one block,
+    # the fine work of slices 1..N-1 in every iteration on the others),
     # timed with events on the stream it runs on; its algorithmic work is
-    # the fine cell updates of those iterations.  Iteration 1's fine launch
-    # (k_rc_theta over all slices) is reported beside it.
+    # the fine cell updates of those slices.  Slice 0's first fine
+    # propagation (k_rc_theta, one system, on a side stream beside the
+    # network grid) is reported beside it.
     s_ms, s_launches, s_cells = prof["solve_ms"], prof["solve_launches"], prof["solve_cells"]
     achieved = FLOPS_PER_CELL * s_cells / (s_ms / 1e3) / 1e12
     f1 = {"kernel": "k_rc_theta", "avg_launch_ms": prof["fine_ms"] / max(prof["fine_launches"], 1),
@@ -209,8 +211,9 @@ def bench_large_put(args, bsp, torch):
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_VALU_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / FP64_VALU_PEAK_TFLOPS,
                      "traffic": None if traffic is None else traffic["hbm_bytes_per_launch"],
-                     "kernel": "k_large_persist (fine work of iterations 2.. on one block per "
-                               "slice, the sweeps of all iterations on one block beside it)",
+                     "kernel": "k_large_persist (the prediction and every sweep on one block, "
+                               "the fine work of slices 1..N-1 in every iteration on one "
+                               "block per slice beside it)",
                      "avg_launch_ms": s_ms / s_launches, "launches_timed": s_launches,
                      "fine_cells_per_launch": s_cells / s_launches,
                      "flops_per_cell": FLOPS_PER_CELL,
@@ -218,7 +221,7 @@ def bench_large_put(args, bsp, torch):
                          (s_cells / s_launches) / (Sf * M) * 16.0 * M,
                      "traffic_source": None if traffic is None else
                      "profiles/k_large_persist_traffic.json"},
-        "first_iteration_fine_launch": f1,
+        "slice0_first_fine_launch": f1,
         "per_slice_costs_ms": {"c_f_fine_launch": c_f, "c_c_sweep_per_slice": c_c},
         "training": info,
         "defects": defects,

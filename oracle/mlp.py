@@ -31,6 +31,15 @@ Readings of the paper used here:
 Pins (tests/test_oracle_mlp.py): torch float64 ``nn.Sequential`` forward and
 ``autograd.grad`` derivatives; the loss gradient against torch autograd and
 against central finite differences.
+
+The bfloat16 option of loss_grad (operand_round=bf16_round) rounds both
+operands of every hidden-layer product, as the matrix-core pass does, and
+computes everything else in float64.  Pins: bf16_round against torch's
+bfloat16 conversion (ties included); no change for a network without hidden
+products; the value-set losses against a torch float64 forward with
+torch-rounded operands.  Where the backward products take rounded operands
+has no independent pin (parity unpinned for that placement beyond the
+agreement with the device pass).
 """
 from __future__ import annotations
 
@@ -72,12 +81,27 @@ def forward(theta, X, n_in, depth, width):
     return (a @ Wo.T + bo)[:, 0]
 
 
-def _hidden_streams(layers, X):
+def bf16_round(x):
+    """x rounded to bfloat16 (8 significant bits, to nearest, ties to even)
+    through float32, as a float32 value converts to bfloat16."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _identity(x):
+    return x
+
+
+def _hidden_streams(layers, X, rnd=_identity):
     """Forward-mode streams through the hidden layers.
 
     Returns per layer the cache (a, z_t, z_x, z_xx) and the final
     (a, a_t, a_x, a_xx).  For a = tanh(z), s = 1 - a^2:
         a_t = s z_t,  a_x = s z_x,  a_xx = s z_xx - 2 a s z_x^2.
+    rnd is applied to both operands of every hidden-layer product (the
+    identity, or bf16_round for operands rounded to bfloat16).
     """
     n = X.shape[0]
     W1, b1 = layers[0]
@@ -89,10 +113,11 @@ def _hidden_streams(layers, X):
     for li in range(len(layers) - 1):
         if li > 0:
             W, b = layers[li]
-            z = a @ W.T + b
-            z_t = a_t @ W.T
-            z_x = a_x @ W.T
-            z_xx = a_xx @ W.T
+            Wr = rnd(W)
+            z = rnd(a) @ Wr.T + b
+            z_t = rnd(a_t) @ Wr.T
+            z_x = rnd(a_x) @ Wr.T
+            z_xx = rnd(a_xx) @ Wr.T
         a = np.tanh(z)
         s = 1.0 - a * a
         caches.append((a, z_t, z_x, z_xx))
@@ -181,9 +206,15 @@ def loss3(theta, X_f, X_e, X_b, n_in, depth, width, is_put=False, sigma=None, r=
 
 
 def loss_grad(theta, X_f, X_e, X_b, n_in, depth, width, is_put=False, sigma=None, r=None,
-              y_e=None, y_b=None):
+              y_e=None, y_b=None, operand_round=None, with_loss=False):
     """Gradient of MSE_f + MSE_exp + MSE_b with respect to the flat parameters
     (targets y_e, y_b as in loss3).
+
+    operand_round (e.g. bf16_round) is applied to both operands of every
+    hidden-layer product, forward (W a_s) and backward (W^T zbar_s and
+    zbar_s a_prev_s^T), and nowhere else: the arithmetic of a pass whose
+    hidden-layer products take bfloat16 operands.  with_loss: return
+    ((MSE_f, MSE_exp, MSE_b), gradient), the losses from the same streams.
 
     Reverse pass, written by hand, through the value and derivative streams.
     Output adjoints per point (gv, gt, gx, gxx) for (v, v_tau, v_x, v_xx):
@@ -206,13 +237,15 @@ def loss_grad(theta, X_f, X_e, X_b, n_in, depth, width, is_put=False, sigma=None
     layers = unpack(theta, n_in, depth, width)
     n_f, n_e, n_b = X_f.shape[0], X_e.shape[0], X_b.shape[0]
     X = np.concatenate([X_f, X_e, X_b], axis=0)
-    caches, (a, a_t, a_x, a_xx) = _hidden_streams(layers, X)
+    rnd = _identity if operand_round is None else operand_round
+    caches, (a, a_t, a_x, a_xx) = _hidden_streams(layers, X, rnd)
     Wo, bo = layers[-1]
     wo = Wo[0]
     v = a @ wo + bo[0]
     v_t, v_x, v_xx = a_t @ wo, a_x @ wo, a_xx @ wo
 
     n = X.shape[0]
+    losses = [0.0, 0.0, 0.0]
     ye, yb = _targets(X_e, X_b, is_put, r, y_e, y_b)
     gv, gt, gx, gxx = np.zeros(n), np.zeros(n), np.zeros(n), np.zeros(n)
     if n_f:
@@ -220,6 +253,7 @@ def loss_grad(theta, X_f, X_e, X_b, n_in, depth, width, is_put=False, sigma=None
         sg, rr = _coeffs(X_f, sigma, r)
         x = X_f[:, 1]
         f = residual_from_streams(v[sl], v_t[sl], v_x[sl], v_xx[sl], x, sg, rr)
+        losses[0] = _mean(f * f)
         df = 2.0 * f / n_f
         gv[sl] = rr * df
         gt[sl] = df
@@ -227,9 +261,11 @@ def loss_grad(theta, X_f, X_e, X_b, n_in, depth, width, is_put=False, sigma=None
         gxx[sl] = -0.5 * sg * sg * x * x * df
     if n_e:
         sl = slice(n_f, n_f + n_e)
+        losses[1] = _mean((v[sl] - ye) ** 2)
         gv[sl] = 2.0 * (v[sl] - ye) / n_e
     if n_b:
         sl = slice(n_f + n_e, n)
+        losses[2] = _mean((v[sl] - yb) ** 2)
         gv[sl] = 2.0 * (v[sl] - yb) / n_b
 
     grads = []
@@ -250,8 +286,10 @@ def loss_grad(theta, X_f, X_e, X_b, n_in, depth, width, is_put=False, sigma=None
             p_s = 1.0 - p_a * p_a
             pa_t, pa_x = p_s * p_zt, p_s * p_zx
             pa_xx = p_s * p_zxx - 2.0 * p_a * p_s * p_zx * p_zx
-            gW = zb.T @ p_a + zb_t.T @ pa_t + zb_x.T @ pa_x + zb_xx.T @ pa_xx
-            A, At, Ax, Axx = zb @ W, zb_t @ W, zb_x @ W, zb_xx @ W
+            gW = (rnd(zb).T @ rnd(p_a) + rnd(zb_t).T @ rnd(pa_t) + rnd(zb_x).T @ rnd(pa_x)
+                  + rnd(zb_xx).T @ rnd(pa_xx))
+            Wr = rnd(W)
+            A, At, Ax, Axx = rnd(zb) @ Wr, rnd(zb_t) @ Wr, rnd(zb_x) @ Wr, rnd(zb_xx) @ Wr
         else:
             gW = zb.T @ X
             gW[:, 0] += zb_t.sum(axis=0)
@@ -260,7 +298,8 @@ def loss_grad(theta, X_f, X_e, X_b, n_in, depth, width, is_put=False, sigma=None
     grads.reverse()
     flat = [np.concatenate([gW.ravel(), gb]) for gW, gb in grads]
     flat.append(np.concatenate([g_wo, g_bo]))
-    return np.concatenate(flat)
+    grad = np.concatenate(flat)
+    return (tuple(losses), grad) if with_loss else grad
 
 
 def grid_values(theta, n_in, depth, width, K, taus, S, sigma=None, r=None):

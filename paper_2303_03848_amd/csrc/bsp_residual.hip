@@ -28,40 +28,11 @@
 // bitwise reproducible.
 #include <cmath>
 
-#include "bsp_common.hpp"
-#include "bsp_net.hpp"
+#include "bsp_residual.hpp"
 
 namespace bsp {
 
 // ------------------------------------------------------------------ layout
-
-struct NetLayout {
-    int n_in, depth, W;
-    long offW[17], offb[17];  // layer l = 1..depth
-    long off_wo, off_bo, total;
-};
-
-static NetLayout net_layout(const pinn_net& n) {
-    NetLayout L{};
-    L.n_in = n.n_in;
-    L.depth = n.depth;
-    L.W = n.width;
-    long o = 0;
-    int fan = n.n_in;
-    for (int l = 1; l <= n.depth; ++l) {
-        L.offW[l] = o;
-        o += (long)n.width * fan;
-        L.offb[l] = o;
-        o += n.width;
-        fan = n.width;
-    }
-    L.off_wo = o;
-    o += n.width;
-    L.off_bo = o;
-    o += 1;
-    L.total = o;
-    return L;
-}
 
 struct ResWs {
     long n_pad;
@@ -70,7 +41,7 @@ struct ResWs {
     float* abar;    // 4 * n_pad * W
     float* g;       // 4 * n_pad
     float* lossc;   // n_pad
-    float* part;    // MFMA path: partial gradients
+    float* part;    // partial gradients: kPartRows rows of total + 3 floats
     size_t bytes;
 };
 
@@ -95,37 +66,9 @@ static ResWs res_layout(const pinn_net& n, long npts, void* base) {
     w.abar = (float*)take(plane);
     w.g = (float*)take(sizeof(float) * 4 * w.n_pad);
     w.lossc = (float*)take(sizeof(float) * w.n_pad);
-    w.part = (float*)take(sizeof(float) * (size_t)kPartRows * net_layout(n).total);
+    w.part = (float*)take(sizeof(float) * (size_t)kPartRows * (net_layout(n).total + 3));
     w.bytes = off;
     return w;
-}
-
-// ------------------------------------------------------------- point access
-
-struct Points {
-    const float *Xf, *Xe, *Xb;
-    int nf, ne, nb, n_in;
-    float sigma, r;   // used when n_in == 2
-    int is_put;
-    const float *ye, *yb;  // value targets of the terminal / boundary sets, or null
-};
-
-__device__ __forceinline__ const float* point_row(const Points& P, long i) {
-    if (i < P.nf) return P.Xf + i * P.n_in;
-    if (i < P.nf + P.ne) return P.Xe + (i - P.nf) * P.n_in;
-    return P.Xb + (i - P.nf - P.ne) * P.n_in;
-}
-
-// Input streams of the layer after `c` (cache of the previous layer).
-__device__ __forceinline__ void streams_from_cache(const float* c, long plane, long idx,
-                                                   float& a, float& at, float& ax, float& axx) {
-    const float av = c[idx], zt = c[plane + idx], zx = c[2 * plane + idx],
-                zxx = c[3 * plane + idx];
-    const float s = 1.0f - av * av;
-    a = av;
-    at = s * zt;
-    ax = s * zx;
-    axx = s * zxx - 2.0f * av * s * zx * zx;
 }
 
 // --------------------------------------------------------- forward kernels
@@ -309,34 +252,8 @@ __global__ void k_res_head(const float* __restrict__ prm, long off_wo, long off_
         return;
     }
     v += prm[off_bo];
-    const float* x = point_row(P, i);
-    const float sig = P.n_in == 4 ? x[2] : P.sigma;
-    const float rr = P.n_in == 4 ? x[3] : P.r;
-    float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, lc;
-    if (i < P.nf) {
-        const float xx = x[1];
-        const float f = vt - 0.5f * sig * sig * xx * xx * vxx - rr * xx * vx + rr * v;
-        lc = f * f;
-        const float df = 2.0f * f / (float)P.nf;
-        g0 = rr * df;
-        g1 = df;
-        g2 = -rr * xx * df;
-        g3 = -0.5f * sig * sig * xx * xx * df;
-    } else if (i < P.nf + P.ne) {
-        const float xx = x[1];
-        const float y = P.ye ? P.ye[i - P.nf]
-                             : (P.is_put ? fmaxf(1.0f - xx, 0.0f) : fmaxf(xx - 1.0f, 0.0f));
-        lc = (v - y) * (v - y);
-        g0 = 2.0f * (v - y) / (float)P.ne;
-    } else {
-        const float tau = x[0], xx = x[1];
-        const float disc = expf(-rr * tau);
-        const bool lower = xx == 0.0f;
-        const float y = P.yb ? P.yb[i - P.nf - P.ne]
-                             : (P.is_put ? (lower ? disc : 0.0f) : (lower ? 0.0f : xx - disc));
-        lc = (v - y) * (v - y);
-        g0 = 2.0f * (v - y) / (float)P.nb;
-    }
+    float g0, g1, g2, g3, lc;
+    head_point(P, i, v, vt, vx, vxx, g0, g1, g2, g3, lc);
     g[i] = g0;
     g[n_pad + i] = g1;
     g[2 * n_pad + i] = g2;
@@ -390,13 +307,13 @@ __global__ void k_res_zbar(const float* __restrict__ c, const float* __restrict_
         Ax = g[2 * n_pad + i] * w;
         Axx = g[3 * n_pad + i] * w;
     }
-    const float a = c[t], zt = c[plane + t], zx = c[2 * plane + t], zxx = c[3 * plane + t];
-    const float s = 1.0f - a * a;
-    zbar[plane + t] = s * At;
-    zbar[2 * plane + t] = s * Ax - 4.0f * a * s * zx * Axx;
-    zbar[3 * plane + t] = s * Axx;
-    zbar[t] = s * (A - 2.0f * a * (zt * At + zx * Ax + zxx * Axx) -
-                   2.0f * zx * zx * (1.0f - 3.0f * a * a) * Axx);
+    float zb, zb_t, zb_x, zb_xx;
+    tanh_adjoint(A, At, Ax, Axx, c[t], c[plane + t], c[2 * plane + t], c[3 * plane + t], zb, zb_t,
+                 zb_x, zb_xx);
+    zbar[plane + t] = zb_t;
+    zbar[2 * plane + t] = zb_x;
+    zbar[3 * plane + t] = zb_xx;
+    zbar[t] = zb;
 }
 
 
@@ -576,9 +493,9 @@ __global__ void k_res_grad_out(const float* __restrict__ g, const float* __restr
 
 int launch_res_reduce(const float* part, int nblk, int count, float* out, hipStream_t st);
 
-int launch_res_gemm_bf16(int which, const float* Wl, const float* bl, const float* cin,
-                         float* cout_or_abar, const float* zbar, long n, long n_pad, int W,
-                         float* gW, float* gb, float* part, hipStream_t st);
+int launch_res_step_bf16(const pinn_net& net, const Points& P, long n, long n_pad, float* cache,
+                         float* abar, float* g, float* part, long ldp, int max_blocks, float* grad,
+                         float* loss3, hipStream_t st);
 
 static dim3 grid_for(long work, int block) { return dim3((unsigned)((work + block - 1) / block)); }
 
@@ -626,24 +543,22 @@ extern "C" int pinn_residual_fwd_bwd(const pinn_net* net, const bs_params* prm, 
     const float* P0 = net->params;
     Points P{X_f, X_e, X_b, n_f, n_e, n_b, net->n_in, (float)prm->sigma, (float)prm->r,
              prm->is_put, y_e, y_b};
-    const bool mfma = net->precision == BS_PREC_BF16;
+    if (net->precision == BS_PREC_BF16) {
+        // the whole pass in one launch, then the reduction of its partial rows
+        BSP_CHECK_ARG(((uintptr_t)P0 & 15) == 0 && ((uintptr_t)ws & 15) == 0,
+                      "the bfloat16 residual path needs 16-byte aligned parameters and workspace");
+        return launch_res_step_bf16(*net, P, n, np, w.cache, w.abar, w.g, w.part, L.total + 3,
+                                    kPartRows, grad, loss3, st);
+    }
     auto cache = [&](int l) { return w.cache + (size_t)(l - 1) * 4 * plane; };
 
     hipLaunchKernelGGL(k_res_first, grid_for(work, 256), dim3(256), 0, st, P0, P, n, np, W,
                        cache(1));
     BSP_LAUNCHED();
-    for (int l = 2; l <= d; ++l) {
-        if (mfma) {
-            if ((rc = launch_res_gemm_bf16(0, P0 + L.offW[l], P0 + L.offb[l], cache(l - 1),
-                                           cache(l), nullptr, n, np, W, nullptr, nullptr,
-                                           nullptr, st)))
-                return rc;
-        } else {
-            if ((rc = launch_res_gemm_f32<0>(P0 + L.offW[l], P0 + L.offb[l], cache(l - 1),
-                                             cache(l), np, W, st)))
-                return rc;
-        }
-    }
+    for (int l = 2; l <= d; ++l)
+        if ((rc = launch_res_gemm_f32<0>(P0 + L.offW[l], P0 + L.offb[l], cache(l - 1), cache(l),
+                                         np, W, st)))
+            return rc;
     hipLaunchKernelGGL(k_res_head, grid_for(np, 32), dim3(256), 0, st, P0, L.off_wo, L.off_bo,
                        P, n, np, W, cache(d), w.g, w.lossc);
     BSP_LAUNCHED();
@@ -668,31 +583,23 @@ extern "C" int pinn_residual_fwd_bwd(const pinn_net* net, const bs_params* prm, 
                 return rc;
             break;
         }
-        if (mfma) {
-            if ((rc = launch_res_gemm_bf16(1, P0 + L.offW[l], nullptr, cache(l - 1), w.abar,
-                                           w.zbar, n, np, W, grad + L.offW[l], grad + L.offb[l],
-                                           w.part, st)))
-                return rc;
-        } else {
-            if ((rc = launch_res_gemm_f32<1>(P0 + L.offW[l], nullptr, w.zbar, w.abar, np, W,
-                                             st)))
-                return rc;
-            switch (W) {
+        if ((rc = launch_res_gemm_f32<1>(P0 + L.offW[l], nullptr, w.zbar, w.abar, np, W, st)))
+            return rc;
+        switch (W) {
 #define BSP_W(W_)                                                                             \
     case W_:                                                                                  \
         hipLaunchKernelGGL(k_res_gradw_tiled<W_>, dim3(kGradwBlocks), dim3(256), 0, st, w.zbar, \
                            cache(l - 1), n, np, w.part);                                      \
         break;
-                BSP_W(16) BSP_W(32) BSP_W(64) BSP_W(128) BSP_W(256)
+            BSP_W(16) BSP_W(32) BSP_W(64) BSP_W(128) BSP_W(256)
 #undef BSP_W
-                default:
-                    set_error("unsupported width %d", W);
-                    return BS_ERR_ARG;
-            }
-            BSP_LAUNCHED();
-            if ((rc = launch_res_reduce(w.part, kGradwBlocks, W * W + W, grad + L.offW[l], st)))
-                return rc;
+            default:
+                set_error("unsupported width %d", W);
+                return BS_ERR_ARG;
         }
+        BSP_LAUNCHED();
+        if ((rc = launch_res_reduce(w.part, kGradwBlocks, W * W + W, grad + L.offW[l], st)))
+            return rc;
     }
     return BS_OK;
 }

@@ -1,188 +1,525 @@
-// Matrix-core (bfloat16 in, float32 accumulate) versions of the two
-// GEMM-shaped steps of the PINN loss gradient, for widths 32, 64, 128.
+// The PINN loss and its gradient (eqs. (11)-(14)) in one launch on the
+// matrix cores (bfloat16 operands, float32 accumulation), for widths 32, 64
+// and 128, plus one launch that reduces the per-block partial sums.
 //
-// Forward hidden layer (k_res_fwd_bf16): a tile of 32 points carries its four
-// input streams (value, d/dtau, d/dx, d2/dx2; recomputed from the previous
-// layer's cache) in LDS; each wavefront owns 32-unit output blocks and runs
-// one MFMA chain per stream against the staged weights; the epilogue applies
-// the tanh stream rule and writes the layer cache.
-//
-// Backward hidden layer (k_res_bwd_bf16), persistent over point tiles:
-//   abar_prev[s] = zbar[s] W                     (data adjoints, per tile)
-//   dW += sum_s zbar[s]^T a_prev[s],  db += sum zbar[0]   (weights)
-// The weight gradient is accumulated per block across its tiles in
-// registers and written as one partial per block; k_res_reduce sums the
-// partials in block order, so the result is deterministic.
-#include "bsp_common.hpp"
-#include "bsp_net.hpp"
+// Every step of the gradient is local to a point except the sums over
+// points, so one block takes a few 32-point tiles through the whole pass:
+//   first layer (vector units) -> hidden layers (one MFMA chain per
+//   derivative stream, weights staged in LDS once per layer and block) ->
+//   head (output layer, loss terms, output adjoints) -> backward through the
+//   hidden layers (data adjoints W^T zbar per tile, weight gradient
+//   sum_s zbar_s^T a_prev_s accumulated over the block's tiles in MFMA
+//   registers) -> first-layer gradient.
+// The per-layer caches (a, z_t, z_x, z_xx), the data adjoints and the output
+// adjoints go through the workspace (float32, written and read back by the
+// same block).  Each block writes one partial row: every parameter's
+// gradient over its points, then the three loss sums by point type;
+// k_res_reduce_step adds the rows in block order, so the result does not
+// depend on timing.
+#include "bsp_residual.hpp"
 
 namespace bsp {
 
-constexpr int kResPartBlocksMfma = 64;
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void streams_of(const float* c, long plane, long idx, float (&a)[4]) {
-    const float av = c[idx], zt = c[plane + idx], zx = c[2 * plane + idx], zxx = c[3 * plane + idx];
-    const float s = 1.0f - av * av;
-    a[0] = av;
-    a[1] = s * zt;
-    a[2] = s * zx;
-    a[3] = s * zxx - 2.0f * av * s * zx * zx;
+constexpr int kResStepThreads = 256;
+constexpr int kResStepMinTiles = 2;  // tiles per block: fewer partial rows to reduce
+
+struct ResStepArgs {
+    const float* prm;  // parameters, float32, nn.Linear order
+    Points P;
+    NetLayout L;
+    long n, n_pad;     // points, points rounded up to whole tiles
+    int ntiles, tiles_per_block;
+    float* cache;      // depth x [4][n_pad][W]: (a, z_t, z_x, z_xx) per layer
+    float* abar;       // [4][n_pad][W]: adjoints of the streams entering a layer
+    float* g;          // [4][n_pad]: output adjoints
+    float* part;       // [blocks][ldp]
+    long ldp;          // L.total + 3
+};
+
+__device__ __forceinline__ float4 ld4(const float* p) { return *reinterpret_cast<const float4*>(p); }
+
+__device__ __forceinline__ void st4(float* p, float x, float y, float z, float w) {
+    *reinterpret_cast<float4*>(p) = make_float4(x, y, z, w);
+}
+
+__device__ __forceinline__ void st_bf16x4(__bf16* p, const float (&v)[4]) {
+    bf16x4 b;
+    b[0] = (__bf16)v[0];
+    b[1] = (__bf16)v[1];
+    b[2] = (__bf16)v[2];
+    b[3] = (__bf16)v[3];
+    *reinterpret_cast<bf16x4*>(p) = b;
+}
+
+__device__ __forceinline__ float comp(const float4& v, int q) {
+    return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w;
 }
 
 template <int W>
-__global__ __launch_bounds__(256) void k_res_fwd_bf16(const float* __restrict__ Wl,
-                                                      const float* __restrict__ bl,
-                                                      const float* __restrict__ cprev,
-                                                      float* __restrict__ cnext, long n_pad) {
-    constexpr int LDA = W + 8;
-    __shared__ __align__(16) __bf16 As[4][32 * LDA];
-    __shared__ __align__(16) __bf16 Ws[W * LDA];
+__global__ __launch_bounds__(kResStepThreads) void k_res_step_bf16(ResStepArgs a) {
+    constexpr int NT = kResStepThreads;
+    constexpr int LDA = W + 8;            // [point][unit] tiles (bf16)
+    constexpr int LDT = 32 + 8;           // [unit][point] tiles (bf16)
+    constexpr int NCB = W / 32;           // 32-unit blocks of a layer
+    constexpr int NBW = (NCB * NCB + 3) / 4;  // 32 x 32 blocks of dW per wavefront
+    constexpr int G4 = W / 4;             // 4-unit groups of a row
+    constexpr int RP = NT / G4;           // rows per pass of the elementwise phases
+    constexpr int PASSES = 32 / RP;
+    constexpr int NG8 = W * W / 8;        // 8-element groups of a weight matrix
+    __shared__ __align__(16) __bf16 Wsh[W * LDA];     // W[j][k] forward, W[j][k] at [k][j] backward
+    __shared__ __align__(16) __bf16 Xs[4][32 * LDA];  // input streams [i][k], or zbar [i][j]
+    __shared__ __align__(16) __bf16 ZT[4][W * LDT];   // zbar [j][i]
+    __shared__ __align__(16) __bf16 aT[4][W * LDT];   // previous layer's streams [k][i]
+    __shared__ float gsh[4][32];
+    __shared__ float lsh[32];
+    float* red = reinterpret_cast<float*>(&ZT[0][0]);  // RP x W floats between phases
+
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r32 = lane & 31, h = lane >> 5;
-    const long i0 = (long)blockIdx.x * 32;
-    const long plane = n_pad * W;
-    for (int e = tid; e < 32 * W; e += 256) {
-        const int i = e / W, k = e - i * W;
-        float a[4];
-        streams_of(cprev, plane, (i0 + i) * W + k, a);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) As[s][i * LDA + k] = (__bf16)a[s];
-    }
-    for (int e = tid; e < W * W; e += 256) {
-        const int j = e / W, k = e - j * W;
-        Ws[j * LDA + k] = (__bf16)Wl[e];
-    }
-    __syncthreads();
-    for (int cb = wave; cb * 32 < W; cb += 4) {
-        f32x16 acc[4];
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int v = 0; v < 16; ++v) acc[s][v] = 0.f;
-#pragma unroll
-        for (int t = 0; t < W / 16; ++t) {
-            const bf16x8 b = lds_frag(&Ws[(cb * 32 + r32) * LDA + 16 * t + 8 * h]);
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-                acc[s] = mfma32x32x16(lds_frag(&As[s][r32 * LDA + 16 * t + 8 * h]), b, acc[s]);
-        }
-        const int j = cb * 32 + r32;
-        const float bj = bl[j];
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const long idx = (i0 + mfma_row(v, lane)) * W + j;
-            cnext[idx] = tanh_f32(acc[0][v] + bj);
-            cnext[plane + idx] = acc[1][v];
-            cnext[2 * plane + idx] = acc[2][v];
-            cnext[3 * plane + idx] = acc[3][v];
-        }
-    }
-}
+    const int u0 = 4 * (tid % G4), rr = tid / G4;  // units u0 .. u0 + 3, rows rr + RP p
+    const NetLayout& L = a.L;
+    const int d = L.depth, n_in = L.n_in;
+    const long n = a.n, n_pad = a.n_pad, plane = n_pad * W;
+    const int t0 = blockIdx.x * a.tiles_per_block;
+    const int t1 = min(t0 + a.tiles_per_block, a.ntiles);
+    const float* prm = a.prm;
+    const float* wo = prm + L.off_wo;
+    float* out = a.part + (long)blockIdx.x * a.ldp;
+    auto cache = [&](int l) { return a.cache + (long)(l - 1) * 4 * plane; };
 
-template <int W>
-__global__ __launch_bounds__(256) void k_res_bwd_bf16(const float* __restrict__ Wl,
-                                                      const float* __restrict__ zbar,
-                                                      const float* __restrict__ cprev,
-                                                      float* __restrict__ abar, long n_pad,
-                                                      int ntiles, float* __restrict__ part) {
-    constexpr int LDA = W + 8;   // [point][unit] tiles
-    constexpr int LDT = 32 + 8;  // [unit][point] tiles
-    constexpr int NBJ = W / 32;  // 32-wide blocks per dimension of dW
-    constexpr int NBW = (NBJ * NBJ + 3) / 4;  // dW blocks per wavefront
-    __shared__ __align__(16) __bf16 Zs[4][32 * LDA];
-    __shared__ __align__(16) __bf16 ZT[4][W * LDT];
-    __shared__ __align__(16) __bf16 aT[4][W * LDT];
-    __shared__ __align__(16) __bf16 WT[W * LDA];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r32 = lane & 31, h = lane >> 5;
-    const long plane = n_pad * W;
-
-    for (int e = tid; e < W * W; e += 256) {
-        const int k = e / W, j = e - k * W;
-        WT[k * LDA + j] = (__bf16)Wl[(long)j * W + k];
-    }
-    f32x16 gacc[NBW];
-#pragma unroll
-    for (int b = 0; b < NBW; ++b)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) gacc[b][v] = 0.f;
-    float gb = 0.f;
-
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const long i0 = (long)tile * 32;
+    // Per-thread partials acc[q] of unit u0 + q over rows rr + RP p, summed
+    // over the RP row groups in order; unit u goes to dst[u * stride].
+    auto combine = [&](const float (&acc)[4], float* dst, int stride) {
         __syncthreads();
-        for (int e = tid; e < 32 * W; e += 256) {
-            const int i = e / W, j = e - i * W;
-            const long idx = (i0 + i) * W + j;
-            float a[4];
-            streams_of(cprev, plane, idx, a);
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const __bf16 z = (__bf16)zbar[s * plane + idx];
-                Zs[s][i * LDA + j] = z;
-                ZT[s][j * LDT + i] = z;
-                aT[s][j * LDT + i] = (__bf16)a[s];
+        for (int q = 0; q < 4; ++q) red[rr * W + u0 + q] = acc[q];
+        __syncthreads();
+        if (tid < W) {
+            float s = red[tid];
+            for (int r = 1; r < RP; ++r) s += red[r * W + tid];
+            dst[(long)tid * stride] = s;
+        }
+    };
+
+    // ---- first layer: z = W1 x + b1, z_t = W1[:,0], z_x = W1[:,1], z_xx = 0
+    {
+        float w1[4][4], b1[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            b1[q] = prm[L.offb[1] + u0 + q];
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                w1[q][c] = c < n_in ? prm[L.offW[1] + (long)(u0 + q) * n_in + c] : 0.f;
+        }
+        float* c1 = cache(1);
+        for (int t = t0; t < t1; ++t)
+#pragma unroll
+            for (int p = 0; p < PASSES; ++p) {
+                const long i = (long)t * 32 + rr + RP * p;
+                float av[4] = {0.f, 0.f, 0.f, 0.f}, zt[4] = {0.f, 0.f, 0.f, 0.f},
+                      zx[4] = {0.f, 0.f, 0.f, 0.f};
+                if (i < n) {
+                    const float* xr = point_row(a.P, i);
+                    float x[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) x[c] = c < n_in ? xr[c] : 0.f;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        float z = b1[q];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            if (c < n_in) z = fmaf(w1[q][c], x[c], z);
+                        av[q] = tanh_f32(z);
+                        zt[q] = w1[q][0];
+                        zx[q] = w1[q][1];
+                    }
+                }
+                const long idx = i * W + u0;
+                st4(c1 + idx, av[0], av[1], av[2], av[3]);
+                st4(c1 + plane + idx, zt[0], zt[1], zt[2], zt[3]);
+                st4(c1 + 2 * plane + idx, zx[0], zx[1], zx[2], zx[3]);
+                st4(c1 + 3 * plane + idx, 0.f, 0.f, 0.f, 0.f);
+            }
+    }
+
+    // ---- hidden layers: z_s = W a_s (+ b for the value), then the tanh streams
+    for (int l = 2; l <= d; ++l) {
+        const float* Wl = prm + L.offW[l];
+        const float* bl = prm + L.offb[l];
+        const float* cp = cache(l - 1);
+        float* cn = cache(l);
+        __syncthreads();  // the previous layer's products are done with Wsh and Xs
+#pragma unroll
+        for (int m = 0; m < (NG8 + NT - 1) / NT; ++m) {
+            const int e = tid + NT * m;
+            if (e < NG8) {
+                const int j = e / (W / 8), k = (e - j * (W / 8)) * 8;
+                const float4 w0 = ld4(Wl + (long)j * W + k), w1 = ld4(Wl + (long)j * W + k + 4);
+                bf16x8 b;
+                b[0] = (__bf16)w0.x; b[1] = (__bf16)w0.y; b[2] = (__bf16)w0.z; b[3] = (__bf16)w0.w;
+                b[4] = (__bf16)w1.x; b[5] = (__bf16)w1.y; b[6] = (__bf16)w1.z; b[7] = (__bf16)w1.w;
+                *reinterpret_cast<bf16x8*>(&Wsh[j * LDA + k]) = b;
             }
         }
-        if (tid < W)
-            for (int i = 0; i < 32; ++i) gb += zbar[(i0 + i) * W + tid];
-        __syncthreads();
-        // data adjoints of the previous layer: abar_prev[s][i][k] = sum_j zbar[s][i][j] W[j][k]
-        for (int cb = wave; cb * 32 < W; cb += 4) {
-            f32x16 acc[4];
+        for (int t = t0; t < t1; ++t) {
+            const long i0 = (long)t * 32;
+            if (t > t0) __syncthreads();  // the previous tile's products are done with Xs
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
+            for (int p = 0; p < PASSES; ++p) {
+                const int i = rr + RP * p;
+                const long idx = (i0 + i) * W + u0;
+                const float4 c0 = ld4(cp + idx), c1 = ld4(cp + plane + idx),
+                             c2 = ld4(cp + 2 * plane + idx), c3 = ld4(cp + 3 * plane + idx);
+                float s0[4], s1[4], s2[4], s3[4];
 #pragma unroll
-                for (int v = 0; v < 16; ++v) acc[s][v] = 0.f;
-#pragma unroll
-            for (int t = 0; t < W / 16; ++t) {
-                const bf16x8 b = lds_frag(&WT[(cb * 32 + r32) * LDA + 16 * t + 8 * h]);
+                for (int q = 0; q < 4; ++q)
+                    streams_of_values(comp(c0, q), comp(c1, q), comp(c2, q), comp(c3, q), s0[q],
+                                      s1[q], s2[q], s3[q]);
+                st_bf16x4(&Xs[0][i * LDA + u0], s0);
+                st_bf16x4(&Xs[1][i * LDA + u0], s1);
+                st_bf16x4(&Xs[2][i * LDA + u0], s2);
+                st_bf16x4(&Xs[3][i * LDA + u0], s3);
+            }
+            __syncthreads();
+            for (int cb = wave; cb < NCB; cb += 4) {
+                f32x16 acc[4];
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
-                    acc[s] = mfma32x32x16(lds_frag(&Zs[s][r32 * LDA + 16 * t + 8 * h]), b, acc[s]);
-            }
-            const int k = cb * 32 + r32;
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const long idx = (i0 + mfma_row(v, lane)) * W + k;
+                    for (int v = 0; v < 16; ++v) acc[s][v] = 0.f;
 #pragma unroll
-                for (int s = 0; s < 4; ++s) abar[s * plane + idx] = acc[s][v];
+                for (int k = 0; k < W / 16; ++k) {
+                    const bf16x8 b = lds_frag(&Wsh[(cb * 32 + r32) * LDA + 16 * k + 8 * h]);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        acc[s] = mfma32x32x16(lds_frag(&Xs[s][r32 * LDA + 16 * k + 8 * h]), b,
+                                              acc[s]);
+                }
+                const int j = cb * 32 + r32;
+                const float bj = bl[j];
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const long idx = (i0 + mfma_row(v, lane)) * W + j;
+                    cn[idx] = tanh_f32(acc[0][v] + bj);
+                    cn[plane + idx] = acc[1][v];
+                    cn[2 * plane + idx] = acc[2][v];
+                    cn[3 * plane + idx] = acc[3][v];
+                }
             }
         }
-        // weight gradient: dW[j][k] += sum_s sum_i zbar[s][i][j] a_prev[s][i][k]
+    }
+
+    // ---- head: output layer, loss terms, output adjoints; output-layer gradient
+    {
+        const float* cd = cache(d);
+        float lsum[3] = {0.f, 0.f, 0.f}, dbo = 0.f;
+        float dwo[4] = {0.f, 0.f, 0.f, 0.f};
+        const int u = tid & 7, pt = tid >> 3;  // eight lanes per point
+        for (int t = t0; t < t1; ++t) {
+            const long i0 = (long)t * 32;
+            __syncthreads();  // cache(d) complete; gsh and lsh free
+            const long i = i0 + pt;
+            float v = 0.f, vt = 0.f, vx = 0.f, vxx = 0.f;
+            if (i < n) {
+                for (int j = u; j < W; j += 8) {
+                    float s0, s1, s2, s3;
+                    streams_from_cache(cd, plane, i * W + j, s0, s1, s2, s3);
+                    v = fmaf(wo[j], s0, v);
+                    vt = fmaf(wo[j], s1, vt);
+                    vx = fmaf(wo[j], s2, vx);
+                    vxx = fmaf(wo[j], s3, vxx);
+                }
+            }
+#pragma unroll
+            for (int o = 1; o < 8; o <<= 1) {
+                v += __shfl_xor(v, o, 8);
+                vt += __shfl_xor(vt, o, 8);
+                vx += __shfl_xor(vx, o, 8);
+                vxx += __shfl_xor(vxx, o, 8);
+            }
+            if (u == 0) {
+                float g0 = 0.f, g1 = 0.f, g2 = 0.f, g3 = 0.f, lc = 0.f;
+                if (i < n) head_point(a.P, i, v + prm[L.off_bo], vt, vx, vxx, g0, g1, g2, g3, lc);
+                gsh[0][pt] = g0;
+                gsh[1][pt] = g1;
+                gsh[2][pt] = g2;
+                gsh[3][pt] = g3;
+                lsh[pt] = lc;
+                a.g[i] = g0;
+                a.g[n_pad + i] = g1;
+                a.g[2 * n_pad + i] = g2;
+                a.g[3 * n_pad + i] = g3;
+            }
+            __syncthreads();
+            if (tid == 0)
+                for (int q = 0; q < 32; ++q) {
+                    const long iq = i0 + q;
+                    if (iq < n) lsum[iq < a.P.nf ? 0 : iq < a.P.nf + a.P.ne ? 1 : 2] += lsh[q];
+                    dbo += gsh[0][q];
+                }
+            // dwo[j] += sum_s g_s[i] a_s[i][j] over this tile's points
+#pragma unroll
+            for (int p = 0; p < PASSES; ++p) {
+                const int ip = rr + RP * p;
+                const long idx = (i0 + ip) * W + u0;
+                const float4 c0 = ld4(cd + idx), c1 = ld4(cd + plane + idx),
+                             c2 = ld4(cd + 2 * plane + idx), c3 = ld4(cd + 3 * plane + idx);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float s0, s1, s2, s3;
+                    streams_of_values(comp(c0, q), comp(c1, q), comp(c2, q), comp(c3, q), s0, s1,
+                                      s2, s3);
+                    float tq = gsh[0][ip] * s0;
+                    tq = fmaf(gsh[1][ip], s1, tq);
+                    tq = fmaf(gsh[2][ip], s2, tq);
+                    tq = fmaf(gsh[3][ip], s3, tq);
+                    dwo[q] += tq;
+                }
+            }
+        }
+        combine(dwo, out + L.off_wo, 1);
+        if (tid == 0) {
+            out[L.off_bo] = dbo;
+            out[L.total] = lsum[0];
+            out[L.total + 1] = lsum[1];
+            out[L.total + 2] = lsum[2];
+        }
+    }
+
+    // ---- backward through the hidden layers
+    for (int l = d; l >= 2; --l) {
+        const float* Wl = prm + L.offW[l];
+        const float* cl = cache(l);
+        const float* cp = cache(l - 1);
+        __syncthreads();  // the head / the previous layer are done with Wsh, Xs, ZT, aT
+        // Wsh[k][j] = W[j][k]: rows j, j + 1 read together, one 4-byte store per k
+#pragma unroll
+        for (int m = 0; m < (NG8 + NT - 1) / NT; ++m) {
+            const int e = tid + NT * m;
+            if (e < NG8) {
+                const int jp = e / (W / 4), k = (e - jp * (W / 4)) * 4, j = 2 * jp;
+                const float4 r0 = ld4(Wl + (long)j * W + k), r1 = ld4(Wl + (long)(j + 1) * W + k);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    bf16x2 b;
+                    b[0] = (__bf16)comp(r0, q);
+                    b[1] = (__bf16)comp(r1, q);
+                    *reinterpret_cast<bf16x2*>(&Wsh[(k + q) * LDA + j]) = b;
+                }
+            }
+        }
+        f32x16 gacc[NBW];
+#pragma unroll
+        for (int b = 0; b < NBW; ++b)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) gacc[b][v] = 0.f;
+        float db[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int t = t0; t < t1; ++t) {
+            const long i0 = (long)t * 32;
+            if (t > t0) __syncthreads();  // the previous tile's products are done
+#pragma unroll
+            for (int p = 0; p < PASSES; ++p) {
+                const int i = rr + RP * p;
+                const long idx = (i0 + i) * W + u0;
+                float A[4][4];
+                if (l == d) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const float gs = a.g[s * n_pad + i0 + i];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) A[s][q] = gs * wo[u0 + q];
+                    }
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const float4 ab = ld4(a.abar + s * plane + idx);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) A[s][q] = comp(ab, q);
+                    }
+                }
+                const float4 c0 = ld4(cl + idx), c1 = ld4(cl + plane + idx),
+                             c2 = ld4(cl + 2 * plane + idx), c3 = ld4(cl + 3 * plane + idx);
+                const float4 p0 = ld4(cp + idx), p1 = ld4(cp + plane + idx),
+                             p2 = ld4(cp + 2 * plane + idx), p3 = ld4(cp + 3 * plane + idx);
+                float zb[4][4], ap[4][4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    tanh_adjoint(A[0][q], A[1][q], A[2][q], A[3][q], comp(c0, q), comp(c1, q),
+                                 comp(c2, q), comp(c3, q), zb[0][q], zb[1][q], zb[2][q],
+                                 zb[3][q]);
+                    streams_of_values(comp(p0, q), comp(p1, q), comp(p2, q), comp(p3, q),
+                                      ap[0][q], ap[1][q], ap[2][q], ap[3][q]);
+                    db[q] += zb[0][q];
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    st_bf16x4(&Xs[s][i * LDA + u0], zb[s]);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        ZT[s][(u0 + q) * LDT + i] = (__bf16)zb[s][q];
+                        aT[s][(u0 + q) * LDT + i] = (__bf16)ap[s][q];
+                    }
+                }
+            }
+            __syncthreads();
+            // adjoints of the streams entering layer l: abar_s[i][k] = sum_j zbar_s[i][j] W[j][k]
+            for (int cb = wave; cb < NCB; cb += 4) {
+                f32x16 acc[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int v = 0; v < 16; ++v) acc[s][v] = 0.f;
+#pragma unroll
+                for (int k = 0; k < W / 16; ++k) {
+                    const bf16x8 b = lds_frag(&Wsh[(cb * 32 + r32) * LDA + 16 * k + 8 * h]);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        acc[s] = mfma32x32x16(lds_frag(&Xs[s][r32 * LDA + 16 * k + 8 * h]), b,
+                                              acc[s]);
+                }
+                const int kk = cb * 32 + r32;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const long idx = (i0 + mfma_row(v, lane)) * W + kk;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) a.abar[s * plane + idx] = acc[s][v];
+                }
+            }
+            // dW[j][k] += sum_s sum_i zbar_s[i][j] a_prev_s[i][k]
+#pragma unroll
+            for (int b = 0; b < NBW; ++b) {
+                const int blk = wave + 4 * b;
+                if (blk < NCB * NCB) {
+                    const int jb = blk / NCB, kb = blk - jb * NCB;
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+#pragma unroll
+                        for (int k = 0; k < 2; ++k)
+                            gacc[b] = mfma32x32x16(
+                                lds_frag(&ZT[s][(jb * 32 + r32) * LDT + 16 * k + 8 * h]),
+                                lds_frag(&aT[s][(kb * 32 + r32) * LDT + 16 * k + 8 * h]), gacc[b]);
+                }
+            }
+        }
 #pragma unroll
         for (int b = 0; b < NBW; ++b) {
             const int blk = wave + 4 * b;
-            if (blk < NBJ * NBJ) {
-                const int jb = blk / NBJ, kb = blk - jb * NBJ;
+            if (blk < NCB * NCB) {
+                const int jb = blk / NCB, kb = blk - jb * NCB;
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
-#pragma unroll
-                    for (int t = 0; t < 2; ++t)
-                        gacc[b] = mfma32x32x16(lds_frag(&ZT[s][(jb * 32 + r32) * LDT + 16 * t + 8 * h]),
-                                               lds_frag(&aT[s][(kb * 32 + r32) * LDT + 16 * t + 8 * h]),
-                                               gacc[b]);
+                for (int v = 0; v < 16; ++v)
+                    out[L.offW[l] + (long)(jb * 32 + mfma_row(v, lane)) * W + kb * 32 + r32] =
+                        gacc[b][v];
             }
         }
+        combine(db, out + L.offb[l], 1);
     }
-    float* out = part + (long)blockIdx.x * (W * W + W);
+
+    // ---- first layer: dW1[j][c] = sum_i zb_ij x_ic (+ zb_t for c = 0, + zb_x
+    // for c = 1), db1[j] = sum_i zb_ij, over the points i < n
+    {
+        const float* c1 = cache(1);
+        float gw[4][4], gb1[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int b = 0; b < NBW; ++b) {
-        const int blk = wave + 4 * b;
-        if (blk < NBJ * NBJ) {
-            const int jb = blk / NBJ, kb = blk - jb * NBJ;
+        for (int c = 0; c < 4; ++c)
 #pragma unroll
-            for (int v = 0; v < 16; ++v)
-                out[(jb * 32 + mfma_row(v, lane)) * W + kb * 32 + r32] = gacc[b][v];
-        }
+            for (int q = 0; q < 4; ++q) gw[c][q] = 0.f;
+        __syncthreads();  // the data adjoints of the last layer are written
+        for (int t = t0; t < t1; ++t)
+#pragma unroll
+            for (int p = 0; p < PASSES; ++p) {
+                const long i = (long)t * 32 + rr + RP * p;
+                if (i >= n) continue;
+                const long idx = i * W + u0;
+                float A[4][4];
+                if (d == 1) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const float gs = a.g[s * n_pad + i];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) A[s][q] = gs * wo[u0 + q];
+                    }
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const float4 ab = ld4(a.abar + s * plane + idx);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) A[s][q] = comp(ab, q);
+                    }
+                }
+                const float4 c0 = ld4(c1 + idx), cz1 = ld4(c1 + plane + idx),
+                             c2 = ld4(c1 + 2 * plane + idx), c3 = ld4(c1 + 3 * plane + idx);
+                const float* xr = point_row(a.P, i);
+                float x[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) x[c] = c < n_in ? xr[c] : 0.f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float zb, zb_t, zb_x, zb_xx;
+                    tanh_adjoint(A[0][q], A[1][q], A[2][q], A[3][q], comp(c0, q), comp(cz1, q),
+                                 comp(c2, q), comp(c3, q), zb, zb_t, zb_x, zb_xx);
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        if (c < n_in) {
+                            float tq = zb * x[c];
+                            if (c == 0) tq += zb_t;
+                            if (c == 1) tq += zb_x;
+                            gw[c][q] += tq;
+                        }
+                    gb1[q] += zb;
+                }
+            }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c < n_in) combine(gw[c], out + L.offW[1] + c, n_in);
+        combine(gb1, out + L.offb[1], 1);
     }
-    if (tid < W) out[W * W + tid] = gb;
 }
 
-// grad[x] = sum over blocks b of part[b][x], x < count.  A block takes 32
-// consecutive x; its 8 row groups sum the partials b = g, g + 8, ... (four
-// running sums each, so the loads overlap), then the groups are added in
-// order: a fixed summation order for every x, independent of timing.
+// grad[x] = sum over blocks b of part[b][x] for x < total, and loss3[t] =
+// (sum over blocks of part[b][total + t]) / (points of type t).  A block
+// takes 32 consecutive x; its 8 row groups sum the partials b = g, g + 8, ...
+// (four running sums each, so the loads overlap), then the groups are added
+// in order: a fixed summation order, independent of timing.
+__global__ __launch_bounds__(256) void k_res_reduce_step(const float* __restrict__ part, int nblk,
+                                                         long ldp, long total, int nf, int ne,
+                                                         int nb, float* __restrict__ grad,
+                                                         float* __restrict__ loss3) {
+    __shared__ float acc[8][33];
+    const int tx = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const long x = (long)blockIdx.x * 32 + tx, count = total + 3;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    if (x < count) {
+        int b = g;
+        for (; b + 24 < nblk; b += 32) {
+            s0 += part[(long)b * ldp + x];
+            s1 += part[(long)(b + 8) * ldp + x];
+            s2 += part[(long)(b + 16) * ldp + x];
+            s3 += part[(long)(b + 24) * ldp + x];
+        }
+        for (; b < nblk; b += 8) s0 += part[(long)b * ldp + x];
+    }
+    acc[g][tx] = (s0 + s1) + (s2 + s3);
+    __syncthreads();
+    if (g == 0 && x < count) {
+        float s = acc[0][tx];
+#pragma unroll
+        for (int r = 1; r < 8; ++r) s += acc[r][tx];
+        if (x < total) {
+            grad[x] = s;
+        } else {
+            const int t = (int)(x - total);
+            const int cnt = t == 0 ? nf : t == 1 ? ne : nb;
+            loss3[t] = cnt > 0 ? s / (float)cnt : 0.f;
+        }
+    }
+}
+
+// grad[x] = sum over blocks b of part[b][x], x < count (row stride count),
+// in the same fixed order; used by the float32 pass.
 __global__ __launch_bounds__(256) void k_res_reduce(const float* __restrict__ part, int nblk,
                                                     int count, float* __restrict__ grad) {
     __shared__ float acc[8][33];
@@ -216,45 +553,52 @@ int launch_res_reduce(const float* part, int nblk, int count, float* out, hipStr
     return BS_OK;
 }
 
-int launch_res_gemm_bf16(int which, const float* Wl, const float* bl, const float* cin,
-                         float* cout_or_abar, const float* zbar, long n, long n_pad, int W,
-                         float* gW, float* gb, float* part, hipStream_t st) {
-    (void)n;
-    const int ntiles = (int)(n_pad / 32);
-    if (which == 0) {
-        switch (W) {
+// Blocks of the fused step for n_pad points: at least kResStepMinTiles
+// tiles per block, at most max_blocks blocks.
+int res_step_blocks(long n_pad, int max_blocks, int* tiles_per_block) {
+    const long ntiles = n_pad / 32;
+    long tpb = (ntiles + max_blocks - 1) / max_blocks;
+    if (tpb < kResStepMinTiles) tpb = kResStepMinTiles;
+    *tiles_per_block = (int)tpb;
+    return (int)((ntiles + tpb - 1) / tpb);
+}
+
+int launch_res_step_bf16(const pinn_net& net, const Points& P, long n, long n_pad, float* cache,
+                         float* abar, float* g, float* part, long ldp, int max_blocks, float* grad,
+                         float* loss3, hipStream_t st) {
+    ResStepArgs a{};
+    a.prm = net.params;
+    a.P = P;
+    a.L = net_layout(net);
+    a.n = n;
+    a.n_pad = n_pad;
+    a.ntiles = (int)(n_pad / 32);
+    const int nblk = res_step_blocks(n_pad, max_blocks, &a.tiles_per_block);
+    a.cache = cache;
+    a.abar = abar;
+    a.g = g;
+    a.part = part;
+    a.ldp = ldp;
+    if (net.width != 32 && net.width != 64 && net.width != 128) {
+        set_error("bfloat16 residual path: width %d not supported (32, 64, 128)", net.width);
+        return BS_ERR_ARG;
+    }
+    if (nblk > 0) {
+        switch (net.width) {
 #define BSP_W(W_)                                                                             \
     case W_:                                                                                  \
-        hipLaunchKernelGGL(k_res_fwd_bf16<W_>, dim3(ntiles), dim3(256), 0, st, Wl, bl, cin,  \
-                           cout_or_abar, n_pad);                                              \
+        hipLaunchKernelGGL(k_res_step_bf16<W_>, dim3(nblk), dim3(kResStepThreads), 0, st, a); \
         break;
             BSP_W(32) BSP_W(64) BSP_W(128)
 #undef BSP_W
-        default:
-            set_error("bfloat16 residual path: width %d not supported (32, 64, 128)", W);
-            return BS_ERR_ARG;
         }
         BSP_LAUNCHED();
-        return BS_OK;
     }
-    const int nblk = ntiles < kResPartBlocksMfma ? ntiles : kResPartBlocksMfma;
-    switch (W) {
-#define BSP_W(W_)                                                                                \
-    case W_:                                                                                     \
-        hipLaunchKernelGGL(k_res_bwd_bf16<W_>, dim3(nblk), dim3(256), 0, st, Wl, zbar, cin,     \
-                           cout_or_abar, n_pad, ntiles, part);                                   \
-        break;
-        BSP_W(32) BSP_W(64) BSP_W(128)
-#undef BSP_W
-    default:
-        set_error("bfloat16 residual path: width %d not supported (32, 64, 128)", W);
-        return BS_ERR_ARG;
-    }
+    const long count = a.L.total + 3;
+    hipLaunchKernelGGL(k_res_reduce_step, dim3((unsigned)((count + 31) / 32)), dim3(256), 0, st,
+                       part, nblk, ldp, a.L.total, P.nf, P.ne, P.nb, grad, loss3);
     BSP_LAUNCHED();
-    const int count = W * W + W;
-    // dW and db are contiguous in the parameter packing (W_l then b_l)
-    (void)gb;
-    return launch_res_reduce(part, nblk, count, gW, st);
+    return BS_OK;
 }
 
 }  // namespace bsp

@@ -199,3 +199,67 @@ def test_value_targets_equal_to_conditions_change_nothing():
     ga = mlp.loss_grad(th, X_f, X_e, X_b, n_in, depth, width, True, 0.2, 0.05)
     gb = mlp.loss_grad(th, X_f, X_e, X_b, n_in, depth, width, True, 0.2, 0.05, y_e=y_e, y_b=y_b)
     assert np.array_equal(ga, gb)
+
+
+def test_bf16_round_vs_torch():
+    """bf16_round against torch's float32 -> bfloat16 conversion, on spread
+    values and on exact ties and their neighbours (ties go to even)."""
+    rng = np.random.default_rng(3)
+    x = (rng.normal(size=4000) * 10.0 ** rng.integers(-8, 8, size=4000)).astype(np.float32)
+    u = rng.normal(size=2000).astype(np.float32).view(np.uint32) & np.uint32(0xFFFF0000)
+    near = np.concatenate([u | np.uint32(0x8000), u | np.uint32(0x7FFF), u | np.uint32(0x8001),
+                           u | np.uint32(0x18000)]).view(np.float32)
+    for v in (x, near, np.array([0.0, -0.0, 1.0, -3.5], dtype=np.float32)):
+        ref = torch.tensor(v).to(torch.bfloat16).to(torch.float64).numpy()
+        assert np.array_equal(mlp.bf16_round(v), ref)
+    assert np.array_equal(mlp.bf16_round(x.astype(np.float64)), mlp.bf16_round(x))
+
+
+@pytest.mark.parametrize("n_in,depth,width", CASES)
+def test_loss_grad_with_loss_matches_loss3(n_in, depth, width):
+    th = _theta(n_in, depth, width)
+    box = ((0.1, 0.5), (0.0, 0.1)) if n_in == 4 else None
+    Xf, Xe, Xb = collocation(50, 9, 7, 1.0, 3.0, seed=4, coeff_box=box)
+    kw = dict(is_put=True, sigma=None if n_in == 4 else 0.3, r=None if n_in == 4 else 0.04)
+    l3 = mlp.loss3(th, Xf, Xe, Xb, n_in, depth, width, **kw)
+    l, g = mlp.loss_grad(th, Xf, Xe, Xb, n_in, depth, width, with_loss=True, **kw)
+    np.testing.assert_allclose(l, l3, rtol=1e-12, atol=1e-300)
+    assert np.array_equal(g, mlp.loss_grad(th, Xf, Xe, Xb, n_in, depth, width, **kw))
+    ident = mlp.loss_grad(th, Xf, Xe, Xb, n_in, depth, width, operand_round=lambda a: a, **kw)
+    assert np.array_equal(g, ident)
+
+
+def test_operand_rounding_only_in_hidden_products():
+    """bf16 operand rounding touches the hidden-layer products only: a
+    one-layer network (no such product) is unchanged bitwise; on a deeper one
+    the value-set losses equal those of a float64 torch forward whose hidden
+    products take operands rounded by torch's own bfloat16 conversion, and
+    the gradient moves by no more than bfloat16 rounding allows."""
+    Xf, Xe, Xb = collocation(40, 30, 20, 1.0, 3.0, seed=8)
+    kw = dict(is_put=False, sigma=0.25, r=0.05)
+    th1 = _theta(2, 1, 16)
+    exact1 = mlp.loss_grad(th1, Xf, Xe, Xb, 2, 1, 16, with_loss=True, **kw)
+    rnd1 = mlp.loss_grad(th1, Xf, Xe, Xb, 2, 1, 16, with_loss=True, operand_round=mlp.bf16_round,
+                         **kw)
+    assert exact1[0] == rnd1[0] and np.array_equal(exact1[1], rnd1[1])
+
+    n_in, depth, width = 2, 3, 32
+    th = _theta(n_in, depth, width)
+    (l_r, g_r) = mlp.loss_grad(th, Xf, Xe, Xb, n_in, depth, width, with_loss=True,
+                               operand_round=mlp.bf16_round, **kw)
+    rt = lambda t: t.to(torch.float32).to(torch.bfloat16).to(torch.float64)  # noqa: E731
+    layers = mlp.unpack(th, n_in, depth, width)
+
+    def value(X):
+        a = torch.tanh(torch.tensor(X) @ torch.tensor(layers[0][0]).T + torch.tensor(layers[0][1]))
+        for W, b in layers[1:-1]:
+            a = torch.tanh(rt(a) @ rt(torch.tensor(W)).T + torch.tensor(b))
+        Wo, bo = layers[-1]
+        return (a @ torch.tensor(Wo).T + torch.tensor(bo))[:, 0].numpy()
+
+    ye, yb = mlp.terminal_target(Xe, False), mlp.boundary_target(Xb, False, 0.05)
+    assert abs(l_r[1] - np.mean((value(Xe) - ye) ** 2)) <= 1e-13 * l_r[1]
+    assert abs(l_r[2] - np.mean((value(Xb) - yb) ** 2)) <= 1e-13 * l_r[2]
+    g = mlp.loss_grad(th, Xf, Xe, Xb, n_in, depth, width, **kw)
+    dev = np.max(np.abs(g_r - g)) / np.max(np.abs(g))
+    assert 0.0 < dev <= 5e-2

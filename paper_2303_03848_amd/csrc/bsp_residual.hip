@@ -42,6 +42,7 @@ struct ResWs {
     float* g;       // 4 * n_pad
     float* lossc;   // n_pad
     float* part;    // partial gradients: kPartRows rows of total + 3 floats
+    __bf16* wbf;    // hidden-layer weights in bfloat16, row-major then transposed
     size_t bytes;
 };
 
@@ -67,6 +68,7 @@ static ResWs res_layout(const pinn_net& n, long npts, void* base) {
     w.g = (float*)take(sizeof(float) * 4 * w.n_pad);
     w.lossc = (float*)take(sizeof(float) * w.n_pad);
     w.part = (float*)take(sizeof(float) * (size_t)kPartRows * (net_layout(n).total + 3));
+    w.wbf = (__bf16*)take(sizeof(__bf16) * 2 * (size_t)(n.depth - 1) * n.width * n.width);
     w.bytes = off;
     return w;
 }
@@ -494,8 +496,8 @@ __global__ void k_res_grad_out(const float* __restrict__ g, const float* __restr
 int launch_res_reduce(const float* part, int nblk, int count, float* out, hipStream_t st);
 
 int launch_res_step_bf16(const pinn_net& net, const Points& P, long n, long n_pad, float* cache,
-                         float* abar, float* g, float* part, long ldp, int max_blocks, float* grad,
-                         float* loss3, hipStream_t st);
+                         float* abar, float* g, __bf16* wbf, float* part, long ldp, int max_blocks,
+                         float* grad, float* loss3, hipStream_t st);
 
 static dim3 grid_for(long work, int block) { return dim3((unsigned)((work + block - 1) / block)); }
 
@@ -547,8 +549,8 @@ extern "C" int pinn_residual_fwd_bwd(const pinn_net* net, const bs_params* prm, 
         // the whole pass in one launch, then the reduction of its partial rows
         BSP_CHECK_ARG(((uintptr_t)P0 & 15) == 0 && ((uintptr_t)ws & 15) == 0,
                       "the bfloat16 residual path needs 16-byte aligned parameters and workspace");
-        return launch_res_step_bf16(*net, P, n, np, w.cache, w.abar, w.g, w.part, L.total + 3,
-                                    kPartRows, grad, loss3, st);
+        return launch_res_step_bf16(*net, P, n, np, w.cache, w.abar, w.g, w.wbf, w.part,
+                                    L.total + 3, kPartRows, grad, loss3, st);
     }
     auto cache = [&](int l) { return w.cache + (size_t)(l - 1) * 4 * plane; };
 

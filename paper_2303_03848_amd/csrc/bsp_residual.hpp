@@ -89,13 +89,13 @@ __device__ __forceinline__ void tanh_adjoint(float A, float At, float Ax, float 
               2.0f * zx * zx * (1.0f - 3.0f * a * a) * Axx);
 }
 
-// Head of one point i < n: given v (bias included) and its derivative
-// streams, the output adjoints g0..g3 of (v, v_t, v_x, v_xx) and the
-// point's squared loss term lc.
-__device__ __forceinline__ void head_point(const Points& P, long i, float v, float vt, float vx,
-                                           float vxx, float& g0, float& g1, float& g2,
-                                           float& g3, float& lc) {
-    const float* x = point_row(P, i);
+// Head of one point i < n with inputs x and value target y (used by terminal
+// and boundary points when the caller gives targets): given v (bias
+// included) and its derivative streams, the output adjoints g0..g3 of
+// (v, v_t, v_x, v_xx) and the point's squared loss term lc.
+__device__ __forceinline__ void head_point_x(const Points& P, long i, const float* x, float ytgt,
+                                             float v, float vt, float vx, float vxx, float& g0,
+                                             float& g1, float& g2, float& g3, float& lc) {
     const float sig = P.n_in == 4 ? x[2] : P.sigma;
     const float rr = P.n_in == 4 ? x[3] : P.r;
     g0 = g1 = g2 = g3 = 0.f;
@@ -110,7 +110,7 @@ __device__ __forceinline__ void head_point(const Points& P, long i, float v, flo
         g3 = -0.5f * sig * sig * xx * xx * df;
     } else if (i < P.nf + P.ne) {
         const float xx = x[1];
-        const float y = P.ye ? P.ye[i - P.nf]
+        const float y = P.ye ? ytgt
                              : (P.is_put ? fmaxf(1.0f - xx, 0.0f) : fmaxf(xx - 1.0f, 0.0f));
         lc = (v - y) * (v - y);
         g0 = 2.0f * (v - y) / (float)P.ne;
@@ -118,11 +118,24 @@ __device__ __forceinline__ void head_point(const Points& P, long i, float v, flo
         const float tau = x[0], xx = x[1];
         const float disc = expf(-rr * tau);
         const bool lower = xx == 0.0f;
-        const float y = P.yb ? P.yb[i - P.nf - P.ne]
+        const float y = P.yb ? ytgt
                              : (P.is_put ? (lower ? disc : 0.0f) : (lower ? 0.0f : xx - disc));
         lc = (v - y) * (v - y);
         g0 = 2.0f * (v - y) / (float)P.nb;
     }
+}
+
+// The value target of point i (its terminal or boundary target when given, else 0).
+__device__ __forceinline__ float point_target(const Points& P, long i) {
+    if (i >= P.nf && i < P.nf + P.ne) return P.ye ? P.ye[i - P.nf] : 0.f;
+    if (i >= P.nf + P.ne) return P.yb ? P.yb[i - P.nf - P.ne] : 0.f;
+    return 0.f;
+}
+
+__device__ __forceinline__ void head_point(const Points& P, long i, float v, float vt, float vx,
+                                           float vxx, float& g0, float& g1, float& g2,
+                                           float& g3, float& lc) {
+    head_point_x(P, i, point_row(P, i), point_target(P, i), v, vt, vx, vxx, g0, g1, g2, g3, lc);
 }
 
 }  // namespace bsp

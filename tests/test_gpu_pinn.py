@@ -152,13 +152,15 @@ BF16_TOL = 1e-3
 
 BF16_CASES = [(2, 4, 64, 1000, 100, 50), (2, 4, 128, 1000, 100, 50), (4, 4, 128, 257, 31, 17),
               (2, 3, 32, 1000, 100, 50), (2, 1, 64, 50, 7, 0), (2, 2, 32, 1, 0, 0),
-              (2, 2, 64, 0, 40, 9), (2, 4, 128, 20000, 600, 300)]
+              (2, 2, 64, 0, 40, 9), (2, 4, 128, 20000, 600, 300), (2, 6, 64, 700, 50, 30),
+              (4, 5, 128, 300, 20, 20), (2, 3, 128, 33, 1, 1)]
 
 
 @pytest.mark.parametrize("n_in,depth,width,nf,ne,nb", BF16_CASES)
 def test_residual_bf16(n_in, depth, width, nf, ne, nb):
     """The fused bfloat16 step: single points, empty sets, ragged tiles, one
-    hidden layer or none, and 654 tiles (three per block)."""
+    hidden layer or none, 654 tiles (three per block), and networks of 5 and
+    6 layers (the kernel with the caches in the point-major workspace)."""
     cuda()
     th = _theta(n_in, depth, width)
     Xf, Xe, Xb = _points(nf, ne, nb, n_in)

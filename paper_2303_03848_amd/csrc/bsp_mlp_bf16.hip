@@ -6,8 +6,10 @@
 // One block of 4 wavefronts (8 for width 256) takes P = 128 points through
 // every layer without leaving the CU: activations ping-pong between two LDS
 // tiles [P][W] (bf16).
-// Each wavefront owns 32-unit column blocks of a layer's output and all P/32
-// row tiles; a weight fragment (8 consecutive inputs of one unit) is read
+// Each wavefront owns 32-unit blocks of a layer's output and all P/32 point
+// tiles; the products are taken as [unit][point] (weights as the first
+// operand), so each lane ends with four consecutive units of one point and
+// stores them together.  A weight fragment (8 consecutive inputs of one unit) is read
 // from global memory (the layer stays in L2), converted to bf16 in
 // registers and used for all row tiles before the next one, so weights are
 // neither staged in LDS nor re-read per 32 points; the fragments are loaded
@@ -18,6 +20,8 @@
 #include "bsp_net.hpp"
 
 namespace bsp {
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMlpPoints = 128;  // points per block
 
@@ -101,17 +105,25 @@ __global__ __launch_bounds__(64 * mlp_waves<W>()) void k_mlp_bf16(const float* _
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
                     const bf16x8 a = lds_frag(&act[cur][(mt * 32 + r32) * LDA + 16 * t + 8 * h]);
-                    acc[mt] = mfma32x32x16(a, bb, acc[mt]);
+                    acc[mt] = mfma32x32x16(bb, a, acc[mt]);  // [unit][point]
                 }
             }
-            const int j = cb * 32 + r32;
-            const float bj = bl[j];
+            // this lane: point mt*32 + r32, units cb*32 + 8 (v >> 2) + 4 h + (v & 3):
+            // four consecutive units of one point per 8-byte store
+            float bj[16];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) bj[v] = bl[cb * 32 + mfma_row(v, lane)];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                for (int v = 0; v < 16; ++v)
-                    act[cur ^ 1][(mt * 32 + mfma_row(v, lane)) * LDA + j] =
-                        (__bf16)tanh_bf16_act(acc[mt][v] + bj);
+                for (int m = 0; m < 4; ++m) {
+                    bf16x4 q;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        q[e] = (__bf16)tanh_bf16_act(acc[mt][4 * m + e] + bj[4 * m + e]);
+                    *reinterpret_cast<bf16x4*>(
+                        &act[cur ^ 1][(mt * 32 + r32) * LDA + cb * 32 + 8 * m + 4 * h]) = q;
+                }
         }
         cur ^= 1;
         off += (long)W * W + W;

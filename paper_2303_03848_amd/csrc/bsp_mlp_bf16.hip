@@ -3,9 +3,11 @@
 // of the network coarse propagator).  tanh is evaluated through the
 // exponential (tanh_bf16_act): the activations are rounded to bfloat16.
 //
-// One block of 4 wavefronts (8 for width 256) takes P = 128 points through
-// every layer without leaving the CU: activations ping-pong between two LDS
-// tiles [P][W] (bf16).
+// One block of 4 wavefronts (8 for width 256) takes P = 256 points through
+// every layer without leaving the CU: the activations [P][W] (bf16) sit in
+// one LDS tile; a layer's products go to registers, and after a barrier its
+// outputs overwrite its inputs (a second tile would halve P, and every block
+// reads the weights once per layer, so points per block set the L2 traffic).
 // Each wavefront owns 32-unit blocks of a layer's output and all P/32 point
 // tiles; the products are taken as [unit][point] (weights as the first
 // operand), so each lane ends with four consecutive units of one point and
@@ -23,7 +25,7 @@ namespace bsp {
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMlpPoints = 128;  // points per block
+constexpr int kMlpPoints = 256;  // points per block
 
 // Wavefronts per block: 8 for the widest layers, so that two wavefronts share
 // each SIMD and one's tanh epilogue overlaps the other's matrix products.
@@ -41,7 +43,7 @@ __global__ __launch_bounds__(64 * mlp_waves<W>()) void k_mlp_bf16(const float* _
     constexpr int LDA = W + 8;                  // row stride of the activation tiles (bf16)
     constexpr int NW = mlp_waves<W>(), NT = 64 * NW;
     constexpr int NB = W >= 32 * NW ? W / (32 * NW) : 1;  // output column blocks per wavefront
-    __shared__ __align__(16) __bf16 act[2][P * LDA];
+    __shared__ __align__(16) __bf16 act[P * LDA];
     __shared__ float xin[P][4];
     __shared__ int ok[P];
 
@@ -61,71 +63,74 @@ __global__ __launch_bounds__(64 * mlp_waves<W>()) void k_mlp_bf16(const float* _
         const int i = e / W, j = e - i * W;
         float z = prm[W * n_in + j];
         for (int c = 0; c < n_in; ++c) z = fmaf(prm[j * n_in + c], xin[i][c], z);
-        act[0][i * LDA + j] = (__bf16)tanh_bf16_act(z);
+        act[i * LDA + j] = (__bf16)tanh_bf16_act(z);
     }
     long off = (long)W * n_in + W;
-    int cur = 0;
     for (int l = 2; l <= depth; ++l) {
         const float* Wl = prm + off;
         const float* bl = Wl + (long)W * W;
-        __syncthreads();  // act[cur] complete
+        __syncthreads();  // the layer's input complete
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int cb = wave + NW * b;
-            if (cb * 32 >= W) continue;
+            const bool active = cb * 32 < W;  // (narrow layers leave wavefronts idle)
             f32x16 acc[MT];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int v = 0; v < 16; ++v) acc[mt][v] = 0.f;
-            // unit j = cb*32 + r32; this lane's inputs 16 t + 8 h .. + 7.
-            // The weight fragments are loaded PD K-steps ahead of their use
-            // (a ring of registers): with one wavefront per SIMD nothing else
-            // hides the L2 latency.
-            const float* wrow = Wl + (long)(cb * 32 + r32) * W + 8 * h;
-            constexpr int KT = W / 16, PD = KT < 8 ? KT : 8;
-            float4 wr0[PD], wr1[PD];
+            if (active) {
+                // unit j = cb*32 + r32; this lane's inputs 16 t + 8 h .. + 7.
+                // The weight fragments are loaded PD K-steps ahead of their use
+                // (a ring of registers): with one wavefront per SIMD nothing else
+                // hides the L2 latency.
+                const float* wrow = Wl + (long)(cb * 32 + r32) * W + 8 * h;
+                constexpr int KT = W / 16, PD = KT < 8 ? KT : 8;
+                float4 wr0[PD], wr1[PD];
 #pragma unroll
-            for (int t = 0; t < PD; ++t) {
-                wr0[t] = *reinterpret_cast<const float4*>(wrow + 16 * t);
-                wr1[t] = *reinterpret_cast<const float4*>(wrow + 16 * t + 4);
+                for (int t = 0; t < PD; ++t) {
+                    wr0[t] = *reinterpret_cast<const float4*>(wrow + 16 * t);
+                    wr1[t] = *reinterpret_cast<const float4*>(wrow + 16 * t + 4);
+                }
+#pragma unroll
+                for (int t = 0; t < KT; ++t) {
+                    const float4 w0 = wr0[t % PD];
+                    const float4 w1 = wr1[t % PD];
+                    if (t + PD < KT) {
+                        wr0[t % PD] = *reinterpret_cast<const float4*>(wrow + 16 * (t + PD));
+                        wr1[t % PD] = *reinterpret_cast<const float4*>(wrow + 16 * (t + PD) + 4);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    bf16x8 bb;
+                    bb[0] = (__bf16)w0.x; bb[1] = (__bf16)w0.y; bb[2] = (__bf16)w0.z; bb[3] = (__bf16)w0.w;
+                    bb[4] = (__bf16)w1.x; bb[5] = (__bf16)w1.y; bb[6] = (__bf16)w1.z; bb[7] = (__bf16)w1.w;
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt) {
+                        const bf16x8 a = lds_frag(&act[(mt * 32 + r32) * LDA + 16 * t + 8 * h]);
+                        acc[mt] = mfma32x32x16(bb, a, acc[mt]);  // [unit][point]
+                    }
+                }
             }
+            __syncthreads();  // every wavefront is done reading the layer's input
+            if (active) {
+                // this lane: point mt*32 + r32, units cb*32 + 8 (v >> 2) + 4 h + (v & 3):
+                // four consecutive units of one point per 8-byte store
+                float bj[16];
 #pragma unroll
-            for (int t = 0; t < KT; ++t) {
-                const float4 w0 = wr0[t % PD];
-                const float4 w1 = wr1[t % PD];
-                if (t + PD < KT) {
-                    wr0[t % PD] = *reinterpret_cast<const float4*>(wrow + 16 * (t + PD));
-                    wr1[t % PD] = *reinterpret_cast<const float4*>(wrow + 16 * (t + PD) + 4);
-                }
-                __builtin_amdgcn_sched_barrier(0);
-                bf16x8 bb;
-                bb[0] = (__bf16)w0.x; bb[1] = (__bf16)w0.y; bb[2] = (__bf16)w0.z; bb[3] = (__bf16)w0.w;
-                bb[4] = (__bf16)w1.x; bb[5] = (__bf16)w1.y; bb[6] = (__bf16)w1.z; bb[7] = (__bf16)w1.w;
+                for (int v = 0; v < 16; ++v) bj[v] = bl[cb * 32 + mfma_row(v, lane)];
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) {
-                    const bf16x8 a = lds_frag(&act[cur][(mt * 32 + r32) * LDA + 16 * t + 8 * h]);
-                    acc[mt] = mfma32x32x16(bb, a, acc[mt]);  // [unit][point]
-                }
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        bf16x4 q;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            q[e] = (__bf16)tanh_bf16_act(acc[mt][4 * m + e] + bj[4 * m + e]);
+                        *reinterpret_cast<bf16x4*>(
+                            &act[(mt * 32 + r32) * LDA + cb * 32 + 8 * m + 4 * h]) = q;
+                    }
             }
-            // this lane: point mt*32 + r32, units cb*32 + 8 (v >> 2) + 4 h + (v & 3):
-            // four consecutive units of one point per 8-byte store
-            float bj[16];
-#pragma unroll
-            for (int v = 0; v < 16; ++v) bj[v] = bl[cb * 32 + mfma_row(v, lane)];
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    bf16x4 q;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        q[e] = (__bf16)tanh_bf16_act(acc[mt][4 * m + e] + bj[4 * m + e]);
-                    *reinterpret_cast<bf16x4*>(
-                        &act[cur ^ 1][(mt * 32 + r32) * LDA + cb * 32 + 8 * m + 4 * h]) = q;
-                }
         }
-        cur ^= 1;
         off += (long)W * W + W;
     }
     __syncthreads();
@@ -133,7 +138,7 @@ __global__ __launch_bounds__(64 * mlp_waves<W>()) void k_mlp_bf16(const float* _
     const int part = tid & 7;
     for (int i = tid >> 3; i < P; i += NT / 8) {
         float s = 0.f;
-        for (int j = part; j < W; j += 8) s = fmaf(prm[off + j], (float)act[cur][i * LDA + j], s);
+        for (int j = part; j < W; j += 8) s = fmaf(prm[off + j], (float)act[i * LDA + j], s);
         s += __shfl_xor(s, 1);
         s += __shfl_xor(s, 2);
         s += __shfl_xor(s, 4);

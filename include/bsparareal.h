@@ -172,7 +172,12 @@ int pinn_residual_workspace_size(const pinn_net* net, int n_f, int n_e, int n_b,
  * Outputs (device, float32): loss3[3] = (MSE_f, MSE_exp, MSE_b); grad[n_params]
  * = d(MSE_f + MSE_exp + MSE_b)/d params, packed like net->params.
  * ws: device workspace of pinn_residual_workspace_size() bytes.
- * n_f, n_e, n_b >= 0; an empty set contributes 0 to loss and gradient. */
+ * n_f, n_e, n_b >= 0; an empty set contributes 0 to loss and gradient.
+ * The sums over points run in a fixed order: the result is the same from
+ * call to call.  Precision BS_PREC_BF16 (width 32, 64 or 128): the whole pass
+ * is one launch plus a reduction, the hidden-layer products take bfloat16
+ * operands (everything else float32); params and ws must then be 16-byte
+ * aligned (BS_ERR_ARG otherwise).  BS_ERR_WORKSPACE if ws_bytes is too small. */
 int pinn_residual_fwd_bwd(const pinn_net* net, const bs_params* prm, int n_f, const float* X_f,
                           int n_e, const float* X_e, const float* y_e, int n_b, const float* X_b,
                           const float* y_b, float* loss3, float* grad, void* ws, size_t ws_bytes,

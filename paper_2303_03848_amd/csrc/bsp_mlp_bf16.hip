@@ -59,11 +59,22 @@ __global__ __launch_bounds__(64 * mlp_waves<W>()) void k_mlp_bf16(const float* _
         for (int c = 0; c < 4; ++c) xin[t][c] = x[c];
     }
     __syncthreads();
-    for (int e = tid; e < P * W; e += NT) {
-        const int i = e / W, j = e - i * W;
-        float z = prm[W * n_in + j];
-        for (int c = 0; c < n_in; ++c) z = fmaf(prm[j * n_in + c], xin[i][c], z);
-        act[i * LDA + j] = (__bf16)tanh_bf16_act(z);
+    {
+        // first layer: NT is a multiple of W, so a thread keeps one unit j
+        // (its weights in registers) over the rows i0, i0 + NT/W, ...
+        static_assert(NT % W == 0, "the first layer keeps one unit per thread");
+        const int j = tid % W;
+        float wj[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) wj[c] = c < n_in ? prm[j * n_in + c] : 0.f;
+        const float bj = prm[W * n_in + j];
+        for (int i = tid / W; i < P; i += NT / W) {
+            float z = bj;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+                if (c < n_in) z = fmaf(wj[c], xin[i][c], z);
+            act[i * LDA + j] = (__bf16)tanh_bf16_act(z);
+        }
     }
     long off = (long)W * n_in + W;
     for (int l = 2; l <= depth; ++l) {
@@ -136,9 +147,13 @@ __global__ __launch_bounds__(64 * mlp_waves<W>()) void k_mlp_bf16(const float* _
     __syncthreads();
     // output layer: 8 threads per point, then a reduction over those 8 lanes
     const int part = tid & 7;
+    float wo[W / 8];  // this thread's output weights, units part, part + 8, ...
+#pragma unroll
+    for (int q = 0; q < W / 8; ++q) wo[q] = prm[off + part + 8 * q];
     for (int i = tid >> 3; i < P; i += NT / 8) {
         float s = 0.f;
-        for (int j = part; j < W; j += 8) s = fmaf(prm[off + j], (float)act[i * LDA + j], s);
+#pragma unroll
+        for (int q = 0; q < W / 8; ++q) s = fmaf(wo[q], (float)act[i * LDA + part + 8 * q], s);
         s += __shfl_xor(s, 1);
         s += __shfl_xor(s, 2);
         s += __shfl_xor(s, 4);

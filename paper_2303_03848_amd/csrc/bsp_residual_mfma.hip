@@ -5,17 +5,18 @@
 // Every step of the gradient is local to a point except the sums over
 // points, so one block takes a few 32-point tiles through the whole pass:
 //   first layer (vector units) -> hidden layers (one MFMA chain per
-//   derivative stream, weights staged in LDS once per layer and block) ->
-//   head (output layer, loss terms, output adjoints) -> backward through the
-//   hidden layers (data adjoints W^T zbar per tile, weight gradient
-//   sum_s zbar_s^T a_prev_s accumulated over the block's tiles in MFMA
-//   registers) -> first-layer gradient.
-// The per-layer caches (a, z_t, z_x, z_xx), the data adjoints and the output
-// adjoints go through the workspace (float32, written and read back by the
-// same block).  Each block writes one partial row: every parameter's
-// gradient over its points, then the three loss sums by point type;
-// k_res_reduce_step adds the rows in block order, so the result does not
-// depend on timing.
+//   derivative stream) -> head (output layer, loss terms, output adjoints)
+//   -> backward through the hidden layers (data adjoints W^T zbar per tile,
+//   weight gradient sum_s zbar_s^T a_prev_s) -> first-layer gradient.
+// Two kernels do this:
+//   k_res_tile_bf16 (networks of 2 to 4 layers): wavefront w owns 32 units of
+//     every layer and meets the adjoints in the matrix-core output layout;
+//     each lane's cache fragments go to the workspace in its own order.
+//   k_res_step_bf16 (any depth): point-major caches, adjoints and output
+//     adjoints in the workspace, the weights staged in LDS once per layer.
+// Each block writes one partial row: every parameter's gradient over its
+// points, then the three loss sums by point type; k_res_reduce_step adds the
+// rows in block order, so the result does not depend on timing.
 #include "bsp_residual.hpp"
 
 namespace bsp {
@@ -73,18 +74,6 @@ __device__ __forceinline__ void st_bf16x4(__bf16* p, const float (&v)[4]) {
 template <class T>
 __device__ __forceinline__ BSP_GLOBAL T* gmem(T* p) {
     return (BSP_GLOBAL T*)p;
-}
-
-// Hide the values of x from the optimiser: what was derived from them before
-// is not kept alive to be reused after (recomputing it is cheaper than
-// holding it in registers).
-__device__ __forceinline__ void opaque(f32x16& x) {
-#pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        float t = x[v];
-        asm volatile("" : "+v"(t));
-        x[v] = t;
-    }
 }
 
 __device__ __forceinline__ float comp(const float4& v, int q) {

@@ -107,14 +107,17 @@ __global__ __launch_bounds__(kResStepThreads) void k_res_step_bf16(ResStepArgs a
     const long n = a.n, n_pad = a.n_pad, plane = n_pad * W;
     const int t0 = blockIdx.x * a.tiles_per_block;
     const int t1 = min(t0 + a.tiles_per_block, a.ntiles);
-    const float* prm = a.prm;
-    const float* wo = prm + L.off_wo;
-    float* out = a.part + (long)blockIdx.x * a.ldp;
-    auto cache = [&](int l) { return a.cache + (long)(l - 1) * 4 * plane; };
+    // global-memory views (global_* rather than flat instructions)
+    const BSP_GLOBAL float* prm = gmem(a.prm);
+    const BSP_GLOBAL float* wo = prm + L.off_wo;
+    BSP_GLOBAL float* out = gmem(a.part) + (long)blockIdx.x * a.ldp;
+    BSP_GLOBAL float* const abar = gmem(a.abar);
+    BSP_GLOBAL float* const gout = gmem(a.g);
+    auto cache = [&](int l) { return gmem(a.cache) + (long)(l - 1) * 4 * plane; };
 
     // Per-thread partials acc[q] of unit u0 + q over rows rr + RP p, summed
     // over the RP row groups in order; unit u goes to dst[u * stride].
-    auto combine = [&](const float (&acc)[4], float* dst, int stride) {
+    auto combine = [&](const float (&acc)[4], BSP_GLOBAL float* dst, int stride) {
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 4; ++q) red[rr * W + u0 + q] = acc[q];
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(kResStepThreads) void k_res_step_bf16(ResStepArgs a
     };
 
     // The same for one unit per thread (unit tid % W, row group tid / W).
-    auto combine1 = [&](float acc, float* dst) {
+    auto combine1 = [&](float acc, BSP_GLOBAL float* dst) {
         __syncthreads();
         red[tid] = acc;
         __syncthreads();
@@ -148,7 +151,7 @@ __global__ __launch_bounds__(kResStepThreads) void k_res_step_bf16(ResStepArgs a
             for (int c = 0; c < 4; ++c)
                 w1[q][c] = c < n_in ? prm[L.offW[1] + (long)(u0 + q) * n_in + c] : 0.f;
         }
-        float* c1 = cache(1);
+        BSP_GLOBAL float* c1 = cache(1);
         for (int t = t0; t < t1; ++t)
 #pragma unroll
             for (int p = 0; p < PASSES; ++p) {
@@ -181,10 +184,10 @@ __global__ __launch_bounds__(kResStepThreads) void k_res_step_bf16(ResStepArgs a
 
     // ---- hidden layers: z_s = W a_s (+ b for the value), then the tanh streams
     for (int l = 2; l <= d; ++l) {
-        const float* Wl = prm + L.offW[l];
-        const float* bl = prm + L.offb[l];
-        const float* cp = cache(l - 1);
-        float* cn = cache(l);
+        const BSP_GLOBAL float* Wl = prm + L.offW[l];
+        const BSP_GLOBAL float* bl = prm + L.offb[l];
+        const BSP_GLOBAL float* cp = cache(l - 1);
+        BSP_GLOBAL float* cn = cache(l);
         __syncthreads();  // the previous layer's products are done with Wsh and Xs
 #pragma unroll
         for (int m = 0; m < (NG8 + NT - 1) / NT; ++m) {
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(kResStepThreads) void k_res_step_bf16(ResStepArgs a
 
     // ---- head: output layer, loss terms, output adjoints; output-layer gradient
     {
-        const float* cd = cache(d);
+        const BSP_GLOBAL float* cd = cache(d);
         float lsum[3] = {0.f, 0.f, 0.f}, dbo = 0.f;
         float dwo[4] = {0.f, 0.f, 0.f, 0.f};
         const int u = tid & 7, pt = tid >> 3;  // eight lanes per point
@@ -261,8 +264,10 @@ __global__ __launch_bounds__(kResStepThreads) void k_res_step_bf16(ResStepArgs a
 #pragma unroll
                 for (int jj = 0; jj < W / 8; ++jj) {
                     const int j = u + 8 * jj;
+                    const long ij = i * W + j;
                     float s0, s1, s2, s3;
-                    streams_from_cache(cd, plane, i * W + j, s0, s1, s2, s3);
+                    streams_of_values(cd[ij], cd[plane + ij], cd[2 * plane + ij],
+                                      cd[3 * plane + ij], s0, s1, s2, s3);
                     v = fmaf(wo[j], s0, v);
                     vt = fmaf(wo[j], s1, vt);
                     vx = fmaf(wo[j], s2, vx);
@@ -284,10 +289,10 @@ __global__ __launch_bounds__(kResStepThreads) void k_res_step_bf16(ResStepArgs a
                 gsh[2][pt] = g2;
                 gsh[3][pt] = g3;
                 lsh[pt] = lc;
-                a.g[i] = g0;
-                a.g[n_pad + i] = g1;
-                a.g[2 * n_pad + i] = g2;
-                a.g[3 * n_pad + i] = g3;
+                gout[i] = g0;
+                gout[n_pad + i] = g1;
+                gout[2 * n_pad + i] = g2;
+                gout[3 * n_pad + i] = g3;
             }
             __syncthreads();
             if (tid == 0)
@@ -327,9 +332,9 @@ __global__ __launch_bounds__(kResStepThreads) void k_res_step_bf16(ResStepArgs a
 
     // ---- backward through the hidden layers
     for (int l = d; l >= 2; --l) {
-        const float* Wl = prm + L.offW[l];
-        const float* cl = cache(l);
-        const float* cp = cache(l - 1);
+        const BSP_GLOBAL float* Wl = prm + L.offW[l];
+        const BSP_GLOBAL float* cl = cache(l);
+        const BSP_GLOBAL float* cp = cache(l - 1);
         __syncthreads();  // the head / the previous layer are done with Wsh, Xs, ZT, aT
         // Wsh[k][j] = W[j][k]: rows j, j + 1 read together, one 4-byte store per k
 #pragma unroll
@@ -373,7 +378,7 @@ __global__ __launch_bounds__(kResStepThreads) void k_res_step_bf16(ResStepArgs a
                     float A[4];
 #pragma unroll
                     for (int s = 0; s < 4; ++s)
-                        A[s] = l == d ? a.g[s * n_pad + i0 + i] * wou : a.abar[s * plane + idx];
+                        A[s] = l == d ? gout[s * n_pad + i0 + i] * wou : abar[s * plane + idx];
                     float zb[4];
                     tanh_adjoint(A[0], A[1], A[2], A[3], cl[idx], cl[plane + idx],
                                  cl[2 * plane + idx], cl[3 * plane + idx], zb[0], zb[1], zb[2],
@@ -414,7 +419,7 @@ __global__ __launch_bounds__(kResStepThreads) void k_res_step_bf16(ResStepArgs a
                 for (int v = 0; v < 16; ++v) {
                     const long idx = (i0 + mfma_row(v, lane)) * W + kk;
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) a.abar[s * plane + idx] = acc[s][v];
+                    for (int s = 0; s < 4; ++s) abar[s * plane + idx] = acc[s][v];
                 }
             }
             // dW[j][k] += sum_s sum_i zbar_s[i][j] a_prev_s[i][k]
@@ -450,7 +455,7 @@ __global__ __launch_bounds__(kResStepThreads) void k_res_step_bf16(ResStepArgs a
     // ---- first layer: dW1[j][c] = sum_i zb_ij x_ic (+ zb_t for c = 0, + zb_x
     // for c = 1), db1[j] = sum_i zb_ij, over the points i < n
     {
-        const float* c1 = cache(1);
+        const BSP_GLOBAL float* c1 = cache(1);
         float gw[4][4], gb1[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -467,14 +472,14 @@ __global__ __launch_bounds__(kResStepThreads) void k_res_step_bf16(ResStepArgs a
                 if (d == 1) {
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
-                        const float gs = a.g[s * n_pad + i];
+                        const float gs = gout[s * n_pad + i];
 #pragma unroll
                         for (int q = 0; q < 4; ++q) A[s][q] = gs * wo[u0 + q];
                     }
                 } else {
 #pragma unroll
                     for (int s = 0; s < 4; ++s) {
-                        const float4 ab = ld4(a.abar + s * plane + idx);
+                        const float4 ab = ld4(abar + s * plane + idx);
 #pragma unroll
                         for (int q = 0; q < 4; ++q) A[s][q] = comp(ab, q);
                     }

@@ -176,6 +176,31 @@ def test_residual_bf16(n_in, depth, width, nf, ne, nb):
     assert el <= BF16_TOL and eg <= BF16_TOL
 
 
+@pytest.mark.parametrize("depth", [4, 6])
+def test_residual_bf16_value_targets(depth):
+    """Given value targets on the terminal and boundary sets (both bfloat16
+    kernels: 4 and 6 layers), against the bfloat16-operand oracle."""
+    cuda()
+    th = _theta(2, depth, 64)
+    Xf, Xe, Xb = _points(500, 70, 45, 2)
+    rng = np.random.default_rng(21)
+    ye = rng.normal(0.2, 0.1, Xe.shape[0]).astype(np.float32)
+    yb = rng.normal(0.1, 0.1, Xb.shape[0]).astype(np.float32)
+    net = bsp.PinnNet(to_dev(th, torch.float32), 2, depth, 64, bsp.PREC_BF16)
+    l3, g = bsp.pinn_residual_fwd_bwd(net, CALL, to_dev(Xf, torch.float32),
+                                      to_dev(Xe, torch.float32), to_dev(Xb, torch.float32),
+                                      y_e=to_dev(ye, torch.float32), y_b=to_dev(yb, torch.float32))
+    l3, g = l3.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)  # noqa: E731
+    rl3, rg = mlp.loss_grad(f32(th), f32(Xf), f32(Xe), f32(Xb), 2, depth, 64, is_put=False,
+                            sigma=CALL["sigma"], r=CALL["r"], y_e=f32(ye), y_b=f32(yb),
+                            operand_round=mlp.bf16_round, with_loss=True)
+    el = np.max(np.abs(l3 - np.array(rl3)) / np.abs(np.array(rl3)))
+    eg = np.max(np.abs(g - rg)) / np.max(np.abs(rg))
+    say(f"bf16 residual with value targets, {depth} layers: loss {el:.2e}, grad {eg:.2e}")
+    assert el <= BF16_TOL and eg <= BF16_TOL
+
+
 def test_residual_bf16_full_training_batch():
     """The training-step workload at full size in bfloat16 (8192 / 512 / 256
     points, 128 x 4) against the bfloat16-operand oracle, and bitwise

@@ -513,30 +513,11 @@ __global__ __launch_bounds__(kResStepThreads) void k_res_step_bf16(ResStepArgs a
     }
 }
 
-// Column x of the partial rows summed over the rows b = g, g + 8, ... of
-// row group g: the loads of up to 24 rows go out together, then are added in
-// row order (a fixed order, so the result does not depend on timing).
-__device__ __forceinline__ float sum_rows(const float* __restrict__ part, int nblk, long ldp,
-                                          long x, int g) {
-    constexpr int R = 24;
-    float s = 0.f;
-    for (int b0 = g; b0 < nblk; b0 += 8 * R) {
-        float v[R];
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const int b = b0 + 8 * q;
-            v[q] = b < nblk ? part[(long)b * ldp + x] : 0.f;
-        }
-#pragma unroll
-        for (int q = 0; q < R; ++q) s += v[q];
-    }
-    return s;
-}
-
 // grad[x] = sum over blocks b of part[b][x] for x < total, and loss3[t] =
 // (sum over blocks of part[b][total + t]) / (points of type t).  A block
-// takes 32 consecutive x; its 8 row groups each sum every eighth row, then
-// the groups are added in order.
+// takes 32 consecutive x; its 8 row groups sum the partials b = g, g + 8, ...
+// (four running sums each, so the loads overlap), then the groups are added
+// in order: a fixed summation order, independent of timing.
 __global__ __launch_bounds__(256) void k_res_reduce_step(const float* __restrict__ part, int nblk,
                                                          long ldp, long total, int nf, int ne,
                                                          int nb, float* __restrict__ grad,
@@ -544,7 +525,18 @@ __global__ __launch_bounds__(256) void k_res_reduce_step(const float* __restrict
     __shared__ float acc[8][33];
     const int tx = threadIdx.x & 31, g = threadIdx.x >> 5;
     const long x = (long)blockIdx.x * 32 + tx, count = total + 3;
-    acc[g][tx] = x < count ? sum_rows(part, nblk, ldp, x, g) : 0.f;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    if (x < count) {
+        int b = g;
+        for (; b + 24 < nblk; b += 32) {
+            s0 += part[(long)b * ldp + x];
+            s1 += part[(long)(b + 8) * ldp + x];
+            s2 += part[(long)(b + 16) * ldp + x];
+            s3 += part[(long)(b + 24) * ldp + x];
+        }
+        for (; b < nblk; b += 8) s0 += part[(long)b * ldp + x];
+    }
+    acc[g][tx] = (s0 + s1) + (s2 + s3);
     __syncthreads();
     if (g == 0 && x < count) {
         float s = acc[0][tx];
@@ -567,7 +559,18 @@ __global__ __launch_bounds__(256) void k_res_reduce(const float* __restrict__ pa
     __shared__ float acc[8][33];
     const int tx = threadIdx.x & 31, g = threadIdx.x >> 5;
     const int x = blockIdx.x * 32 + tx;
-    acc[g][tx] = x < count ? sum_rows(part, nblk, count, x, g) : 0.f;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+    if (x < count) {
+        int b = g;
+        for (; b + 24 < nblk; b += 32) {
+            s0 += part[(long)b * count + x];
+            s1 += part[(long)(b + 8) * count + x];
+            s2 += part[(long)(b + 16) * count + x];
+            s3 += part[(long)(b + 24) * count + x];
+        }
+        for (; b < nblk; b += 8) s0 += part[(long)b * count + x];
+    }
+    acc[g][tx] = (s0 + s1) + (s2 + s3);
     __syncthreads();
     if (g == 0 && x < count) {
         float s = acc[0][tx];
